@@ -1,0 +1,140 @@
+"""Benchmark of the product-convolution apply on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one pc_apply_batch of the whole hot path (gather with weights,
+forward FFT, spectral product, inverse FFT, deterministic scatter-add) on the
+1024^2 spatially varying blur with ~600 adaptive sample points and 64
+right-hand sides in FP32, inputs resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector FLOP/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E B/s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path has no multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1805_06018_amd import _lib
+    from workloads import make_config
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    w = make_config(1)
+    B = w.batch
+    t0 = time.time()
+    op = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F32)
+    t_create = time.time() - t0
+    st = op.stats()
+    U = torch.from_numpy(w.vectors(B, dtype=np.float32)).to(dev)
+    OUT = torch.empty_like(U)
+    print(f"# workload {w.name}: N={w.N} r={w.r} B={B} items={st['n_items']} create={t_create:.2f}s",
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        op.apply_batch(U, OUT)
+    torch.cuda.synchronize()
+
+    # timed region (kernel events recorded on the same stream)
+    op.read_profile()
+    op.set_profiling(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        op.apply_batch(U, OUT)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    op.set_profiling(False)
+    prof = op.read_profile()
+    ms_step = ms_total / args.steps
+    value = w.N * B / (ms_step * 1e-3)
+
+    # dominant kernel: the fused convolution launch
+    conv_avg_s = prof["conv_ms"] / max(prof["conv_launches"], 1) * 1e-3
+    vec_per_launch = prof["conv_vectors"] / max(prof["conv_launches"], 1)
+    flops_launch = st["alg_flops_per_rhs"] * vec_per_launch
+    achieved = flops_launch / conv_avg_s
+    alg_bytes_step = 8.0 * w.N * B + 4.0 * st["kernel_elems"]
+
+    # plain per-patch / per-vector apply (same kernels, one launch each)
+    plain_ms = None
+    if args.plain_steps > 0:
+        OUTp = torch.empty_like(U)
+        op.apply_batch_plain(U, OUTp)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        for _ in range(args.plain_steps):
+            op.apply_batch_plain(U, OUTp)
+        torch.cuda.synchronize()
+        plain_ms = (time.time() - t1) * 1e3 / args.plain_steps
+        same = bool(torch.equal(OUTp, OUT))
+    else:
+        same = None
+
+    rec = {
+        "metric": "PC apply grid-points/s (FP32, 1e-5 rel.L2) vs plain apply",
+        "value": value,
+        "unit": "grid-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "blur2d_1024x1024_quadtree_r579_b64", "grid": list(w.shape), "r": w.r,
+                   "batch": B, "items": st["n_items"]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None},
+        "kernels": {"conv_ms_per_launch": conv_avg_s * 1e3, "conv_launches_per_step": prof["conv_launches"] / args.steps,
+                    "reduce_ms_per_step": prof["reduce_ms"] / args.steps,
+                    "alg_flops_per_vector": st["alg_flops_per_rhs"]},
+        "hbm_alg_frac": alg_bytes_step / (ms_step * 1e-3) / PEAK_HBM,
+        "plain": {"ms_per_step": plain_ms, "value": (w.N * B / (plain_ms * 1e-3)) if plain_ms else None,
+                  "bitwise_equal_to_fused": same},
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import OracleOperator
+        ora = OracleOperator.from_workload(w)
+        u0 = U[0].cpu().numpy().astype(np.float64)
+        t2 = time.time()
+        ref = ora.apply(u0, backend="c")
+        t_cpu = time.time() - t2
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        got = OUT[0].cpu().numpy().astype(np.float64)
+        rec["cpu_baseline"] = {"value": w.N / t_cpu, "unit": "grid-points/s", "cores": cores, "kind": "oracle",
+                               "sample": "1 of 64 vectors, full 1024^2 output, FP64 direct summation (C core)"}
+        rec["rel_l2_vs_oracle_vec0"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/* pc.h -- C ABI of the MI355X product-convolution library.
+ *
+ * The library applies the adaptive product-convolution approximation of
+ * Alger, Rao, Myers, Bui-Thanh and Ghattas (arXiv 1805.06018),
+ *
+ *     A~ u = sum_k phi_k^E * (w_k . u)                    (eq. 2.3)
+ *
+ * and its adjoint (eq. 1.4) to batches of vectors on one AMD Instinct
+ * MI355X (gfx950), and drives the randomized a-posteriori error estimator
+ * (Sec. 2.6) on top of the adjoint.
+ *
+ * Conventions
+ *  - The domain Omega is the box prod_i [0, shape[i]-1] in Z^d, d in {1, 2}
+ *    (d = 3 is rejected with PC_ERR_UNSUPPORTED).  Grid functions are stored
+ *    row-major over Omega (axis 0 slowest), N = prod shape.
+ *  - Boxes are inclusive integer boxes [lo, hi]; arrays of boxes and points
+ *    are row-major [count][d] int64.
+ *  - Batched vectors are contiguous: vector j of a batch starts at
+ *    base + j * ld elements (ld >= N).
+ *  - Every pointer named u/U/V/OUT/Z/Y is DEVICE memory owned by the caller;
+ *    every other pointer is HOST memory owned by the caller and only read
+ *    during the call (pc_create deep-copies what it needs).
+ *  - Calls are asynchronous on the given HIP stream unless stated; nothing
+ *    throws across the ABI; a failing call returns a status and sets a
+ *    thread-local message readable with pc_last_error().
+ *  - An operator is read-only after pc_create.  Calls on one operator must be
+ *    serialised by the caller (they share the operator's work buffers);
+ *    different operators are independent.
+ */
+#ifndef PC_H_
+#define PC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pc_op pc_op;
+
+typedef enum {
+    PC_OK = 0,
+    PC_ERR_ARG = 1,          /* invalid argument (null pointer, bad size, bad radius) */
+    PC_ERR_GRID = 2,         /* leaves do not tile Omega, or points != sorted corners  */
+    PC_ERR_OOM = 3,          /* device or host allocation failed                       */
+    PC_ERR_BUDGET = 4,       /* request exceeds a configured memory budget             */
+    PC_ERR_DEVICE = 5,       /* a HIP call failed; destroy the operator                */
+    PC_ERR_CALLBACK = 6,     /* the user's exact-adjoint callback returned non-zero    */
+    PC_ERR_UNSUPPORTED = 7   /* valid input outside what this build implements         */
+} pc_status;
+
+typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
+
+/* Extend impulse responses by zero instead of by the neighbour average of
+ * Sec. 2.5 (the plain scheme whose boundary artifacts Fig. 2 shows). */
+#define PC_NO_EXTEND (1u << 0)
+
+/* pc_create -- build the operator (Sec. 2.2, 2.4, 2.5) and its device data.
+ *
+ *  d, shape[d]          : Omega.
+ *  n_leaves, leaf_lo/hi : the leaf cells of the adaptive cell tree (Sec. 2.2),
+ *                         [n_leaves][d] inclusive boxes.  They must tile Omega
+ *                         (interiors disjoint, union = Omega), else PC_ERR_GRID.
+ *  r, points[r][d]      : the sample points p_k = sorted (axis 0 most
+ *                         significant) union of all leaf corners, else
+ *                         PC_ERR_GRID.  Index k of a point is its position.
+ *  radius[r][d]         : phi_k is supplied on the box prod_i [-R_ki, R_ki]
+ *                         (R >= 0, else PC_ERR_ARG).
+ *  phi, phi_off[r+1]    : the impulse responses phi_k[z] = (A delta_{p_k})[z+p_k]
+ *                         (eq. 2.4), concatenated: patch k occupies
+ *                         phi[phi_off[k] .. phi_off[k+1]) = prod (2R_ki+1)
+ *                         doubles, row-major with offset z = -R first.
+ *                         Entries with p_k + z outside Omega are ignored;
+ *                         phi_k is taken as 0 outside the supplied box.
+ *  dtype                : arithmetic of the apply (FP32 or FP64).  Setup is
+ *                         FP64; the spectra are rounded once to dtype.
+ *  flags                : PC_NO_EXTEND or 0.
+ *  s                    : stream used for the uploads (synchronised before
+ *                         return).
+ *  out                  : receives the operator.
+ * Weights w_k are the harmonic partition of unity of Sec. 2.4 (multilinear
+ * hats on cells without hanging nodes); 2-D hanging nodes are supported.
+ */
+pc_status pc_create(int d, const int64_t* shape,
+                    int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                    int64_t r, const int64_t* points, const int64_t* radius,
+                    const double* phi, const int64_t* phi_off,
+                    pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out);
+
+/* pc_apply -- out = A~ u for one vector (eq. 2.3).  u, out: device, N
+ * elements of the operator's dtype; out must not alias u. */
+pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s);
+
+/* pc_apply_batch -- OUT[:, j] = A~ U[:, j] for j < B (eq. 2.3), all vectors
+ * in one fused launch sequence.  U and OUT are device arrays with leading
+ * dimensions ldu, ldo >= N; B >= 0 (B = 0 is a no-op). */
+pc_status pc_apply_batch(pc_op* op, int64_t B, const void* U, int64_t ldu,
+                         void* OUT, int64_t ldo, hipStream_t s);
+
+/* pc_apply_adjoint_batch -- OUT[:, j] = A~* V[:, j] (eq. 1.4: the same
+ * patches in reverse order, convolution with the flipped kernel first, then
+ * the weight). */
+pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ldv,
+                                 void* OUT, int64_t ldo, hipStream_t s);
+
+/* pc_apply_batch_plain -- same result as pc_apply_batch, computed the plain
+ * way: one launch per patch and per vector, outputs summed in the same
+ * order.  Kept as the baseline the fused path is measured against. */
+pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu,
+                               void* OUT, int64_t ldo, hipStream_t s);
+
+/* Exact adjoint matvec supplied by the caller: out[:, j] = A* in[:, j] for
+ * j < B on stream s (device arrays of the operator's dtype).  Return 0 on
+ * success; any other value aborts the estimate with PC_ERR_CALLBACK. */
+typedef int (*pc_matvec_fn)(void* user, int64_t B, const void* in, int64_t ldin,
+                            void* out, int64_t ldout, hipStream_t s);
+
+/* pc_error_estimate -- randomized estimator of Sec. 2.6 (eq. 2.10).
+ *  Z [q][ldz]         : probe vectors (device).
+ *  Y_or_null [q][ldy] : Y = A* Z if the caller has it (computed once and
+ *                       reused, Sec. 2.8); if NULL the library calls
+ *                       exact_adjoint to fill a work buffer.
+ *  eta_leaf[n_leaves] : host output or NULL; eta_C = q^{-1/2} ||(Y~ - Y)[C, :]||_F
+ *                       with C's own points (shared facets count in each cell).
+ *  eta_abs            : host output, q^{-1/2} ||Y~ - Y||_F.
+ *  eta_rel            : host output, ||Y~ - Y||_F / ||Y||_F.
+ * Y~ and Y are promoted to FP64 before they are subtracted, and all sums of
+ * squares are accumulated in FP64 in a fixed order.  Synchronises s before
+ * returning.  The operator stays valid after PC_ERR_CALLBACK. */
+pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
+                            const void* Y_or_null, int64_t ldy,
+                            pc_matvec_fn exact_adjoint, void* user,
+                            double* eta_leaf, double* eta_abs, double* eta_rel,
+                            hipStream_t s);
+
+/* Plan statistics (for measurement and admission). */
+typedef struct {
+    int64_t n;              /* N = |Omega|                                          */
+    int64_t r;              /* number of sample points                              */
+    int64_t n_leaves;
+    int64_t n_items;        /* convolution work items (patches, or patch pieces)    */
+    int64_t sum_fft_points; /* sum over items of the FFT box size                   */
+    double  alg_flops_per_rhs;  /* 5 n log2 n + 3 n + |I| + |O| summed, n = FFT box */
+    int64_t kernel_elems;   /* sum over patches of the extended kernel box size     */
+    int64_t spectrum_bytes; /* resident spectra                                     */
+    int64_t weight_bytes;   /* resident weight tables                               */
+    int64_t slot_elems_fwd; /* per-vector staging elements of the forward apply     */
+    int64_t slot_elems_adj; /* per-vector staging elements of the adjoint apply     */
+    int64_t device_bytes;   /* everything resident except per-call work buffers     */
+    int32_t dtype;
+    int32_t max_lds_bytes;  /* largest LDS footprint of an item                     */
+} pc_stats;
+
+pc_status   pc_get_stats(const pc_op* op, pc_stats* st);
+
+/* Kernel timing for measurement.  pc_set_profiling(op, 1) makes every later
+ * apply record a HIP event pair on its stream around each convolution and
+ * each reduction launch; pc_read_profile waits for those events, returns the
+ * accumulated device times and launch counts since the last read, and resets
+ * them.  Profiling is off after pc_create. */
+typedef struct {
+    double  conv_ms;          /* summed duration of the convolution launches  */
+    double  reduce_ms;        /* summed duration of the reduction launches    */
+    int64_t conv_launches;
+    int64_t reduce_launches;
+    int64_t conv_vectors;     /* vectors processed by those convolution launches */
+} pc_profile;
+
+pc_status   pc_set_profiling(pc_op* op, int enable);
+pc_status   pc_read_profile(pc_op* op, pc_profile* out);
+size_t      pc_device_bytes(const pc_op* op);
+pc_status   pc_destroy(pc_op* op);
+const char* pc_status_string(pc_status st);
+const char* pc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PC_H_ */

@@ -1,0 +1,107 @@
+// CPU emulation of the convolution and reduction kernels (test tool only).
+//
+// Built host-only into a separate library (libpc_emu.so), never linked into
+// the product library.  It runs the same phase functions as the GPU kernel,
+// one simulated thread after another with the phase boundary standing in for
+// the barrier, on exact-size host buffers so that an address sanitizer build
+// reports any out-of-range index.  It checks the kernels' indexing on the CPU
+// before they run on a GPU.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pc_phases.h"
+#include "pc_plan.h"
+
+namespace {
+thread_local std::string g_emu_err;
+
+template <class T>
+void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
+    using C = pc::cx<T>;
+    const int64_t N = P.N;
+    std::vector<T> spec(P.spec.begin(), P.spec.end());
+    std::vector<T> wts(P.wts.begin(), P.wts.end());
+    std::vector<T> tw(P.tw.begin(), P.tw.end());
+    const int64_t per = adj ? P.slot_adj : P.slot_fwd;
+    for (int64_t b = 0; b < B; ++b) {
+        std::vector<T> in(U + b * ldu, U + b * ldu + N);
+        std::vector<T> slots((size_t)per, T(0));
+        for (const pc::Item& it : P.items) {
+            std::vector<C> buf((size_t)it.n0 * it.ld);
+            for (auto& v : buf) v = C{T(1e30), T(1e30)};   // poison: unwritten reads show up
+            pc::Ctx<T> c = pc::make_ctx<T>(it, adj, in.data(), slots.data(), wts.data(),
+                                           reinterpret_cast<const C*>(spec.data()),
+                                           reinterpret_cast<const C*>(tw.data()), P.cols);
+            const int nth = pc::kThreads;
+            for (int t = 0; t < nth; ++t) pc::ph1(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph_rows2<-1>(c, buf.data(), t, nth, c.s_off0, c.s_n0);
+            for (int t = 0; t < nth; ++t) pc::ph3(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph4(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph5(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph6(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph7(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::ph_rows2<1>(c, buf.data(), t, nth, c.d_off0, c.d_n0);
+            for (int t = 0; t < nth; ++t) pc::ph9(c, buf.data(), t, nth);
+        }
+        std::vector<T> out((size_t)N, T(0));
+        const auto& tiles = adj ? P.tiles_adj : P.tiles_fwd;
+        const auto& contrib = adj ? P.contrib_adj : P.contrib_fwd;
+        const auto& boxes = adj ? P.boxes_adj : P.boxes_fwd;
+        for (const pc::Tile& t : tiles)
+            for (int col = 0; col < pc::kReduceCols; ++col)
+                pc::reduce_tile<T>(t, col, contrib.data(), boxes.data(), slots.data(), out.data(), P.cols);
+        std::memcpy(OUT + b * ldo, out.data(), sizeof(T) * (size_t)N);
+    }
+}
+}  // namespace
+
+struct pc_emu {
+    pc::Plan plan;
+};
+
+extern "C" {
+
+int pc_emu_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                  int64_t r, const int64_t* points, const int64_t* radius, const double* phi, const int64_t* phi_off,
+                  int dtype, uint32_t flags, pc_emu** out) {
+    *out = nullptr;
+    pc_emu* e = new pc_emu();
+    pc::CreateArgs a{d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags};
+    std::string err;
+    pc_status st = pc::build_plan(a, e->plan, err);
+    if (st != PC_OK) {
+        g_emu_err = err;
+        delete e;
+        return (int)st;
+    }
+    *out = e;
+    return 0;
+}
+
+int pc_emu_apply(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo) {
+    if (e->plan.dtype == PC_F64)
+        emu_apply<double>(e->plan, adj != 0, B, static_cast<const double*>(U), ldu, static_cast<double*>(OUT), ldo);
+    else
+        emu_apply<float>(e->plan, adj != 0, B, static_cast<const float*>(U), ldu, static_cast<float*>(OUT), ldo);
+    return 0;
+}
+
+int pc_emu_stats(pc_emu* e, int64_t* out8) {
+    const pc::Plan& P = e->plan;
+    out8[0] = (int64_t)P.items.size();
+    out8[1] = P.sum_fft_points;
+    out8[2] = P.slot_fwd;
+    out8[3] = P.slot_adj;
+    out8[4] = P.max_lds;
+    out8[5] = (int64_t)P.tiles_fwd.size();
+    out8[6] = (int64_t)P.contrib_fwd.size();
+    out8[7] = P.kernel_elems;
+    return 0;
+}
+
+void pc_emu_destroy(pc_emu* e) { delete e; }
+
+const char* pc_emu_last_error(void) { return g_emu_err.c_str(); }
+
+}  // extern "C"

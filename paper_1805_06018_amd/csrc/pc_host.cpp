@@ -1,0 +1,442 @@
+// C ABI of the product-convolution library (declared in include/pc.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pc.h"
+#include "pc_kernels.h"
+#include "pc_plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pc_status fail(pc_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+pc_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PC_ERR_OOM : PC_ERR_DEVICE;
+}
+
+// Staging buffers larger than this are split into vector chunks.
+constexpr size_t kSlotCapBytes = size_t(2) << 30;
+
+}  // namespace
+
+struct pc_op {
+    pc::Plan plan;
+    pc::DevPlan dev{};
+    int device = 0;
+    size_t esz = 4;
+    std::vector<void*> allocs;
+    size_t resident = 0;
+    void* slots = nullptr;
+    size_t slots_bytes = 0;
+    void* work = nullptr;     // estimator: Y~ and (if needed) Y
+    size_t work_bytes = 0;
+    double* est = nullptr;    // estimator sums
+    size_t est_bytes = 0;
+    int32_t* leaf_box = nullptr;   // [L][4] leaf boxes (2-D view), device
+    // profiling: event pairs of launches not yet read
+    bool profiling = false;
+    struct Timed {
+        hipEvent_t a, b;
+        int kind;        // 0 conv, 1 reduce
+        int vectors;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+
+    ~pc_op() {
+        for (auto& t : timed) {
+            hipEventDestroy(t.a);
+            hipEventDestroy(t.b);
+        }
+        for (hipEvent_t e : event_pool) hipEventDestroy(e);
+        for (void* p : allocs) hipFree(p);
+        if (slots) hipFree(slots);
+        if (work) hipFree(work);
+        if (est) hipFree(est);
+    }
+};
+
+namespace {
+
+template <class V>
+pc_status upload(pc_op* op, const V& host, void** dptr) {
+    size_t bytes = host.size() * sizeof(host[0]);
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(dptr, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (operator data)");
+    op->allocs.push_back(*dptr);
+    op->resident += bytes;
+    if (!host.empty()) {
+        e = hipMemcpy(*dptr, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (operator data)");
+    }
+    return PC_OK;
+}
+
+pc_status upload_real(pc_op* op, const std::vector<double>& v, void** dptr) {
+    if (op->plan.dtype == PC_F64) return upload(op, v, dptr);
+    std::vector<float> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+    return upload(op, f, dptr);
+}
+
+pc_status ensure(void** buf, size_t* have, size_t need, const char* what) {
+    if (*have >= need) return PC_OK;
+    if (*buf) {
+        hipError_t e = hipDeviceSynchronize();   // a previous call may still use it
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+    }
+    hipError_t e = hipMalloc(buf, need);
+    if (e != hipSuccess) return hip_fail(e, what);
+    *have = need;
+    return PC_OK;
+}
+
+hipEvent_t get_event(pc_op* op) {
+    if (!op->event_pool.empty()) {
+        hipEvent_t e = op->event_pool.back();
+        op->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start event of a timed launch (no-op when not profiling).
+void prof_begin(pc_op* op, hipStream_t s, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!op->profiling) return;
+    *ev = get_event(op);
+    if (*ev) hipEventRecord(*ev, s);
+}
+
+void prof_end(pc_op* op, hipStream_t s, hipEvent_t start, int kind, int vectors) {
+    if (!op->profiling || !start) return;
+    hipEvent_t e = get_event(op);
+    if (!e) return;
+    hipEventRecord(e, s);
+    op->timed.push_back({start, e, kind, vectors});
+}
+
+pc_status check_op(const pc_op* op) {
+    if (!op) return fail(PC_ERR_ARG, "null operator");
+    return PC_OK;
+}
+
+pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                    hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    const int64_t N = op->plan.N;
+    if (B < 0) return fail(PC_ERR_ARG, "negative batch size");
+    if (B == 0) return PC_OK;
+    if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
+    if (ldu < N || ldo < N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
+    if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
+    const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
+    const size_t per_bytes = (size_t)per * op->esz;
+    int64_t chunk = plain ? 1 : (int64_t)std::max<size_t>(1, kSlotCapBytes / std::max<size_t>(per_bytes, 1));
+    if (chunk > B) chunk = B;
+    st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    if (st != PC_OK) return st;
+    const char* u = static_cast<const char*>(U);
+    char* o = static_cast<char*>(OUT);
+    const int n_items = (int)op->plan.items.size();
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        const void* in = u + (size_t)b0 * ldu * op->esz;
+        void* out = o + (size_t)b0 * ldo * op->esz;
+        hipError_t e;
+        hipEvent_t ev;
+        if (plain) {
+            for (int it = 0; it < n_items; ++it) {
+                prof_begin(op, s, &ev);
+                e = pc::launch_conv(op->dev, adj, it, it + 1, 1, in, ldu, op->slots, per, s);
+                if (e != hipSuccess) return hip_fail(e, "conv launch");
+                prof_end(op, s, ev, 0, 1);
+            }
+        } else {
+            prof_begin(op, s, &ev);
+            e = pc::launch_conv(op->dev, adj, 0, n_items, nb, in, ldu, op->slots, per, s);
+            if (e != hipSuccess) return hip_fail(e, "conv launch");
+            prof_end(op, s, ev, 0, nb);
+        }
+        prof_begin(op, s, &ev);
+        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s);
+        if (e != hipSuccess) return hip_fail(e, "reduce launch");
+        prof_end(op, s, ev, 1, nb);
+    }
+    return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                    int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
+                    const int64_t* phi_off, pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out) {
+    (void)s;
+    if (!out) return fail(PC_ERR_ARG, "null output handle");
+    *out = nullptr;
+    pc_op* op = new (std::nothrow) pc_op();
+    if (!op) return fail(PC_ERR_OOM, "host allocation failed");
+    pc::CreateArgs a{d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, (int)dtype, flags};
+    std::string err;
+    pc_status st;
+    try {
+        st = pc::build_plan(a, op->plan, err);
+    } catch (const std::bad_alloc&) {
+        st = PC_ERR_OOM;
+        err = "host allocation failed while planning";
+    } catch (...) {
+        st = PC_ERR_ARG;
+        err = "unexpected error while planning";
+    }
+    if (st != PC_OK) {
+        delete op;
+        return fail(st, err);
+    }
+    hipError_t e = hipGetDevice(&op->device);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipGetDevice");
+    }
+    int lds_max = 0;
+    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
+    if (op->plan.max_lds > lds_max) {
+        delete op;
+        return fail(PC_ERR_UNSUPPORTED, "device LDS per workgroup (" + std::to_string(lds_max) +
+                                            " B) is below the plan's need (" + std::to_string(op->plan.max_lds) + " B)");
+    }
+    e = pc::set_kernel_attributes();
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipFuncSetAttribute");
+    }
+    op->esz = (dtype == PC_F64) ? 8 : 4;
+    pc::Plan& P = op->plan;
+    void *d_items, *d_spec, *d_wts, *d_tw, *d_tf, *d_ta, *d_cf, *d_ca, *d_bf, *d_ba;
+    if ((st = upload(op, P.items, &d_items)) != PC_OK || (st = upload_real(op, P.spec, &d_spec)) != PC_OK ||
+        (st = upload_real(op, P.wts, &d_wts)) != PC_OK || (st = upload_real(op, P.tw, &d_tw)) != PC_OK ||
+        (st = upload(op, P.tiles_fwd, &d_tf)) != PC_OK || (st = upload(op, P.tiles_adj, &d_ta)) != PC_OK ||
+        (st = upload(op, P.contrib_fwd, &d_cf)) != PC_OK || (st = upload(op, P.contrib_adj, &d_ca)) != PC_OK ||
+        (st = upload(op, P.boxes_fwd, &d_bf)) != PC_OK || (st = upload(op, P.boxes_adj, &d_ba)) != PC_OK) {
+        delete op;
+        return st;
+    }
+    void* d_leaf;
+    if ((st = upload(op, P.leaf_box, &d_leaf)) != PC_OK) {
+        delete op;
+        return st;
+    }
+    pc::DevPlan& D = op->dev;
+    D.items = static_cast<const pc::Item*>(d_items);
+    D.n_items = (int)P.items.size();
+    D.rows = P.rows;
+    D.cols = P.cols;
+    D.spec = d_spec;
+    D.wts = d_wts;
+    D.tw = d_tw;
+    D.tiles_fwd = static_cast<const pc::Tile*>(d_tf);
+    D.tiles_adj = static_cast<const pc::Tile*>(d_ta);
+    D.n_tiles_fwd = (int)P.tiles_fwd.size();
+    D.n_tiles_adj = (int)P.tiles_adj.size();
+    D.contrib_fwd = static_cast<const int32_t*>(d_cf);
+    D.contrib_adj = static_cast<const int32_t*>(d_ca);
+    D.boxes_fwd = static_cast<const pc::Box*>(d_bf);
+    D.boxes_adj = static_cast<const pc::Box*>(d_ba);
+    D.slot_fwd = P.slot_fwd;
+    D.slot_adj = P.slot_adj;
+    D.max_lds = P.max_lds;
+    D.dtype = (int)dtype;
+    op->leaf_box = static_cast<int32_t*>(d_leaf);
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipDeviceSynchronize after upload");
+    }
+    // spectra are only needed on the device from now on
+    std::vector<double>().swap(P.spec);
+    *out = op;
+    return PC_OK;
+}
+
+pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s) {
+    if (!op) return fail(PC_ERR_ARG, "null operator");
+    return run_batch(op, false, false, 1, u, op->plan.N, out, op->plan.N, s);
+}
+
+pc_status pc_apply_batch(pc_op* op, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo, hipStream_t s) {
+    return run_batch(op, false, false, B, U, ldu, OUT, ldo, s);
+}
+
+pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ldv, void* OUT, int64_t ldo,
+                                 hipStream_t s) {
+    return run_batch(op, true, false, B, V, ldv, OUT, ldo, s);
+}
+
+pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                               hipStream_t s) {
+    return run_batch(op, false, true, B, U, ldu, OUT, ldo, s);
+}
+
+pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, const void* Y_or_null, int64_t ldy,
+                            pc_matvec_fn exact_adjoint, void* user, double* eta_leaf, double* eta_abs,
+                            double* eta_rel, hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    const int64_t N = op->plan.N;
+    if (q < 1 || !Z || ldz < N) return fail(PC_ERR_ARG, "invalid probe block");
+    if (!eta_abs || !eta_rel) return fail(PC_ERR_ARG, "null output scalar");
+    if (!Y_or_null && !exact_adjoint) return fail(PC_ERR_ARG, "need Y or an exact-adjoint callback");
+    if (Y_or_null && ldy < N) return fail(PC_ERR_ARG, "ldy smaller than N");
+    const size_t vec = (size_t)N * op->esz;
+    const size_t need = (size_t)q * vec * (Y_or_null ? 1 : 2);
+    st = ensure(&op->work, &op->work_bytes, need, "hipMalloc (estimator work)");
+    if (st != PC_OK) return st;
+    char* Yt = static_cast<char*>(op->work);
+    const void* Y = Y_or_null;
+    int64_t ldY = ldy;
+    if (!Y_or_null) {
+        void* Ybuf = Yt + (size_t)q * vec;
+        int rc = exact_adjoint(user, q, Z, ldz, Ybuf, N, s);
+        if (rc != 0) return fail(PC_ERR_CALLBACK, "exact-adjoint callback returned " + std::to_string(rc));
+        Y = Ybuf;
+        ldY = N;
+    }
+    st = run_batch(op, true, false, q, Z, ldz, Yt, N, s);
+    if (st != PC_OK) return st;
+    const int L = (int)op->plan.L;
+    const int n_part = 512;
+    void* est = op->est;
+    st = ensure(&est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 * n_part), "hipMalloc (estimator sums)");
+    op->est = static_cast<double*>(est);
+    if (st != PC_OK) return st;
+    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, N, Y, ldY, op->plan.rows, op->plan.cols, op->est,
+                       op->est + L, n_part, s);
+    if (e != hipSuccess) return hip_fail(e, "estimator launch");
+    std::vector<double> h((size_t)L + 2 * n_part);
+    e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (estimator sums)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (estimator)");
+    double dd = 0.0, yy = 0.0;
+    for (int i = 0; i < n_part; ++i) {
+        dd += h[(size_t)L + 2 * i];
+        yy += h[(size_t)L + 2 * i + 1];
+    }
+    if (eta_leaf)
+        for (int c = 0; c < L; ++c) eta_leaf[c] = std::sqrt(h[(size_t)c] / (double)q);
+    *eta_abs = std::sqrt(dd / (double)q);
+    *eta_rel = yy > 0.0 ? std::sqrt(dd) / std::sqrt(yy) : INFINITY;
+    return PC_OK;
+}
+
+pc_status pc_get_stats(const pc_op* op, pc_stats* st) {
+    if (!op || !st) return fail(PC_ERR_ARG, "null argument");
+    const pc::Plan& P = op->plan;
+    std::memset(st, 0, sizeof(*st));
+    st->n = P.N;
+    st->r = P.r;
+    st->n_leaves = P.L;
+    st->n_items = (int64_t)P.items.size();
+    st->sum_fft_points = P.sum_fft_points;
+    st->alg_flops_per_rhs = P.alg_flops;
+    st->kernel_elems = P.kernel_elems;
+    int64_t spec_elems = 0;
+    {
+        // one spectrum per patch: n0 x (m + 1) complex
+        int last = -1;
+        for (const auto& it : P.items)
+            if (it.patch != last) {
+                spec_elems += (int64_t)it.n0 * (it.m + 1);
+                last = it.patch;
+            }
+    }
+    st->spectrum_bytes = spec_elems * 2 * (int64_t)op->esz;
+    st->weight_bytes = (int64_t)P.wts.size() * (int64_t)op->esz;
+    st->slot_elems_fwd = P.slot_fwd;
+    st->slot_elems_adj = P.slot_adj;
+    st->device_bytes = (int64_t)op->resident;
+    st->dtype = P.dtype;
+    st->max_lds_bytes = P.max_lds;
+    return PC_OK;
+}
+
+pc_status pc_set_profiling(pc_op* op, int enable) {
+    if (!op) return fail(PC_ERR_ARG, "null operator");
+    op->profiling = enable != 0;
+    return PC_OK;
+}
+
+pc_status pc_read_profile(pc_op* op, pc_profile* out) {
+    if (!op || !out) return fail(PC_ERR_ARG, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    pc_status st = PC_OK;
+    for (auto& t : op->timed) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && st == PC_OK) st = hip_fail(e, "hipEventElapsedTime");
+        if (t.kind == 0) {
+            out->conv_ms += ms;
+            out->conv_launches += 1;
+            out->conv_vectors += t.vectors;
+        } else {
+            out->reduce_ms += ms;
+            out->reduce_launches += 1;
+        }
+        op->event_pool.push_back(t.a);
+        op->event_pool.push_back(t.b);
+    }
+    op->timed.clear();
+    return st;
+}
+
+size_t pc_device_bytes(const pc_op* op) { return op ? op->resident : 0; }
+
+pc_status pc_destroy(pc_op* op) {
+    if (!op) return PC_OK;
+    hipDeviceSynchronize();
+    delete op;
+    return PC_OK;
+}
+
+const char* pc_status_string(pc_status st) {
+    switch (st) {
+        case PC_OK: return "PC_OK";
+        case PC_ERR_ARG: return "PC_ERR_ARG";
+        case PC_ERR_GRID: return "PC_ERR_GRID";
+        case PC_ERR_OOM: return "PC_ERR_OOM";
+        case PC_ERR_BUDGET: return "PC_ERR_BUDGET";
+        case PC_ERR_DEVICE: return "PC_ERR_DEVICE";
+        case PC_ERR_CALLBACK: return "PC_ERR_CALLBACK";
+        case PC_ERR_UNSUPPORTED: return "PC_ERR_UNSUPPORTED";
+    }
+    return "PC_ERR_UNKNOWN";
+}
+
+const char* pc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

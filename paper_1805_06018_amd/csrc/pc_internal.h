@@ -1,0 +1,54 @@
+// Internal definitions shared by the host planner (pc_host.cpp) and the HIP
+// kernels (pc_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace pc {
+
+// Largest radix handled by the register codelets; every FFT length used by
+// the library is a * b with a, b in {1,2,3,4,5,6,7,8,9,10,12,14,15,16}.
+constexpr int kMaxRadix = 16;
+constexpr int kThreads = 512;          // threads per convolution workgroup
+constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+constexpr int kReduceCols = 256;       // reduce tile width (threads)
+constexpr int kReduceRows = 8;         // reduce tile height (accumulators per thread)
+
+// One convolution work item: a patch (or a row piece of a patch) of the
+// 2-D product-convolution sum.  FFT index (i0, i1) <-> Omega point
+// (g0 + i0, g1 + i1).  The input box of the forward sum (the patch's
+// weighted gather box I) sits at FFT offset (in_off0, in_off1) with extent
+// (in_n0, in_n1); the output box O = (I + kernel box) n Omega sits at FFT
+// offset (0, 0) with extent (out_n0, out_n1).  The adjoint swaps the roles.
+struct Item {
+    int32_t n0;          // column FFT length (axis 0); 1 for 1-D problems
+    int32_t a0, b0;      // n0 = a0 * b0
+    int32_t m;           // row complex FFT length; the real row length is 2m
+    int32_t am, bm;      // m = am * bm
+    int32_t ld;          // LDS row stride (complex elements), >= m + 1, odd
+    int32_t tw0, twm, tw2m;  // offsets of the twiddle tables for n0, m, 2m
+    int32_t g0, g1;      // Omega coordinates of FFT index (0, 0)
+    int32_t in_off0, in_off1, in_n0, in_n1;
+    int32_t out_n0, out_n1;
+    int32_t patch;       // k
+    int32_t pad_;
+    int64_t w_off;       // weight table (in_n0 x in_n1, row-major)
+    int64_t spec_off;    // spectrum (n0 x (m+1), slot-permuted)
+    int64_t slot_fwd;    // forward staging offset (out_n0 x out_n1)
+    int64_t slot_adj;    // adjoint staging offset (in_n0 x in_n1)
+};
+
+// Output tile of the deterministic reduction and the staging boxes that
+// overlap it (a CSR range into the contributor list, ascending item order).
+struct Tile {
+    int32_t r0, c0, nr, nc;
+    int32_t beg, end;
+};
+
+// Staging box of one contributor: Omega box and staging offset per vector.
+struct Box {
+    int32_t lo0, lo1, n0, n1;
+    int64_t off;
+};
+
+}  // namespace pc

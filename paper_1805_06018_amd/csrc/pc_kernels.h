@@ -1,0 +1,48 @@
+// Launch interface of the HIP kernels (used by the C ABI in pc_host.cpp).
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+#include "pc_internal.h"
+
+namespace pc {
+
+struct DevPlan {
+    const Item* items;
+    int n_items;
+    int rows, cols;                 // 2-D view of Omega
+    const void* spec;               // complex dtype
+    const void* wts;                // dtype
+    const void* tw;                 // complex dtype
+    const Tile* tiles_fwd;
+    const Tile* tiles_adj;
+    int n_tiles_fwd, n_tiles_adj;
+    const int32_t* contrib_fwd;
+    const int32_t* contrib_adj;
+    const Box* boxes_fwd;
+    const Box* boxes_adj;
+    int64_t slot_fwd, slot_adj;     // staging elements per vector
+    int max_lds;
+    int dtype;                      // 0 = f32, 1 = f64
+};
+
+// Convolution items -> staging (one workgroup per item and vector).
+// item_lo/item_hi restrict the launch to a range of items (the plain mode
+// launches one item at a time); B vectors starting at 'in'.
+hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi, int B,
+                       const void* in, int64_t ld_in, void* slots, int64_t slot_stride,
+                       hipStream_t s);
+
+// Deterministic reduction of the staging boxes into the outputs.
+hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride,
+                         void* out, int64_t ldo, hipStream_t s);
+
+// Estimator: per-leaf FP64 sums of squares of (Yt - Y) over q vectors and
+// the totals sum (Yt - Y)^2 and sum Y^2 (per row-block partials).
+hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q,
+                      const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
+                      int rows, int cols, double* leaf_sq, double* partials, int n_part,
+                      hipStream_t s);
+
+hipError_t set_kernel_attributes();
+
+}  // namespace pc

@@ -1,0 +1,682 @@
+// Host planner of the product-convolution operator (see pc_plan.h).
+#include "pc_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <set>
+#include <tuple>
+
+namespace pc {
+
+namespace {
+
+using cd = std::complex<double>;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ------------------------------------------------------------------ FFT sizes
+const int kRadices[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16};
+
+}  // namespace
+
+bool fft_factor(int n, int* a, int* b) {
+    int best_a = 0, best_b = 0;
+    for (int x : kRadices)
+        for (int y : kRadices)
+            if (x * y == n) {
+                bool better = best_a == 0 || std::max(x, y) < std::max(best_a, best_b) ||
+                              (std::max(x, y) == std::max(best_a, best_b) && x > best_a);
+                if (better) {
+                    best_a = x;
+                    best_b = y;
+                }
+            }
+    if (!best_a) return false;
+    *a = best_a;
+    *b = best_b;
+    return true;
+}
+
+int next_fft_size(int need) {
+    if (need < 1) need = 1;
+    for (int n = need; n <= 256; ++n) {
+        int a, b;
+        if (fft_factor(n, &a, &b)) return n;
+    }
+    return -1;
+}
+
+namespace {
+
+int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
+
+int smallest_7smooth(int64_t need) {
+    for (int64_t n = std::max<int64_t>(need, 1);; ++n) {
+        int64_t m = n;
+        for (int p : {2, 3, 5, 7})
+            while (m % p == 0) m /= p;
+        if (m == 1) return (int)n;
+    }
+}
+
+// --------------------------------------------------------- FP64 host FFT
+// y[k] = sum_j x[j * stride] w_n^(j k), w_n = exp(-2 pi i / n); recursive
+// mixed radix over the smallest prime factor, twiddles from a table of the
+// top-level length Wn (n divides Wn).
+void fft_rec(const cd* x, int64_t stride, int n, cd* y, const std::vector<cd>& W, int Wn,
+             std::vector<cd>& scratch) {
+    if (n == 1) {
+        y[0] = x[0];
+        return;
+    }
+    int p = n;
+    for (int f = 2; f * f <= n; ++f)
+        if (n % f == 0) {
+            p = f;
+            break;
+        }
+    int m = n / p;
+    for (int q = 0; q < p; ++q) fft_rec(x + q * stride, stride * p, m, y + q * m, W, Wn, scratch);
+    std::vector<cd> t(n);
+    const int step = Wn / n;
+    for (int k = 0; k < m; ++k)
+        for (int q = 0; q < p; ++q) {
+            int K = k + q * m;
+            cd s = 0.0;
+            for (int rr = 0; rr < p; ++rr) s += y[rr * m + k] * W[(int64_t)((rr * (int64_t)K) % n) * step];
+            t[K] = s;
+        }
+    std::copy(t.begin(), t.end(), y);
+}
+
+std::vector<cd> twiddles(int n) {
+    std::vector<cd> W(n);
+    for (int e = 0; e < n; ++e) {
+        double ang = 2.0 * kPi * (double)e / (double)n;
+        W[e] = cd(std::cos(ang), -std::sin(ang));
+    }
+    return W;
+}
+
+// -------------------------------------------------------- harmonic weights
+// Hat of point 'pos' among sorted cut positions, evaluated on [c0, c1].
+void edge_hat(const std::vector<int64_t>& cuts, int64_t pos, int64_t c0, int64_t c1, double* out) {
+    // cuts sorted, contain c0 and c1
+    for (int64_t x = c0; x <= c1; ++x) {
+        auto it = std::upper_bound(cuts.begin(), cuts.end(), x);
+        double v;
+        if (it == cuts.end()) {
+            v = (x == pos) ? 1.0 : 0.0;
+        } else {
+            int64_t right = *it, left = *(it - 1);
+            double fl = (left == pos) ? 1.0 : 0.0, fr = (right == pos) ? 1.0 : 0.0;
+            double t = (double)(x - left) / (double)(right - left);
+            v = fl * (1.0 - t) + fr * t;
+        }
+        out[x - c0] = v;
+    }
+}
+
+// Dirichlet problem for the 5-point graph Laplacian on the interior
+// (p x q) of a box: L U = R with L = T_p (x) I + I (x) T_q, solved exactly in
+// the sine eigenbasis of the tridiagonal T_n (T_n = S diag(lambda) S, S
+// symmetric orthogonal).
+void dst_solve(int p, int q, std::vector<double>& R) {
+    auto basis = [](int n, std::vector<double>& S, std::vector<double>& lam) {
+        S.assign((size_t)n * n, 0.0);
+        lam.assign(n, 0.0);
+        double sc = std::sqrt(2.0 / (n + 1));
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < n; ++a) S[(size_t)i * n + a] = sc * std::sin(kPi * (i + 1) * (a + 1) / (n + 1));
+        for (int a = 0; a < n; ++a) lam[a] = 2.0 - 2.0 * std::cos(kPi * (a + 1) / (n + 1));
+    };
+    std::vector<double> Sp, lp, Sq, lq;
+    basis(p, Sp, lp);
+    basis(q, Sq, lq);
+    std::vector<double> T((size_t)p * q), U((size_t)p * q);
+    auto left = [&](const std::vector<double>& A, std::vector<double>& B) {   // B = Sp A
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < q; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < p; ++k) s += Sp[(size_t)i * p + k] * A[(size_t)k * q + j];
+                B[(size_t)i * q + j] = s;
+            }
+    };
+    auto right = [&](const std::vector<double>& A, std::vector<double>& B) {  // B = A Sq
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < q; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < q; ++k) s += A[(size_t)i * q + k] * Sq[(size_t)k * q + j];
+                B[(size_t)i * q + j] = s;
+            }
+    };
+    left(R, T);
+    right(T, U);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < q; ++b) U[(size_t)a * q + b] /= (lp[a] + lq[b]);
+    left(U, T);
+    right(T, R);
+}
+
+// Weights of every sample point lying on a 2-D leaf over the leaf box.
+// pts: indices into the point list; returns vals[j][(y0-lo0)*(w1) + (y1-lo1)].
+void leaf_weights_2d(const int64_t* lo, const int64_t* hi, const std::vector<int64_t>& pts,
+                     const int64_t* P, std::vector<std::vector<double>>& vals) {
+    const int64_t H0 = hi[0] - lo[0], H1 = hi[1] - lo[1];
+    const int64_t w0 = H0 + 1, w1 = H1 + 1;
+    vals.assign(pts.size(), std::vector<double>((size_t)(w0 * w1), 0.0));
+    if (pts.size() == 4) {   // conforming leaf: bilinear hats
+        for (size_t j = 0; j < pts.size(); ++j) {
+            const int64_t* p = P + 2 * pts[j];
+            for (int64_t y0 = 0; y0 < w0; ++y0) {
+                double f0 = 1.0 - std::fabs((double)(lo[0] + y0 - p[0])) / (double)H0;
+                for (int64_t y1 = 0; y1 < w1; ++y1) {
+                    double f1 = 1.0 - std::fabs((double)(lo[1] + y1 - p[1])) / (double)H1;
+                    vals[j][(size_t)(y0 * w1 + y1)] = f0 * f1;
+                }
+            }
+        }
+        return;
+    }
+    // cut positions on each edge
+    std::vector<int64_t> top, bot, lef, rig;   // rows lo0 / hi0 (by col), cols lo1 / hi1 (by row)
+    for (int64_t k : pts) {
+        const int64_t* p = P + 2 * k;
+        if (p[0] == lo[0]) top.push_back(p[1]);
+        if (p[0] == hi[0]) bot.push_back(p[1]);
+        if (p[1] == lo[1]) lef.push_back(p[0]);
+        if (p[1] == hi[1]) rig.push_back(p[0]);
+    }
+    for (auto* v : {&top, &bot, &lef, &rig}) std::sort(v->begin(), v->end());
+    const int p_in = (int)H0 - 1, q_in = (int)H1 - 1;
+    std::vector<double> e(std::max(w0, w1));
+    for (size_t j = 0; j < pts.size(); ++j) {
+        const int64_t* p = P + 2 * pts[j];
+        std::vector<double>& V = vals[j];
+        // edges (a point not on an edge contributes a zero hat there)
+        edge_hat(top, p[0] == lo[0] ? p[1] : INT64_MIN, lo[1], hi[1], e.data());
+        for (int64_t y1 = 0; y1 < w1; ++y1) V[(size_t)y1] = e[y1];
+        edge_hat(bot, p[0] == hi[0] ? p[1] : INT64_MIN, lo[1], hi[1], e.data());
+        for (int64_t y1 = 0; y1 < w1; ++y1) V[(size_t)(H0 * w1 + y1)] = e[y1];
+        edge_hat(lef, p[1] == lo[1] ? p[0] : INT64_MIN, lo[0], hi[0], e.data());
+        for (int64_t y0 = 0; y0 < w0; ++y0) V[(size_t)(y0 * w1)] = e[y0];
+        edge_hat(rig, p[1] == hi[1] ? p[0] : INT64_MIN, lo[0], hi[0], e.data());
+        for (int64_t y0 = 0; y0 < w0; ++y0) V[(size_t)(y0 * w1 + H1)] = e[y0];
+        if (p_in <= 0 || q_in <= 0) continue;
+        std::vector<double> R((size_t)p_in * q_in, 0.0);
+        for (int i = 0; i < p_in; ++i)
+            for (int jj = 0; jj < q_in; ++jj) {
+                double s = 0.0;
+                if (i == 0) s += V[(size_t)(0 * w1 + jj + 1)];
+                if (i == p_in - 1) s += V[(size_t)(H0 * w1 + jj + 1)];
+                if (jj == 0) s += V[(size_t)((i + 1) * w1)];
+                if (jj == q_in - 1) s += V[(size_t)((i + 1) * w1 + H1)];
+                R[(size_t)i * q_in + jj] = s;
+            }
+        dst_solve(p_in, q_in, R);
+        for (int i = 0; i < p_in; ++i)
+            for (int jj = 0; jj < q_in; ++jj) V[(size_t)((i + 1) * w1 + jj + 1)] = R[(size_t)i * q_in + jj];
+    }
+}
+
+}  // namespace
+
+// ======================================================================
+pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
+    // ---------------------------------------------------------- arguments
+    if (a.d < 1 || a.d > 3) {
+        err = "d must be 1, 2 or 3";
+        return PC_ERR_ARG;
+    }
+    if (!a.shape || !a.leaf_lo || !a.leaf_hi || !a.points || !a.radius || !a.phi || !a.phi_off) {
+        err = "null host pointer";
+        return PC_ERR_ARG;
+    }
+    if (a.n_leaves < 1 || a.r < 1) {
+        err = "need at least one leaf and one point";
+        return PC_ERR_ARG;
+    }
+    if (a.dtype != PC_F32 && a.dtype != PC_F64) {
+        err = "dtype must be PC_F32 or PC_F64";
+        return PC_ERR_ARG;
+    }
+    if (a.flags & ~(uint32_t)PC_NO_EXTEND) {
+        err = "unknown flag bits";
+        return PC_ERR_ARG;
+    }
+    const int d = a.d;
+    p.d = d;
+    p.dtype = a.dtype;
+    p.flags = a.flags;
+    int64_t N = 1;
+    for (int i = 0; i < d; ++i) {
+        if (a.shape[i] < 1 || a.shape[i] > (1 << 20)) {
+            err = "shape entries must be in [1, 2^20]";
+            return PC_ERR_ARG;
+        }
+        p.shape[i] = a.shape[i];
+        N *= a.shape[i];
+    }
+    if (N > ((int64_t)1 << 30)) {
+        err = "domain too large (N > 2^30)";
+        return PC_ERR_ARG;
+    }
+    p.N = N;
+    const int64_t L = a.n_leaves, r = a.r;
+    p.L = L;
+    p.r = r;
+    const int64_t* n = a.shape;
+    // ------------------------------------------------------ tiling checks
+    for (int64_t c = 0; c < L; ++c)
+        for (int i = 0; i < d; ++i) {
+            int64_t lo = a.leaf_lo[c * d + i], hi = a.leaf_hi[c * d + i];
+            if (lo < 0 || hi > n[i] - 1 || lo > hi) {
+                err = "leaf " + std::to_string(c) + " outside Omega or inverted";
+                return PC_ERR_GRID;
+            }
+            if (n[i] > 1 && hi == lo) {
+                err = "leaf " + std::to_string(c) + " is degenerate along a live axis";
+                return PC_ERR_GRID;
+            }
+        }
+    {
+        long double vol = 0, tot = 1;
+        for (int i = 0; i < d; ++i)
+            if (n[i] > 1) tot *= (long double)(n[i] - 1);
+        for (int64_t c = 0; c < L; ++c) {
+            long double v = 1;
+            for (int i = 0; i < d; ++i)
+                if (n[i] > 1) v *= (long double)(a.leaf_hi[c * d + i] - a.leaf_lo[c * d + i]);
+            vol += v;
+        }
+        if (std::fabs((double)(vol - tot)) > 0.5) {
+            err = "leaf volumes do not add up to Omega";
+            return PC_ERR_GRID;
+        }
+        // pairwise interiors: sort by lo along axis 0 and sweep
+        std::vector<int64_t> ord(L);
+        for (int64_t c = 0; c < L; ++c) ord[c] = c;
+        std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return a.leaf_lo[x * d] < a.leaf_lo[y * d]; });
+        for (int64_t ii = 0; ii < L; ++ii) {
+            int64_t c = ord[ii];
+            for (int64_t jj = ii + 1; jj < L; ++jj) {
+                int64_t e = ord[jj];
+                if (n[0] > 1 && a.leaf_lo[e * d] >= a.leaf_hi[c * d]) break;
+                bool ov = true;
+                for (int i = 0; i < d && ov; ++i) {
+                    if (n[i] <= 1) continue;
+                    int64_t lo = std::max(a.leaf_lo[c * d + i], a.leaf_lo[e * d + i]);
+                    int64_t hi = std::min(a.leaf_hi[c * d + i], a.leaf_hi[e * d + i]);
+                    ov = hi - lo > 0;
+                }
+                if (ov) {
+                    err = "leaf interiors overlap (" + std::to_string(c) + ", " + std::to_string(e) + ")";
+                    return PC_ERR_GRID;
+                }
+            }
+        }
+    }
+    // ----------------------------------------------- points = leaf corners
+    {
+        std::set<std::vector<int64_t>> cs;
+        std::vector<int64_t> v(d);
+        for (int64_t c = 0; c < L; ++c)
+            for (int bits = 0; bits < (1 << d); ++bits) {
+                for (int i = 0; i < d; ++i)
+                    v[i] = (bits >> (d - 1 - i)) & 1 ? a.leaf_hi[c * d + i] : a.leaf_lo[c * d + i];
+                cs.insert(v);
+            }
+        if ((int64_t)cs.size() != r) {
+            err = "point count " + std::to_string(r) + " != number of distinct leaf corners " +
+                  std::to_string(cs.size());
+            return PC_ERR_GRID;
+        }
+        int64_t k = 0;
+        for (const auto& q : cs) {
+            for (int i = 0; i < d; ++i)
+                if (a.points[k * d + i] != q[i]) {
+                    err = "points are not the sorted union of leaf corners (index " + std::to_string(k) + ")";
+                    return PC_ERR_GRID;
+                }
+            ++k;
+        }
+    }
+    // ------------------------------------------------- impulse responses
+    {
+        if (a.phi_off[0] != 0) {
+            err = "phi_off[0] must be 0";
+            return PC_ERR_ARG;
+        }
+        for (int64_t k = 0; k < r; ++k) {
+            int64_t sz = 1;
+            for (int i = 0; i < d; ++i) {
+                int64_t R = a.radius[k * d + i];
+                if (R < 0 || R > (1 << 16)) {
+                    err = "radius of point " + std::to_string(k) + " out of range";
+                    return PC_ERR_ARG;
+                }
+                sz *= 2 * R + 1;
+            }
+            if (a.phi_off[k + 1] - a.phi_off[k] != sz) {
+                err = "phi_off does not match the radii at point " + std::to_string(k);
+                return PC_ERR_ARG;
+            }
+        }
+    }
+    if (d == 3) {
+        err = "3-D operators are not implemented by this build";
+        return PC_ERR_UNSUPPORTED;
+    }
+
+    // ------------------------------------------------------- 2-D view
+    // d = 1 is handled as a single row: axis 0 of the view has extent 1.
+    auto c0 = [&](const int64_t* v, int64_t k) -> int64_t { return d == 1 ? 0 : v[k * d + 0]; };
+    auto c1 = [&](const int64_t* v, int64_t k) -> int64_t { return d == 1 ? v[k] : v[k * d + 1]; };
+    const int64_t nr = (d == 1) ? 1 : n[0], nc = (d == 1) ? n[0] : n[1];
+    p.rows = (int)nr;
+    p.cols = (int)nc;
+    std::vector<int64_t> P2(2 * r), R2(2 * r), LO(2 * L), HI(2 * L);
+    for (int64_t k = 0; k < r; ++k) {
+        P2[2 * k] = c0(a.points, k);
+        P2[2 * k + 1] = c1(a.points, k);
+        R2[2 * k] = d == 1 ? 0 : a.radius[k * d];
+        R2[2 * k + 1] = c1(a.radius, k);
+    }
+    for (int64_t c = 0; c < L; ++c) {
+        LO[2 * c] = c0(a.leaf_lo, c);
+        LO[2 * c + 1] = c1(a.leaf_lo, c);
+        HI[2 * c] = c0(a.leaf_hi, c);
+        HI[2 * c + 1] = c1(a.leaf_hi, c);
+    }
+    // ------------------------------------------------ cells, nbrs, U_k
+    std::vector<std::vector<int64_t>> leaf_pts(L), cells(r);
+    for (int64_t c = 0; c < L; ++c)
+        for (int64_t k = 0; k < r; ++k)
+            if (P2[2 * k] >= LO[2 * c] && P2[2 * k] <= HI[2 * c] && P2[2 * k + 1] >= LO[2 * c + 1] &&
+                P2[2 * k + 1] <= HI[2 * c + 1]) {
+                leaf_pts[c].push_back(k);
+                cells[k].push_back(c);
+            }
+    std::vector<std::vector<int64_t>> nbrs(r);
+    std::vector<int64_t> Ulo(2 * r), Uhi(2 * r);
+    for (int64_t k = 0; k < r; ++k) {
+        std::set<int64_t> s;
+        Ulo[2 * k] = Ulo[2 * k + 1] = INT64_MAX;
+        Uhi[2 * k] = Uhi[2 * k + 1] = INT64_MIN;
+        for (int64_t c : cells[k]) {
+            for (int64_t j : leaf_pts[c]) s.insert(j);
+            for (int i = 0; i < 2; ++i) {
+                Ulo[2 * k + i] = std::min(Ulo[2 * k + i], LO[2 * c + i]);
+                Uhi[2 * k + i] = std::max(Uhi[2 * k + i], HI[2 * c + i]);
+            }
+        }
+        nbrs[k].assign(s.begin(), s.end());
+    }
+    // ----------------------------------------------------------- weights
+    std::vector<int64_t> w_base(r + 1, 0);
+    for (int64_t k = 0; k < r; ++k)
+        w_base[k + 1] = w_base[k] + (Uhi[2 * k] - Ulo[2 * k] + 1) * (Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1);
+    std::vector<double> W((size_t)w_base[r], 0.0);
+    for (int64_t c = 0; c < L; ++c) {
+        std::vector<std::vector<double>> vals;
+        const int64_t lo[2] = {LO[2 * c], LO[2 * c + 1]}, hi[2] = {HI[2 * c], HI[2 * c + 1]};
+        if (d == 1) {
+            // two end points; linear hats
+            vals.assign(leaf_pts[c].size(), std::vector<double>((size_t)(hi[1] - lo[1] + 1)));
+            for (size_t j = 0; j < leaf_pts[c].size(); ++j) {
+                int64_t pp = P2[2 * leaf_pts[c][j] + 1];
+                for (int64_t y = lo[1]; y <= hi[1]; ++y)
+                    vals[j][(size_t)(y - lo[1])] = 1.0 - std::fabs((double)(y - pp)) / (double)(hi[1] - lo[1]);
+            }
+        } else {
+            leaf_weights_2d(lo, hi, leaf_pts[c], P2.data(), vals);
+        }
+        const int64_t w1 = hi[1] - lo[1] + 1;
+        for (size_t j = 0; j < leaf_pts[c].size(); ++j) {
+            int64_t k = leaf_pts[c][j];
+            int64_t um1 = Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1;
+            for (int64_t y0 = lo[0]; y0 <= hi[0]; ++y0)
+                for (int64_t y1 = lo[1]; y1 <= hi[1]; ++y1)
+                    W[(size_t)(w_base[k] + (y0 - Ulo[2 * k]) * um1 + (y1 - Ulo[2 * k + 1]))] =
+                        vals[j][(size_t)((y0 - lo[0]) * w1 + (y1 - lo[1]))];
+        }
+    }
+    p.wts = std::move(W);
+    // ------------------------------------------------ extension + planning
+    const bool extend = !(a.flags & PC_NO_EXTEND);
+    const size_t csz = (a.dtype == PC_F64) ? 16 : 8;
+    std::map<int, int> tw_off;   // length -> complex offset
+    auto want_tw = [&](int len) {
+        if (tw_off.count(len)) return tw_off[len];
+        int off = (int)(p.tw.size() / 2);
+        tw_off[len] = off;
+        for (int e = 0; e < len; ++e) {
+            double ang = 2.0 * kPi * (double)e / (double)len;
+            p.tw.push_back(std::cos(ang));
+            p.tw.push_back(-std::sin(ang));
+        }
+        return off;
+    };
+    p.items.clear();
+    p.spec.clear();
+    int64_t kernel_elems = 0;
+    double alg_flops = 0.0;
+    for (int64_t k = 0; k < r; ++k) {
+        const int64_t I_lo[2] = {Ulo[2 * k], Ulo[2 * k + 1]}, I_hi[2] = {Uhi[2 * k], Uhi[2 * k + 1]};
+        const int64_t m[2] = {I_hi[0] - I_lo[0] + 1, I_hi[1] - I_lo[1] + 1};
+        int64_t Rm[2] = {R2[2 * k], R2[2 * k + 1]};
+        if (extend)
+            for (int64_t j : nbrs[k])
+                for (int i = 0; i < 2; ++i) Rm[i] = std::max(Rm[i], R2[2 * j + i]);
+        const int64_t ndom[2] = {nr, nc};
+        int64_t zlo[2], zhi[2], K[2];
+        for (int i = 0; i < 2; ++i) {
+            zlo[i] = std::max(-Rm[i], -I_hi[i]);
+            zhi[i] = std::min(Rm[i], ndom[i] - 1 - I_lo[i]);
+            K[i] = zhi[i] - zlo[i] + 1;
+        }
+        kernel_elems += (2 * R2[2 * k] + 1) * (2 * R2[2 * k + 1] + 1);
+        // extended kernel phi_k^E on the box [zlo, zhi]
+        std::vector<double> E((size_t)(K[0] * K[1]), 0.0);
+        auto defined = [&](int64_t j, int64_t z0, int64_t z1) {
+            int64_t y0 = P2[2 * j] + z0, y1 = P2[2 * j + 1] + z1;
+            return y0 >= 0 && y0 < nr && y1 >= 0 && y1 < nc;
+        };
+        auto val = [&](int64_t j, int64_t z0, int64_t z1) -> double {
+            int64_t Ra = R2[2 * j], Rb = R2[2 * j + 1];
+            if (z0 < -Ra || z0 > Ra || z1 < -Rb || z1 > Rb) return 0.0;
+            return a.phi[a.phi_off[j] + (z0 + Ra) * (2 * Rb + 1) + (z1 + Rb)];
+        };
+        for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0)
+            for (int64_t z1 = zlo[1]; z1 <= zhi[1]; ++z1) {
+                double v = 0.0;
+                if (defined(k, z0, z1)) {
+                    v = val(k, z0, z1);
+                } else if (extend) {
+                    int cnt = 0;
+                    double s = 0.0;
+                    for (int64_t j : nbrs[k]) {
+                        if (j == k || !defined(j, z0, z1)) continue;
+                        ++cnt;
+                        s += val(j, z0, z1);
+                    }
+                    if (cnt) v = s / (double)cnt;
+                }
+                E[(size_t)((z0 - zlo[0]) * K[1] + (z1 - zlo[1]))] = v;
+            }
+        // algorithmic flops by the unsplit 7-smooth convention
+        {
+            int64_t nn = (int64_t)smallest_7smooth(m[0] + K[0] - 1) * smallest_7smooth(m[1] + K[1] - 1);
+            int64_t O = (std::min(I_hi[0] + zhi[0], nr - 1) - std::max(I_lo[0] + zlo[0], (int64_t)0) + 1) *
+                        (std::min(I_hi[1] + zhi[1], nc - 1) - std::max(I_lo[1] + zlo[1], (int64_t)0) + 1);
+            alg_flops += 5.0 * nn * std::log2((double)nn) + 3.0 * nn + (double)(m[0] * m[1]) + (double)O;
+        }
+        // choose FFT lengths and the number of row pieces
+        const int64_t need1 = m[1] + K[1] - 1;
+        int M = next_fft_size((int)((need1 + 1) / 2));
+        if (M < 0) {
+            err = "patch " + std::to_string(k) + " needs a row FFT longer than 512";
+            return PC_ERR_UNSUPPORTED;
+        }
+        int ldr = M + 1;
+        if (ldr % 2 == 0) ++ldr;
+        int best_P = -1, best_n0 = 0;
+        double best_cost = 1e300;
+        const int maxP = (int)std::min<int64_t>(m[0], 64);
+        for (int P = 1; P <= maxP; ++P) {
+            int64_t h = (m[0] + P - 1) / P;
+            int n0 = (d == 1) ? 1 : next_fft_size((int)(h + K[0] - 1));
+            if (n0 < 0) continue;
+            int64_t lds = (int64_t)n0 * ldr * (int64_t)csz;
+            if (lds > kLdsBytes) continue;
+            double nn = (double)n0 * 2.0 * M;
+            double cost = P * nn * std::log2(std::max(nn, 2.0));
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_P = P;
+                best_n0 = n0;
+            }
+        }
+        if (best_P < 0) {
+            err = "patch " + std::to_string(k) + " does not fit the LDS-resident FFT";
+            return PC_ERR_UNSUPPORTED;
+        }
+        const int n0 = best_n0;
+        int a0, b0, am, bm;
+        fft_factor(n0, &a0, &b0);
+        fft_factor(M, &am, &bm);
+        const int n1 = 2 * M;
+        // spectrum of phi_k^E placed circularly, FP64, half spectrum along axis 1
+        const int64_t spec_off = (int64_t)(p.spec.size() / 2);
+        {
+            std::vector<cd> G((size_t)n0 * n1, cd(0.0));
+            for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0)
+                for (int64_t z1 = zlo[1]; z1 <= zhi[1]; ++z1) {
+                    int64_t i0 = ((z0 % n0) + n0) % n0, i1 = ((z1 % n1) + n1) % n1;
+                    G[(size_t)(i0 * n1 + i1)] += E[(size_t)((z0 - zlo[0]) * K[1] + (z1 - zlo[1]))];
+                }
+            std::vector<cd> rowout((size_t)n1), colin((size_t)n0), colout((size_t)n0), scratch;
+            std::vector<cd> W1 = twiddles(n1), W0 = twiddles(n0);
+            std::vector<cd> H((size_t)n0 * (M + 1));
+            for (int i0 = 0; i0 < n0; ++i0) {
+                fft_rec(&G[(size_t)i0 * n1], 1, n1, rowout.data(), W1, n1, scratch);
+                for (int kk = 0; kk <= M; ++kk) H[(size_t)i0 * (M + 1) + kk] = rowout[kk];
+            }
+            const double sc = 1.0 / ((double)n0 * (double)M);
+            std::vector<double> out((size_t)n0 * (M + 1) * 2);
+            for (int kk = 0; kk <= M; ++kk) {
+                for (int i0 = 0; i0 < n0; ++i0) colin[i0] = H[(size_t)i0 * (M + 1) + kk];
+                fft_rec(colin.data(), 1, n0, colout.data(), W0, n0, scratch);
+                int s1 = (kk < M) ? perm_slot(kk, am, bm) : M;
+                for (int k0 = 0; k0 < n0; ++k0) {
+                    int s0 = perm_slot(k0, a0, b0);
+                    out[2 * ((size_t)s0 * (M + 1) + s1)] = colout[k0].real() * sc;
+                    out[2 * ((size_t)s0 * (M + 1) + s1) + 1] = colout[k0].imag() * sc;
+                }
+            }
+            p.spec.insert(p.spec.end(), out.begin(), out.end());
+        }
+        const int t0 = want_tw(n0), tm = want_tw(M), t2m = want_tw(2 * M);
+        // row pieces
+        const int P = best_P;
+        for (int pc_i = 0; pc_i < P; ++pc_i) {
+            int64_t s = (m[0] * pc_i) / P, e = (m[0] * (pc_i + 1)) / P;
+            if (e <= s) continue;
+            int64_t plo0 = I_lo[0] + s, phi0 = I_lo[0] + e - 1;
+            int64_t olo0 = std::max(plo0 + zlo[0], (int64_t)0), ohi0 = std::min(phi0 + zhi[0], nr - 1);
+            int64_t olo1 = std::max(I_lo[1] + zlo[1], (int64_t)0), ohi1 = std::min(I_hi[1] + zhi[1], nc - 1);
+            Item it;
+            std::memset(&it, 0, sizeof(it));
+            it.n0 = n0;
+            it.a0 = a0;
+            it.b0 = b0;
+            it.m = M;
+            it.am = am;
+            it.bm = bm;
+            it.ld = ldr;
+            it.tw0 = t0;
+            it.twm = tm;
+            it.tw2m = t2m;
+            it.g0 = (int32_t)olo0;
+            it.g1 = (int32_t)olo1;
+            it.in_off0 = (int32_t)(plo0 - olo0);
+            it.in_off1 = (int32_t)(I_lo[1] - olo1);
+            it.in_n0 = (int32_t)(e - s);
+            it.in_n1 = (int32_t)m[1];
+            it.out_n0 = (int32_t)(ohi0 - olo0 + 1);
+            it.out_n1 = (int32_t)(ohi1 - olo1 + 1);
+            it.patch = (int32_t)k;
+            it.w_off = w_base[k] + s * m[1];
+            it.spec_off = spec_off;
+            // the FFT box must hold input and output without wrap-around
+            if (it.in_off0 < 0 || it.in_off1 < 0 || it.in_off0 + it.in_n0 > n0 || it.in_off1 + it.in_n1 > n1 ||
+                it.out_n0 > n0 || it.out_n1 > n1) {
+                err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
+                return PC_ERR_ARG;
+            }
+            it.slot_fwd = p.slot_fwd;
+            it.slot_adj = p.slot_adj;
+            p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
+            p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
+            p.sum_fft_points += (int64_t)n0 * n1;
+            p.max_lds = std::max(p.max_lds, (int)(n0 * ldr * csz));
+            p.items.push_back(it);
+        }
+    }
+    p.kernel_elems = kernel_elems;
+    p.alg_flops = alg_flops;
+    // --------------------------------------------------- reduction tiles
+    auto build_tiles = [&](bool adj, std::vector<Tile>& tiles, std::vector<int32_t>& contrib, std::vector<Box>& boxes) {
+        boxes.resize(p.items.size());
+        for (size_t i = 0; i < p.items.size(); ++i) {
+            const Item& it = p.items[i];
+            Box b;
+            if (!adj) {
+                b.lo0 = it.g0;
+                b.lo1 = it.g1;
+                b.n0 = it.out_n0;
+                b.n1 = it.out_n1;
+                b.off = it.slot_fwd;
+            } else {
+                b.lo0 = it.g0 + it.in_off0;
+                b.lo1 = it.g1 + it.in_off1;
+                b.n0 = it.in_n0;
+                b.n1 = it.in_n1;
+                b.off = it.slot_adj;
+            }
+            boxes[i] = b;
+        }
+        tiles.clear();
+        contrib.clear();
+        for (int r0 = 0; r0 < nr; r0 += kReduceRows)
+            for (int cc0 = 0; cc0 < nc; cc0 += kReduceCols) {
+                Tile t;
+                t.r0 = r0;
+                t.c0 = cc0;
+                t.nr = (int)std::min<int64_t>(kReduceRows, nr - r0);
+                t.nc = (int)std::min<int64_t>(kReduceCols, nc - cc0);
+                t.beg = (int32_t)contrib.size();
+                for (size_t i = 0; i < boxes.size(); ++i) {
+                    const Box& b = boxes[i];
+                    if (b.lo0 < r0 + t.nr && b.lo0 + b.n0 > r0 && b.lo1 < cc0 + t.nc && b.lo1 + b.n1 > cc0)
+                        contrib.push_back((int32_t)i);
+                }
+                t.end = (int32_t)contrib.size();
+                tiles.push_back(t);
+            }
+    };
+    build_tiles(false, p.tiles_fwd, p.contrib_fwd, p.boxes_fwd);
+    build_tiles(true, p.tiles_adj, p.contrib_adj, p.boxes_adj);
+    p.leaf_box.resize(4 * L);
+    for (int64_t c = 0; c < L; ++c) {
+        p.leaf_box[4 * c] = (int32_t)LO[2 * c];
+        p.leaf_box[4 * c + 1] = (int32_t)LO[2 * c + 1];
+        p.leaf_box[4 * c + 2] = (int32_t)(HI[2 * c] - LO[2 * c] + 1);
+        p.leaf_box[4 * c + 3] = (int32_t)(HI[2 * c + 1] - LO[2 * c + 1] + 1);
+    }
+    return PC_OK;
+}
+
+}  // namespace pc

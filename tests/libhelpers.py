@@ -1,0 +1,38 @@
+"""Helpers for the library tests (inputs, tolerances, tiny cases)."""
+import numpy as np
+
+from workloads import make_config
+from tests.tilings import hanging_2d, const_blur, workload_from, tensor
+
+# Per-vector relative L2 bars against the FP64 oracle.
+TOL = {0: 1e-5, 1: 1e-12}     # PC_F32, PC_F64
+
+
+def relerr(got, ref):
+    got = np.asarray(got, dtype=np.float64).reshape(ref.shape)
+    num = np.linalg.norm((got - ref).reshape(ref.shape[0], -1), axis=1)
+    den = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    return num / np.maximum(den, 1e-300)
+
+
+def small_cases():
+    """(name, workload) pairs spanning several tiles, ragged tails, hanging
+    nodes, 1-D, rectangles and boundary-clipped patches."""
+    cases = [("cfg0", make_config(0))]
+    lo, hi = hanging_2d(33, corner=(32, 0), levels=3)
+    x0, x1 = np.meshgrid(np.arange(33), np.arange(33), indexing="ij")
+    s = 0.8 + 1.5 * (x0 + x1) / 64
+    cases.append(("hanging33", workload_from(np.stack([s, s]), lo, hi)))
+    lo = np.array([[0], [9], [13], [30], [77]])
+    hi = np.array([[9], [13], [30], [77], [100]])
+    x = np.arange(101)
+    s1 = 1.0 + 2.0 * np.sin(x / 17.0) ** 2
+    cases.append(("1d", workload_from(s1[None, :], lo, hi)))
+    lo, hi = tensor((45, 301), 4)
+    cases.append(("rect45x301", const_blur((45, 301), 1.6, lo, hi)))
+    lo, hi = tensor((70, 70), 2)                     # one leaf: a big single patch
+    x0, x1 = np.meshgrid(np.arange(70), np.arange(70), indexing="ij")
+    s = 2.0 + 3.0 * (x0 / 69.0)
+    cases.append(("oneleaf70", workload_from(np.stack([s, s]), lo, hi)))
+    cases.append(("cfg1_small", make_config(1, scale=0.25)))
+    return cases

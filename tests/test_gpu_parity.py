@@ -1,0 +1,196 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Bars (per-vector relative L2 against the FP64 oracle on the same
+dtype-rounded inputs): FP32 <= 1e-5, FP64 <= 1e-12.  Integer/layout
+properties (batch vs single apply, plain vs fused, repeat runs) are checked
+bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import OracleOperator, estimate
+from workloads import make_config
+from tests.libhelpers import small_cases, relerr, TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible HIP device")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    _require_gpu()
+    from paper_1805_06018_amd import _lib
+    return _lib
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dt(dtype):
+    return (torch.float64, np.float64) if dtype == 1 else (torch.float32, np.float32)
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_small_cases_parity(lib, idx):
+    name, w = small_cases()[idx]
+    rng = np.random.default_rng(200 + idx)
+    U = rng.standard_normal((5, w.N))
+    for flags in (0, lib.PC_NO_EXTEND):
+        ora = OracleOperator.from_workload(w, extend=(flags == 0))
+        for dtype in (lib.PC_F64, lib.PC_F32):
+            _note(f"case={name} flags={flags} dtype={dtype}")
+            tdt, ndt = _dt(dtype)
+            op = lib.PcOperator.from_workload(w, dtype=dtype, flags=flags)
+            Ur = U.astype(ndt)
+            Ud = torch.from_numpy(Ur).cuda()
+            for adj in (False, True):
+                out = torch.full_like(Ud, float("nan"))
+                (op.apply_adjoint_batch if adj else op.apply_batch)(Ud, out)
+                torch.cuda.synchronize()
+                ref = ora.apply_batch(Ur.astype(np.float64), adjoint=adj)
+                e = relerr(out.cpu().numpy(), ref)
+                assert e.max() <= TOL[dtype], (name, flags, dtype, adj, e)
+            op.close()
+
+
+def test_batch_column_equals_single_apply_and_plain(lib):
+    w = make_config(1, scale=0.25)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    U = torch.from_numpy(w.vectors(7, dtype=np.float32)).cuda()
+    out = torch.zeros_like(U)
+    op.apply_batch(U, out)
+    plain = torch.zeros_like(U)
+    op.apply_batch_plain(U, plain)
+    single = torch.zeros(w.N, dtype=torch.float32, device="cuda")
+    again = torch.zeros_like(U)
+    op.apply_batch(U, again)
+    torch.cuda.synchronize()
+    assert torch.equal(out, again)                   # repeat run: bitwise
+    assert torch.equal(out, plain)                   # plain path: same sums, same order
+    for j in (0, 3, 6):
+        op.apply(U[j].contiguous(), single)
+        torch.cuda.synchronize()
+        assert torch.equal(single, out[j])           # column j of the batch
+    # empty batch is a no-op; strided rows are honoured
+    empty = torch.zeros((0, w.N), dtype=torch.float32, device="cuda")
+    op.apply_batch(empty, empty)
+    Ubig = torch.zeros((3, w.N + 64), dtype=torch.float32, device="cuda")
+    Ubig[:, :w.N] = U[:3]
+    Obig = torch.full((3, w.N + 64), 7.0, dtype=torch.float32, device="cuda")
+    op.apply_batch(Ubig[:, :w.N], Obig[:, :w.N])
+    torch.cuda.synchronize()
+    assert torch.equal(Obig[:, :w.N], out[:3])
+    assert torch.all(Obig[:, w.N:] == 7.0)
+
+
+def test_full_size_blur1024_batch64(lib):
+    """The benchmark workload (1024^2, ~600 points, B = 64, FP32) in the
+    launch configuration the benchmark times: vector 0 against the full oracle
+    apply, every vector at sampled outputs."""
+    w = make_config(1)
+    _note(f"blur1024: r={w.r}")
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    U = w.vectors(64, dtype=np.float32)
+    Ud = torch.from_numpy(U).cuda()
+    out = torch.zeros_like(Ud)
+    op.apply_batch(Ud, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    ora = OracleOperator.from_workload(w)
+    _note("oracle apply of vector 0")
+    ref0 = ora.apply(U[0].astype(np.float64))
+    e0 = np.linalg.norm(got[0] - ref0) / np.linalg.norm(ref0)
+    assert e0 <= 1e-5, e0
+    rng = np.random.default_rng(7)
+    ys = np.stack([rng.integers(0, 1024, 24), rng.integers(0, 1024, 24)], axis=1)
+    ys = np.vstack([ys, [[0, 0], [1023, 1023], [0, 1023], [1023, 0], [511, 512]]])
+    flat = ys[:, 0] * 1024 + ys[:, 1]
+    scale = np.abs(ref0).max()
+    for j in range(0, 64, 9):
+        refj = ora.apply_at(U[j].astype(np.float64), ys)
+        err = np.abs(got[j, flat] - refj).max() / scale
+        assert err <= 1e-5, (j, err)
+    # adjoint on the same operator, one vector, full oracle
+    outa = torch.zeros_like(Ud[:1])
+    op.apply_adjoint_batch(Ud[:1], outa)
+    torch.cuda.synchronize()
+    refa = ora.apply_adjoint(U[0].astype(np.float64))
+    ea = np.linalg.norm(outa.cpu().numpy()[0] - refa) / np.linalg.norm(refa)
+    assert ea <= 1e-5, ea
+
+
+class _DevView:
+    """A device array view built from a raw pointer (for the callback)."""
+
+    def __init__(self, ptr, rows, cols, ld, typestr, esz):
+        self.__cuda_array_interface__ = {"shape": (rows, cols), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": (ld * esz, esz)}
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_error_estimate_matches_oracle(lib, dtype):
+    from tests.tilings import hanging_2d, workload_from
+    n = 33
+    lo, hi = hanging_2d(n, corner=(0, 32), levels=3)
+    x0, x1 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    s = 0.7 + 1.2 * (x0 + 2 * x1) / (3 * n)
+    w = workload_from(np.stack([s, s]), lo, hi)
+    tdt, ndt = _dt(dtype)
+    A = w.op.dense()
+    q = 6
+    Z = np.random.default_rng(31).standard_normal((q, w.N)).astype(ndt)
+    Y = np.ascontiguousarray((A.T @ Z.astype(np.float64).T).T.astype(ndt))
+    ora = OracleOperator.from_workload(w)
+    eta_o, eom_o, erel_o, _ = estimate(ora, Z.astype(np.float64), Y.astype(np.float64))
+    op = lib.PcOperator.from_workload(w, dtype=dtype)
+    Zd = torch.from_numpy(Z).cuda()
+    Yd = torch.from_numpy(Y).cuda()
+    eta, eom, erel = op.error_estimate(Zd, Yd)
+    tol = 1e-10 if dtype == 1 else 2e-4
+    assert np.abs(eta - eta_o).max() <= tol * eta_o.max()
+    assert abs(eom - eom_o) <= tol * eom_o and abs(erel - erel_o) <= tol * erel_o
+    # exact adjoint supplied through the callback instead of Y
+    At = torch.from_numpy(A.astype(ndt)).cuda()
+    esz = 8 if dtype == 1 else 4
+    typestr = "<f8" if dtype == 1 else "<f4"
+    calls = []
+
+    def cb(B, iptr, ldi, optr, ldo, sptr):
+        zin = torch.as_tensor(_DevView(iptr, B, w.N, ldi, typestr, esz), device="cuda")
+        yout = torch.as_tensor(_DevView(optr, B, w.N, ldo, typestr, esz), device="cuda")
+        yout.copy_(zin @ At)
+        torch.cuda.synchronize()
+        calls.append(B)
+        return 0
+
+    eta2, eom2, erel2 = op.error_estimate(Zd, None, exact_adjoint=cb)
+    assert calls == [q]
+    assert np.abs(eta2 - eta_o).max() <= max(tol, 1e-5) * eta_o.max()
+    # a failing callback reports PC_ERR_CALLBACK and leaves the operator usable
+    with pytest.raises(lib.PcError) as ei:
+        op.error_estimate(Zd, None, exact_adjoint=lambda *a: 3)
+    assert ei.value.status == lib.PC_ERR_CALLBACK
+    eta3, _, _ = op.error_estimate(Zd, Yd)
+    assert np.array_equal(eta3, eta)
+
+
+def test_apply_argument_errors(lib):
+    w = make_config(0)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F64)
+    U = torch.zeros((2, w.N - 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.PcError) as ei:
+        op.apply_batch(U, U)
+    assert ei.value.status == lib.PC_ERR_ARG
+    with pytest.raises(TypeError):
+        op.apply_batch(torch.zeros((1, w.N), dtype=torch.float32, device="cuda"),
+                       torch.zeros((1, w.N), dtype=torch.float32, device="cuda"))

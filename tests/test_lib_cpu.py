@@ -1,0 +1,144 @@
+"""CPU tests of the HIP library: exported symbols, argument validation (all
+of which happens before any HIP call), and the kernel phases run by the CPU
+emulation build against the oracle (with an AddressSanitizer pass)."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import OracleOperator
+from workloads import make_config
+from tests.libhelpers import small_cases, relerr, TOL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_1805_06018_amd")
+
+
+def _declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "pc.h")).read()
+    return sorted(set(re.findall(r"^(?:pc_status|size_t|const char\*)\s+(pc_\w+)\s*\(", hdr, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(os.path.join(PKG, "libpc.so"))
+    syms = _declared_symbols()
+    assert "pc_create" in syms and "pc_error_estimate" in syms and len(syms) >= 11
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_binding_lists_every_symbol():
+    from paper_1805_06018_amd import _lib
+    assert sorted(_lib.EXPORTED) == _declared_symbols()
+
+
+# ------------------------------------------------------------- validation
+def _args(w):
+    return dict(d=w.d, shape=w.shape, leaf_lo=w.leaf_lo, leaf_hi=w.leaf_hi, points=w.points,
+                radius=w.radius, phi=w.phi, phi_off=w.phi_off)
+
+
+def test_create_rejects_bad_input():
+    from paper_1805_06018_amd._lib import raw_create, PC_ERR_ARG, PC_ERR_GRID, PC_ERR_UNSUPPORTED
+    w = make_config(0)
+    a = _args(w)
+    st, msg = raw_create(**{**a, "leaf_lo": a["leaf_lo"][:-1], "leaf_hi": a["leaf_hi"][:-1]})
+    assert st == PC_ERR_GRID, msg                          # gap in the tiling
+    lo = np.vstack([a["leaf_lo"], [[1, 1]]])
+    hi = np.vstack([a["leaf_hi"], [[5, 5]]])
+    st, msg = raw_create(**{**a, "leaf_lo": lo, "leaf_hi": hi})
+    assert st == PC_ERR_GRID, msg                          # overlap
+    pts = a["points"].copy()
+    pts[3] += 1
+    st, msg = raw_create(**{**a, "points": pts})
+    assert st == PC_ERR_GRID, msg                          # points != corners
+    rad = a["radius"].copy()
+    rad[0, 0] = -1
+    st, msg = raw_create(**{**a, "radius": rad})
+    assert st == PC_ERR_ARG, msg                           # negative radius
+    off = a["phi_off"].copy()
+    off[5] += 1
+    st, msg = raw_create(**{**a, "phi_off": off})
+    assert st == PC_ERR_ARG, msg                           # phi_off inconsistent
+    st, msg = raw_create(**{**a, "d": 4})
+    assert st == PC_ERR_ARG, msg
+    st, msg = raw_create(**a, dtype=7)
+    assert st == PC_ERR_ARG, msg
+    st, msg = raw_create(**a, flags=1 << 5)
+    assert st == PC_ERR_ARG, msg
+    w3 = make_config(2, scale=0.125)
+    st, msg = raw_create(**_args(w3))
+    assert st == PC_ERR_UNSUPPORTED, msg                   # 3-D apply not built
+
+
+# ------------------------------------------------------------- CPU emulation
+def _emu_lib(path=os.path.join(PKG, "libpc_emu.so")):
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.pc_emu_create.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P, P, P,
+                                  ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.pc_emu_apply.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64]
+    lib.pc_emu_destroy.argtypes = [P]
+    lib.pc_emu_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+def emu_apply(lib, w, U, dtype, flags=0, adj=False):
+    k = [np.ascontiguousarray(v, dtype=np.int64) for v in (w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius)]
+    phi = np.ascontiguousarray(w.phi, dtype=np.float64)
+    off = np.ascontiguousarray(w.phi_off, dtype=np.int64)
+    h = ctypes.c_void_p()
+    rc = lib.pc_emu_create(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
+                           len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data, off.ctypes.data,
+                           dtype, flags, ctypes.byref(h))
+    assert rc == 0, lib.pc_emu_last_error()
+    dt = np.float64 if dtype == 1 else np.float32
+    U = np.ascontiguousarray(U, dtype=dt)
+    out = np.zeros_like(U)
+    lib.pc_emu_apply(h, int(adj), U.shape[0], U.ctypes.data, U.shape[1], out.ctypes.data, out.shape[1])
+    lib.pc_emu_destroy(h)
+    return out
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_emulated_kernels_match_oracle(idx):
+    name, w = small_cases()[idx]
+    lib = _emu_lib()
+    rng = np.random.default_rng(100 + idx)
+    U = rng.standard_normal((3, w.N))
+    for flags in (0, 1):
+        op = OracleOperator.from_workload(w, extend=(flags == 0))
+        for dtype in (1, 0):
+            Ur = U.astype(np.float32).astype(np.float64) if dtype == 0 else U
+            for adj in (False, True):
+                got = emu_apply(lib, w, Ur, dtype, flags, adj)
+                ref = op.apply_batch(Ur, adjoint=adj)
+                e = relerr(got, ref)
+                assert e.max() <= TOL[dtype], (name, flags, dtype, adj, e)
+
+
+def test_emulated_kernels_under_address_sanitizer():
+    """Same emulation built with AddressSanitizer, run in a child process with
+    the sanitizer runtime preloaded: any out-of-range index aborts it."""
+    asan_rt = "/opt/rocm/lib/llvm/lib/clang/22/lib/linux/libclang_rt.asan-x86_64.so"
+    lib = os.path.join(PKG, "libpc_emu_asan.so")
+    if not (os.path.exists(asan_rt) and os.path.exists(lib)):
+        pytest.skip("sanitizer runtime or ASan emulation build not present")
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r)\n"
+        "from tests.test_lib_cpu import _emu_lib, emu_apply\n"
+        "from tests.libhelpers import small_cases\n"
+        "lib = _emu_lib(%r)\n"
+        "for name, w in small_cases():\n"
+        "    U = np.random.default_rng(1).standard_normal((2, w.N))\n"
+        "    for dt in (0, 1):\n"
+        "        for fl in (0, 1):\n"
+        "            for adj in (0, 1): emu_apply(lib, w, U, dt, fl, adj)\n"
+        "print('ASAN-CLEAN')\n" % (ROOT, lib))
+    env = dict(os.environ, LD_PRELOAD=asan_rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0 and "ASAN-CLEAN" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
