@@ -33,16 +33,15 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
             pc::Ctx<T> c = pc::make_ctx<T>(it, adj, in.data(), slots.data(), wts.data(),
                                            reinterpret_cast<const C*>(spec.data()),
                                            reinterpret_cast<const C*>(tw.data()), P.cols);
-            const int nth = pc::kThreads;
-            for (int t = 0; t < nth; ++t) pc::ph1(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph_rows2<-1>(c, buf.data(), t, nth, c.s_off0, c.s_n0);
-            for (int t = 0; t < nth; ++t) pc::ph3(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph4(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph5(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph6(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph7(c, buf.data(), t, nth);
-            for (int t = 0; t < nth; ++t) pc::ph_rows2<1>(c, buf.data(), t, nth, c.d_off0, c.d_n0);
-            for (int t = 0; t < nth; ++t) pc::ph9(c, buf.data(), t, nth);
+            const int nth = pc::threads_for<T>();
+            for (int t = 0; t < nth; ++t) pc::phA(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phB(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phC(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phD(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phE(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phF(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phG(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phH(c, buf.data(), t, nth);
         }
         std::vector<T> out((size_t)N, T(0));
         const auto& tiles = adj ? P.tiles_adj : P.tiles_fwd;

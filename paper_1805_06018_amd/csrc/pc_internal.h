@@ -9,7 +9,6 @@ namespace pc {
 // Largest radix handled by the register codelets; every FFT length used by
 // the library is a * b with a, b in {1,2,3,4,5,6,7,8,9,10,12,14,15,16}.
 constexpr int kMaxRadix = 16;
-constexpr int kThreads = 512;          // threads per convolution workgroup
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kReduceCols = 256;       // reduce tile width (threads)
 constexpr int kReduceRows = 8;         // reduce tile height (accumulators per thread)

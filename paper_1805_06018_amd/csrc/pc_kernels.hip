@@ -25,9 +25,10 @@ struct ConvArgs {
 // all their vectors in sequence, so a patch's spectrum is fetched into one
 // XCD's L2 and reused there by every vector.
 template <class T>
-__global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs<T> A) {
+__global__ __launch_bounds__(threads_for<T>()) void conv_kernel(ConvArgs<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    constexpr int NT = threads_for<T>();
     const int bid = blockIdx.x;
     const int xcd = bid & 7, l = bid >> 3;
     const int item = xcd + 8 * (l / A.B);
@@ -37,23 +38,21 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs<T> A) {
     const Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
                                  A.wts, A.spec, A.tw, A.pitch);
     const int tid = threadIdx.x;
-    ph1(c, buf, tid, kThreads);
+    phA(c, buf, tid, NT);
     __syncthreads();
-    ph_rows2<-1>(c, buf, tid, kThreads, c.s_off0, c.s_n0);
+    phB(c, buf, tid, NT);
     __syncthreads();
-    ph3(c, buf, tid, kThreads);
+    phC(c, buf, tid, NT);
     __syncthreads();
-    ph4(c, buf, tid, kThreads);
+    phD(c, buf, tid, NT);
     __syncthreads();
-    ph5(c, buf, tid, kThreads);
+    phE(c, buf, tid, NT);
     __syncthreads();
-    ph6(c, buf, tid, kThreads);
+    phF(c, buf, tid, NT);
     __syncthreads();
-    ph7(c, buf, tid, kThreads);
+    phG(c, buf, tid, NT);
     __syncthreads();
-    ph_rows2<1>(c, buf, tid, kThreads, c.d_off0, c.d_n0);
-    __syncthreads();
-    ph9(c, buf, tid, kThreads);
+    phH(c, buf, tid, NT);
 }
 
 template <class T>
@@ -153,7 +152,7 @@ static hipError_t conv_t(const DevPlan& P, bool adj, int item_lo, int item_hi, i
     const int64_t per_xcd = (int64_t)((A.n_items + 7) / 8) * B;
     const int64_t nblk = 8 * per_xcd;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(conv_kernel<T>, dim3((unsigned)nblk), dim3(kThreads), P.max_lds, s, A);
+    hipLaunchKernelGGL(conv_kernel<T>, dim3((unsigned)nblk), dim3(threads_for<T>()), P.max_lds, s, A);
     return hipGetLastError();
 }
 

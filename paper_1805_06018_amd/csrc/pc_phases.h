@@ -1,4 +1,4 @@
-// The nine phases of one convolution work item (a patch or row piece of the
+// The phases of one convolution work item (a patch or row piece of the
 // product-convolution sum, eq. 2.3, or of its adjoint, eq. 1.4).
 //
 // Work item layout: an n0 x n1 FFT box (n1 = 2m) lives in LDS as n0 rows of
@@ -13,19 +13,20 @@
 // transform undoes the passes in reverse, so no reordering pass is needed.
 //
 // Phases (one barrier between consecutive phases):
-//   1 gather (weighted for the forward sum) + row pass 1
-//   2 row pass 2
-//   3 real-row post-processing (thread-private, in place)
-//   4 column pass 1 (only the gathered rows are non-zero)
-//   5 column pass 2, product with the spectrum (conjugate for the adjoint),
+//   A gather (weighted for the forward sum) + row pass 1
+//   B row pass 2 fused with the real-row post-processing: a task owns the
+//     slot groups k1 and m-k1's group, which hold every pair Z[k], Z[m-k]
+//   C column pass 1 (only the gathered rows are non-zero)
+//   D column pass 2, product with the spectrum (conjugate for the adjoint),
 //     inverse column pass 2
-//   6 inverse column pass 1 (only rows needed by the output are kept)
-//   7 real-row pre-processing for the inverse
-//   8 inverse row pass 2
-//   9 inverse row pass 1 + write of the output box (weighted for the adjoint)
+//   E inverse column pass 1 (only rows needed by the output are kept)
+//   F real-row pre-processing fused with inverse row pass 2
+//   G inverse row pass 1 in place (rows end in natural order)
+//   H coalesced copy of the output box to staging (weighted for the adjoint)
 //
-// All functions are __host__ __device__: the GPU kernel runs them with a
-// barrier in between; a host-only build can run them thread by thread.
+// Every phase is templated on its radix (dispatched once per phase) and all
+// functions are __host__ __device__: the GPU kernel runs them with a barrier
+// in between; a host-only build runs them thread by thread.
 #pragma once
 #include "pc_fft.h"
 #include "pc_internal.h"
@@ -33,11 +34,21 @@
 namespace pc {
 
 template <class T>
+constexpr int threads_for() {
+    return sizeof(T) == 4 ? 1024 : 512;
+}
+
+// floor(x / d) for 0 <= x < 2^22 with inv = 1.0f / d (exact: the fraction
+// (x + 1/2) / d stays at least 1/(2d) away from an integer).
+__host__ __device__ inline int fdiv(int x, float inv) { return (int)(((float)x + 0.5f) * inv); }
+
+template <class T>
 struct Ctx {
     Item it;
     bool adj;
     int s_off0, s_n0, s_off1, s_n1;   // gathered box (FFT coordinates)
     int d_off0, d_n0, d_off1, d_n1;   // written box
+    float inv_bm, inv_b0, inv_nc, inv_sn0, inv_dn0;
     const T* src;                     // input vector, Omega origin
     T* dst;                           // staging box of this item and vector
     const T* w;                       // weight table of the item's input box
@@ -63,6 +74,11 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
         c.d_off0 = it.in_off0; c.d_n0 = it.in_n0; c.d_off1 = it.in_off1; c.d_n1 = it.in_n1;
         c.dst = slot_vec + it.slot_adj;
     }
+    c.inv_bm = 1.0f / (float)it.bm;
+    c.inv_b0 = 1.0f / (float)it.b0;
+    c.inv_nc = 1.0f / (float)(it.m + 1);
+    c.inv_sn0 = 1.0f / (float)c.s_n0;
+    c.inv_dn0 = 1.0f / (float)c.d_n0;
     c.src = in_vec;
     c.w = wts + it.w_off;
     c.spec = spec + it.spec_off;
@@ -73,210 +89,339 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
     return c;
 }
 
-// 1: gather + row pass 1 (forward DFT_am, twiddle w_m^(j0 k1))
-template <class T>
-__host__ __device__ inline void ph1(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int am = c.it.am, bm = c.it.bm, ld = c.it.ld;
+#define PC_RADIX_SWITCH(R, FN, ...)               \
+    switch (R) {                                  \
+        case 1: FN<1>(__VA_ARGS__); break;        \
+        case 2: FN<2>(__VA_ARGS__); break;        \
+        case 3: FN<3>(__VA_ARGS__); break;        \
+        case 4: FN<4>(__VA_ARGS__); break;        \
+        case 5: FN<5>(__VA_ARGS__); break;        \
+        case 6: FN<6>(__VA_ARGS__); break;        \
+        case 7: FN<7>(__VA_ARGS__); break;        \
+        case 8: FN<8>(__VA_ARGS__); break;        \
+        case 9: FN<9>(__VA_ARGS__); break;        \
+        case 10: FN<10>(__VA_ARGS__); break;      \
+        case 12: FN<12>(__VA_ARGS__); break;      \
+        case 14: FN<14>(__VA_ARGS__); break;      \
+        case 15: FN<15>(__VA_ARGS__); break;      \
+        case 16: FN<16>(__VA_ARGS__); break;      \
+        default: break;                           \
+    }
+
+// Row pass-2 radices: m <= 128 and the larger factor goes first, so bm <= 10.
+#define PC_RADIX_SWITCH_ROW2(R, FN, ...)          \
+    switch (R) {                                  \
+        case 1: FN<1>(__VA_ARGS__); break;        \
+        case 2: FN<2>(__VA_ARGS__); break;        \
+        case 3: FN<3>(__VA_ARGS__); break;        \
+        case 4: FN<4>(__VA_ARGS__); break;        \
+        case 5: FN<5>(__VA_ARGS__); break;        \
+        case 6: FN<6>(__VA_ARGS__); break;        \
+        case 7: FN<7>(__VA_ARGS__); break;        \
+        case 8: FN<8>(__VA_ARGS__); break;        \
+        case 9: FN<9>(__VA_ARGS__); break;        \
+        case 10: FN<10>(__VA_ARGS__); break;      \
+        default: break;                           \
+    }
+constexpr int kMaxRowPass2Radix = 10;
+
+// ---------------------------------------------------------------- phase A
+template <int A, class T>
+__host__ __device__ inline void phA_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int bm = c.it.bm, ld = c.it.ld;
     const int ntask = c.s_n0 * bm;
     for (int t = tid; t < ntask; t += nth) {
-        const int j0 = t % bm, q = t / bm;
+        const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
         const int row = c.s_off0 + q;
         const T* srow = c.src + (int64_t)(c.it.g0 + row) * c.pitch + c.it.g1;
         const T* wrow = c.w + (int64_t)q * c.s_n1;
-        cx<T> x[kMaxRadix];
+        cx<T> x[A];
 #pragma unroll
-        for (int j1 = 0; j1 < kMaxRadix; ++j1) {
-            if (j1 < am) {
-                const int j = bm * j1 + j0;
-                const int e0 = 2 * j - c.s_off1, e1 = e0 + 1;
-                T v0 = T(0), v1 = T(0);
-                if ((unsigned)e0 < (unsigned)c.s_n1) {
-                    v0 = srow[2 * j];
-                    if (!c.adj) v0 *= wrow[e0];
-                }
-                if ((unsigned)e1 < (unsigned)c.s_n1) {
-                    v1 = srow[2 * j + 1];
-                    if (!c.adj) v1 *= wrow[e1];
-                }
-                x[j1] = {v0, v1};
+        for (int j1 = 0; j1 < A; ++j1) {
+            const int j = bm * j1 + j0;
+            const int e0 = 2 * j - c.s_off1, e1 = e0 + 1;
+            T v0 = T(0), v1 = T(0);
+            if ((unsigned)e0 < (unsigned)c.s_n1) {
+                v0 = srow[2 * j];
+                if (!c.adj) v0 *= wrow[e0];
             }
+            if ((unsigned)e1 < (unsigned)c.s_n1) {
+                v1 = srow[2 * j + 1];
+                if (!c.adj) v1 *= wrow[e1];
+            }
+            x[j1] = {v0, v1};
         }
-        dft_rt<-1>(am, x);
+        Dft<A, -1>::run(x);
         cx<T>* out = buf + (int64_t)row * ld + j0;
 #pragma unroll
-        for (int k1 = 0; k1 < kMaxRadix; ++k1)
-            if (k1 < am) out[bm * k1] = cmul(x[k1], c.twm[j0 * k1]);
+        for (int k1 = 0; k1 < A; ++k1) out[bm * k1] = cmul(x[k1], c.twm[j0 * k1]);
     }
 }
-
-// 2 (forward) / 8 (inverse): row pass 2 over rows [r_off, r_off + r_n)
-template <int S, class T>
-__host__ __device__ inline void ph_rows2(const Ctx<T>& c, cx<T>* buf, int tid, int nth, int r_off, int r_n) {
-    const int am = c.it.am, bm = c.it.bm, ld = c.it.ld;
-    const int ntask = r_n * am;
-    for (int t = tid; t < ntask; t += nth) {
-        const int r = t % r_n, k1 = t / r_n;
-        cx<T>* p = buf + (int64_t)(r_off + r) * ld + bm * k1;
-        cx<T> x[kMaxRadix];
-#pragma unroll
-        for (int k0 = 0; k0 < kMaxRadix; ++k0)
-            if (k0 < bm) x[k0] = p[k0];
-        dft_rt<S>(bm, x);
-#pragma unroll
-        for (int k0 = 0; k0 < kMaxRadix; ++k0)
-            if (k0 < bm) p[k0] = x[k0];
-    }
-}
-
-__host__ __device__ inline int slot_of(int k, int a, int b) { return b * (k % a) + k / a; }
-
-// 3: Z = DFT_m(x_even + i x_odd)  ->  X = DFT_2m(x) for k in [0, m]
-//    (X[m] goes to the extra column m), thread-private in place.
 template <class T>
-__host__ __device__ inline void ph3(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int M = c.it.m, am = c.it.am, bm = c.it.bm, ld = c.it.ld;
-    const int H = M / 2 + 1;
+__host__ __device__ inline void phA(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.am, phA_r, c, buf, tid, nth);
+}
+
+// Real-row post-processing of one frequency pair: from Z[k], Z[m-k] of
+// Z = DFT_m(x_even + i x_odd) to X[k] and X[m-k] of X = DFT_2m(x).
+template <class T>
+__host__ __device__ inline void post_pair(cx<T> Zk, cx<T> Zm, cx<T> w, cx<T>& Xk, cx<T>& Xm) {
+    const T h = T(0.5);
+    const cx<T> E = {(Zk.x + Zm.x) * h, (Zk.y - Zm.y) * h};
+    const cx<T> O = {(Zk.y + Zm.y) * h, (Zm.x - Zk.x) * h};
+    const cx<T> wO = cmul(w, O);
+    Xk = E + wO;
+    Xm = conj(E - wO);
+}
+// Inverse: from X[k], X[m-k] back to Z[k], Z[m-k].
+template <class T>
+__host__ __device__ inline void pre_pair(cx<T> Xk, cx<T> Xm, cx<T> w, cx<T>& Zk, cx<T>& Zm) {
+    const T h = T(0.5);
+    const cx<T> E = {(Xk.x + Xm.x) * h, (Xk.y - Xm.y) * h};
+    const cx<T> D = {(Xk.x - Xm.x) * h, (Xk.y + Xm.y) * h};
+    const cx<T> O = cmulc(D, w);
+    Zk = {E.x - O.y, E.y + O.x};
+    Zm = {E.x + O.y, O.x - E.y};
+}
+
+// ---------------------------------------------------------------- phase B
+// Task (row, k1) with k1 in [0, am/2]: groups k1 and k1b = (am - k1) mod am.
+// Frequencies k = k1 + am k0 and m - k = k1b + am (bm - 1 - k0) for k1 > 0;
+// for k1 = 0 the partner of am k0 is am (bm - k0); slot(k) = bm k1 + k0 and
+// X[m] goes to the extra column m.
+template <int Bm, class T>
+__host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int am = c.it.am, ld = c.it.ld, M = c.it.m;
+    const int H = am / 2 + 1;
     const int ntask = c.s_n0 * H;
-    const T half = T(0.5);
     for (int t = tid; t < ntask; t += nth) {
-        const int r = t % c.s_n0, k = t / c.s_n0;
+        const int k1 = fdiv(t, c.inv_sn0), r = t - k1 * c.s_n0;
         cx<T>* p = buf + (int64_t)(c.s_off0 + r) * ld;
-        const int sk = slot_of(k, am, bm);
-        const cx<T> Zk = p[sk];
-        if (k == 0) {
-            p[sk] = {Zk.x + Zk.y, T(0)};
-            p[M] = {Zk.x - Zk.y, T(0)};
-        } else {
-            const int skm = slot_of(M - k, am, bm);
-            const cx<T> Zm = p[skm];
-            const cx<T> E = {(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
-            const cx<T> O = {(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
-            const cx<T> wO = cmul(c.tw2m[k], O);
-            p[sk] = E + wO;
-            if (2 * k != M) p[skm] = conj(E - wO);
-        }
-    }
-}
-
-// 4: column pass 1 (forward), columns 0..m
-template <class T>
-__host__ __device__ inline void ph4(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int a0 = c.it.a0, b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
-    const int ntask = NC * b0;
-    for (int t = tid; t < ntask; t += nth) {
-        const int col = t % NC, j0 = t / NC;
-        cx<T> x[kMaxRadix];
+        const int k1b = (k1 == 0) ? 0 : am - k1;
+        cx<T> za[Bm], zb[Bm];
 #pragma unroll
-        for (int j1 = 0; j1 < kMaxRadix; ++j1) {
-            if (j1 < a0) {
-                const int row = b0 * j1 + j0;
-                x[j1] = ((unsigned)(row - c.s_off0) < (unsigned)c.s_n0) ? buf[(int64_t)row * ld + col]
-                                                                        : cx<T>{T(0), T(0)};
+        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = p[Bm * k1 + k0];
+        Dft<Bm, -1>::run(za);
+        if (k1b != k1) {
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = p[Bm * k1b + k0];
+            Dft<Bm, -1>::run(zb);
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) {
+                const int k = k1 + am * k0;
+                cx<T> Xk, Xm;
+                post_pair(za[k0], zb[Bm - 1 - k0], c.tw2m[k], Xk, Xm);
+                za[k0] = Xk;
+                zb[Bm - 1 - k0] = Xm;
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1b + k0] = zb[k0];
+        } else if (k1 == 0) {
+            // k = am k0 pairs with am (bm - k0); k0 = 0 gives X[0] and X[m]
+            const cx<T> z0 = za[0];
+#pragma unroll
+            for (int k0 = 1; 2 * k0 <= Bm; ++k0) {
+                const int k = am * k0;
+                cx<T> Xk, Xm;
+                post_pair(za[k0], za[Bm - k0], c.tw2m[k], Xk, Xm);
+                za[k0] = Xk;
+                if (2 * k0 != Bm) za[Bm - k0] = Xm;
+            }
+            za[0] = {z0.x + z0.y, T(0)};
+            p[M] = {z0.x - z0.y, T(0)};
+        } else {
+            // am even, k1 = am/2: k0 pairs with bm - 1 - k0
+#pragma unroll
+            for (int k0 = 0; 2 * k0 < Bm; ++k0) {
+                const int k = k1 + am * k0;
+                cx<T> Xk, Xm;
+                post_pair(za[k0], za[Bm - 1 - k0], c.tw2m[k], Xk, Xm);
+                za[k0] = Xk;
+                if (2 * k0 != Bm - 1) za[Bm - 1 - k0] = Xm;
             }
         }
-        dft_rt<-1>(a0, x);
 #pragma unroll
-        for (int k1 = 0; k1 < kMaxRadix; ++k1)
-            if (k1 < a0) buf[(int64_t)(b0 * k1 + j0) * ld + col] = cmul(x[k1], c.tw0[j0 * k1]);
+        for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1 + k0] = za[k0];
     }
 }
-
-// 5: column pass 2, spectral product, inverse column pass 2
 template <class T>
-__host__ __device__ inline void ph5(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int a0 = c.it.a0, b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
+__host__ __device__ inline void phB(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH_ROW2(c.it.bm, phB_r, c, buf, tid, nth);
+}
+
+// ---------------------------------------------------------------- phase C
+template <int A0, class T>
+__host__ __device__ inline void phC_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
+    const int ntask = NC * b0;
+    for (int t = tid; t < ntask; t += nth) {
+        const int j0 = fdiv(t, c.inv_nc), col = t - j0 * NC;
+        cx<T> x[A0];
+#pragma unroll
+        for (int j1 = 0; j1 < A0; ++j1) {
+            const int row = b0 * j1 + j0;
+            x[j1] = ((unsigned)(row - c.s_off0) < (unsigned)c.s_n0) ? buf[(int64_t)row * ld + col]
+                                                                    : cx<T>{T(0), T(0)};
+        }
+        Dft<A0, -1>::run(x);
+#pragma unroll
+        for (int k1 = 0; k1 < A0; ++k1) buf[(int64_t)(b0 * k1 + j0) * ld + col] = cmul(x[k1], c.tw0[j0 * k1]);
+    }
+}
+template <class T>
+__host__ __device__ inline void phC(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.a0, phC_r, c, buf, tid, nth);
+}
+
+// ---------------------------------------------------------------- phase D
+template <int B0, class T>
+__host__ __device__ inline void phD_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int a0 = c.it.a0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * a0;
     for (int t = tid; t < ntask; t += nth) {
-        const int col = t % NC, k1 = t / NC;
-        cx<T>* p = buf + (int64_t)(b0 * k1) * ld + col;
-        const cx<T>* sp = c.spec + (int64_t)(b0 * k1) * NC + col;
-        cx<T> x[kMaxRadix];
+        const int k1 = fdiv(t, c.inv_nc), col = t - k1 * NC;
+        cx<T>* p = buf + (int64_t)(B0 * k1) * ld + col;
+        const cx<T>* sp = c.spec + (int64_t)(B0 * k1) * NC + col;
+        cx<T> s[B0], x[B0];
 #pragma unroll
-        for (int k0 = 0; k0 < kMaxRadix; ++k0)
-            if (k0 < b0) x[k0] = p[(int64_t)k0 * ld];
-        dft_rt<-1>(b0, x);
+        for (int k0 = 0; k0 < B0; ++k0) s[k0] = sp[(int64_t)k0 * NC];
 #pragma unroll
-        for (int k0 = 0; k0 < kMaxRadix; ++k0) {
-            if (k0 < b0) {
-                const cx<T> s = sp[(int64_t)k0 * NC];
-                x[k0] = c.adj ? cmulc(x[k0], s) : cmul(x[k0], s);
-            }
-        }
-        dft_rt<1>(b0, x);
+        for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
+        Dft<B0, -1>::run(x);
 #pragma unroll
-        for (int k0 = 0; k0 < kMaxRadix; ++k0)
-            if (k0 < b0) p[(int64_t)k0 * ld] = x[k0];
+        for (int k0 = 0; k0 < B0; ++k0) x[k0] = c.adj ? cmulc(x[k0], s[k0]) : cmul(x[k0], s[k0]);
+        Dft<B0, 1>::run(x);
+#pragma unroll
+        for (int k0 = 0; k0 < B0; ++k0) p[(int64_t)k0 * ld] = x[k0];
     }
 }
-
-// 6: inverse column pass 1; keeps the rows of the written box
 template <class T>
-__host__ __device__ inline void ph6(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int a0 = c.it.a0, b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
+__host__ __device__ inline void phD(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.b0, phD_r, c, buf, tid, nth);
+}
+
+// ---------------------------------------------------------------- phase E
+template <int A0, class T>
+__host__ __device__ inline void phE_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * b0;
     for (int t = tid; t < ntask; t += nth) {
-        const int col = t % NC, j0 = t / NC;
-        cx<T> x[kMaxRadix];
+        const int j0 = fdiv(t, c.inv_nc), col = t - j0 * NC;
+        cx<T> x[A0];
 #pragma unroll
-        for (int k1 = 0; k1 < kMaxRadix; ++k1)
-            if (k1 < a0) x[k1] = cmulc(buf[(int64_t)(b0 * k1 + j0) * ld + col], c.tw0[j0 * k1]);
-        dft_rt<1>(a0, x);
+        for (int k1 = 0; k1 < A0; ++k1) x[k1] = cmulc(buf[(int64_t)(b0 * k1 + j0) * ld + col], c.tw0[j0 * k1]);
+        Dft<A0, 1>::run(x);
 #pragma unroll
-        for (int j1 = 0; j1 < kMaxRadix; ++j1) {
-            if (j1 < a0) {
-                const int row = b0 * j1 + j0;
-                if ((unsigned)(row - c.d_off0) < (unsigned)c.d_n0) buf[(int64_t)row * ld + col] = x[j1];
-            }
+        for (int j1 = 0; j1 < A0; ++j1) {
+            const int row = b0 * j1 + j0;
+            if ((unsigned)(row - c.d_off0) < (unsigned)c.d_n0) buf[(int64_t)row * ld + col] = x[j1];
         }
     }
 }
-
-// 7: X (k in [0, m]) -> Z = DFT_m(y_even + i y_odd), thread-private in place
 template <class T>
-__host__ __device__ inline void ph7(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int M = c.it.m, am = c.it.am, bm = c.it.bm, ld = c.it.ld;
-    const int H = M / 2 + 1;
-    const int ntask = c.d_n0 * H;
-    const T half = T(0.5);
-    for (int t = tid; t < ntask; t += nth) {
-        const int r = t % c.d_n0, k = t / c.d_n0;
-        cx<T>* p = buf + (int64_t)(c.d_off0 + r) * ld;
-        const int sk = slot_of(k, am, bm);
-        const int skm = (k == 0) ? M : slot_of(M - k, am, bm);
-        const cx<T> Xk = p[sk], Xm = p[skm];
-        const cx<T> E = {(Xk.x + Xm.x) * half, (Xk.y - Xm.y) * half};
-        const cx<T> D = {(Xk.x - Xm.x) * half, (Xk.y + Xm.y) * half};
-        const cx<T> O = cmulc(D, c.tw2m[k]);
-        p[sk] = {E.x - O.y, E.y + O.x};
-        if (k != 0 && 2 * k != M) p[skm] = {E.x + O.y, O.x - E.y};
-    }
+__host__ __device__ inline void phE(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.a0, phE_r, c, buf, tid, nth);
 }
 
-// 9: inverse row pass 1 + write of the output box
+// ---------------------------------------------------------------- phase F
+// Mirror of phase B on the written rows: pre-processing of the frequency
+// pairs, then the inverse DFT_bm of groups k1 and k1b.
+template <int Bm, class T>
+__host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int am = c.it.am, ld = c.it.ld, M = c.it.m;
+    const int H = am / 2 + 1;
+    const int ntask = c.d_n0 * H;
+    for (int t = tid; t < ntask; t += nth) {
+        const int k1 = fdiv(t, c.inv_dn0), r = t - k1 * c.d_n0;
+        cx<T>* p = buf + (int64_t)(c.d_off0 + r) * ld;
+        const int k1b = (k1 == 0) ? 0 : am - k1;
+        cx<T> za[Bm], zb[Bm];
+#pragma unroll
+        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = p[Bm * k1 + k0];
+        if (k1b != k1) {
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = p[Bm * k1b + k0];
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) {
+                const int k = k1 + am * k0;
+                cx<T> Zk, Zm;
+                pre_pair(za[k0], zb[Bm - 1 - k0], c.tw2m[k], Zk, Zm);
+                za[k0] = Zk;
+                zb[Bm - 1 - k0] = Zm;
+            }
+            Dft<Bm, 1>::run(zb);
+#pragma unroll
+            for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1b + k0] = zb[k0];
+        } else if (k1 == 0) {
+            const cx<T> X0 = za[0], XM = p[M];
+#pragma unroll
+            for (int k0 = 1; 2 * k0 <= Bm; ++k0) {
+                const int k = am * k0;
+                cx<T> Zk, Zm;
+                pre_pair(za[k0], za[Bm - k0], c.tw2m[k], Zk, Zm);
+                za[k0] = Zk;
+                if (2 * k0 != Bm) za[Bm - k0] = Zm;
+            }
+            cx<T> Z0, Zunused;
+            pre_pair(X0, XM, cx<T>{T(1), T(0)}, Z0, Zunused);
+            za[0] = Z0;
+        } else {
+#pragma unroll
+            for (int k0 = 0; 2 * k0 < Bm; ++k0) {
+                const int k = k1 + am * k0;
+                cx<T> Zk, Zm;
+                pre_pair(za[k0], za[Bm - 1 - k0], c.tw2m[k], Zk, Zm);
+                za[k0] = Zk;
+                if (2 * k0 != Bm - 1) za[Bm - 1 - k0] = Zm;
+            }
+        }
+        Dft<Bm, 1>::run(za);
+#pragma unroll
+        for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1 + k0] = za[k0];
+    }
+}
 template <class T>
-__host__ __device__ inline void ph9(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int am = c.it.am, bm = c.it.bm, ld = c.it.ld;
+__host__ __device__ inline void phF(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH_ROW2(c.it.bm, phF_r, c, buf, tid, nth);
+}
+
+// ---------------------------------------------------------------- phase G
+// Inverse row pass 1, in place: the thread that reads slots bm k1 + j0 writes
+// z[bm j1 + j0] back to the same slots, so each LDS row ends in natural order
+// and, read as reals, is the real output row.
+template <int A, class T>
+__host__ __device__ inline void phG_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int bm = c.it.bm, ld = c.it.ld;
     const int ntask = c.d_n0 * bm;
     for (int t = tid; t < ntask; t += nth) {
-        const int j0 = t % bm, q = t / bm;
-        const int row = c.d_off0 + q;
-        const cx<T>* in = buf + (int64_t)row * ld + j0;
-        cx<T> x[kMaxRadix];
+        const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
+        cx<T>* p = buf + (int64_t)(c.d_off0 + q) * ld + j0;
+        cx<T> x[A];
 #pragma unroll
-        for (int k1 = 0; k1 < kMaxRadix; ++k1)
-            if (k1 < am) x[k1] = cmulc(in[bm * k1], c.twm[j0 * k1]);
-        dft_rt<1>(am, x);
-        T* drow = c.dst + (int64_t)q * c.d_n1;
-        const T* wrow = c.w + (int64_t)q * c.d_n1;
+        for (int k1 = 0; k1 < A; ++k1) x[k1] = cmulc(p[bm * k1], c.twm[j0 * k1]);
+        Dft<A, 1>::run(x);
 #pragma unroll
-        for (int j1 = 0; j1 < kMaxRadix; ++j1) {
-            if (j1 < am) {
-                const int j = bm * j1 + j0;
-                const int e0 = 2 * j - c.d_off1, e1 = e0 + 1;
-                if ((unsigned)e0 < (unsigned)c.d_n1) drow[e0] = c.adj ? x[j1].x * wrow[e0] : x[j1].x;
-                if ((unsigned)e1 < (unsigned)c.d_n1) drow[e1] = c.adj ? x[j1].y * wrow[e1] : x[j1].y;
-            }
-        }
+        for (int j1 = 0; j1 < A; ++j1) p[bm * j1] = x[j1];
+    }
+}
+template <class T>
+__host__ __device__ inline void phG(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.am, phG_r, c, buf, tid, nth);
+}
+
+// ---------------------------------------------------------------- phase H
+// Copy of the written box from LDS to the staging buffer, consecutive lanes on
+// consecutive columns (weighted for the adjoint).
+template <class T>
+__host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    const int n1 = c.d_n1, ntask = c.d_n0 * n1;
+    const float inv = 1.0f / (float)n1;
+    const T* rows = reinterpret_cast<const T*>(buf);
+    for (int t = tid; t < ntask; t += nth) {
+        const int q = fdiv(t, inv), e = t - q * n1;
+        T v = rows[(int64_t)(c.d_off0 + q) * (2 * c.it.ld) + c.d_off1 + e];
+        if (c.adj) v *= c.w[t];
+        c.dst[t] = v;
     }
 }
 

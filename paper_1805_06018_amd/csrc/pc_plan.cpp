@@ -547,6 +547,10 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         int a0, b0, am, bm;
         fft_factor(n0, &a0, &b0);
         fft_factor(M, &am, &bm);
+        if (M > 128 || bm > 10) {
+            err = "patch " + std::to_string(k) + " needs a row FFT outside the supported lengths";
+            return PC_ERR_UNSUPPORTED;
+        }
         const int n1 = 2 * M;
         // spectrum of phi_k^E placed circularly, FP64, half spectrum along axis 1
         const int64_t spec_off = (int64_t)(p.spec.size() / 2);
