@@ -29,6 +29,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device copy of the 256 MiB input (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -80,6 +83,12 @@ def main():
     flops_launch = st["alg_flops_per_rhs"] * vec_per_launch
     achieved = flops_launch / conv_avg_s
     alg_bytes_step = 8.0 * w.N * B + 4.0 * st["kernel_elems"]
+
+    if args.copy_probe:
+        probe = torch.empty_like(U)
+        probe.copy_(U)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {U.numel() * 4} bytes read and written", file=sys.stderr, flush=True)
 
     # plain per-patch / per-vector apply (same kernels, one launch each)
     plain_ms = None

@@ -3,9 +3,9 @@
  * The library applies the adaptive product-convolution approximation of
  * Alger, Rao, Myers, Bui-Thanh and Ghattas (arXiv 1805.06018),
  *
- *     A~ u = sum_k phi_k^E * (w_k . u)                    (eq. 2.3)
+ *     A~ u = sum_k phi_k^E * (w_k . u)                    (eq. (2.5))
  *
- * and its adjoint (eq. 1.4) to batches of vectors on one AMD Instinct
+ * and its adjoint (eq. (1.6)) to batches of vectors on one AMD Instinct
  * MI355X (gfx950), and drives the randomized a-posteriori error estimator
  * (Sec. 2.6) on top of the adjoint.
  *
@@ -69,7 +69,7 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *  radius[r][d]         : phi_k is supplied on the box prod_i [-R_ki, R_ki]
  *                         (R >= 0, else PC_ERR_ARG).
  *  phi, phi_off[r+1]    : the impulse responses phi_k[z] = (A delta_{p_k})[z+p_k]
- *                         (eq. 2.4), concatenated: patch k occupies
+ *                         (eq. (2.6)), concatenated: patch k occupies
  *                         phi[phi_off[k] .. phi_off[k+1]) = prod (2R_ki+1)
  *                         doubles, row-major with offset z = -R first.
  *                         Entries with p_k + z outside Omega are ignored;
@@ -89,17 +89,17 @@ pc_status pc_create(int d, const int64_t* shape,
                     const double* phi, const int64_t* phi_off,
                     pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out);
 
-/* pc_apply -- out = A~ u for one vector (eq. 2.3).  u, out: device, N
+/* pc_apply -- out = A~ u for one vector (eq. (2.5)).  u, out: device, N
  * elements of the operator's dtype; out must not alias u. */
 pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s);
 
-/* pc_apply_batch -- OUT[:, j] = A~ U[:, j] for j < B (eq. 2.3), all vectors
+/* pc_apply_batch -- OUT[:, j] = A~ U[:, j] for j < B (eq. (2.5)), all vectors
  * in one fused launch sequence.  U and OUT are device arrays with leading
  * dimensions ldu, ldo >= N; B >= 0 (B = 0 is a no-op). */
 pc_status pc_apply_batch(pc_op* op, int64_t B, const void* U, int64_t ldu,
                          void* OUT, int64_t ldo, hipStream_t s);
 
-/* pc_apply_adjoint_batch -- OUT[:, j] = A~* V[:, j] (eq. 1.4: the same
+/* pc_apply_adjoint_batch -- OUT[:, j] = A~* V[:, j] (eq. (1.6): the same
  * patches in reverse order, convolution with the flipped kernel first, then
  * the weight). */
 pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ldv,
@@ -117,7 +117,7 @@ pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu,
 typedef int (*pc_matvec_fn)(void* user, int64_t B, const void* in, int64_t ldin,
                             void* out, int64_t ldout, hipStream_t s);
 
-/* pc_error_estimate -- randomized estimator of Sec. 2.6 (eq. 2.10).
+/* pc_error_estimate -- randomized estimator of Sec. 2.6 (eq. (2.11)).
  *  Z [q][ldz]         : probe vectors (device).
  *  Y_or_null [q][ldy] : Y = A* Z if the caller has it (computed once and
  *                       reused, Sec. 2.8); if NULL the library calls

@@ -11,7 +11,7 @@ Modules
   grid       sample points, cells(p), blocky neighbourhoods U_k, nbrs(k)  (Sec. 2.2)
   weights    harmonic partition-of-unity weights w_k                     (Sec. 2.4)
   extension  extended impulse responses phi_k^E                          (Sec. 2.5)
-  apply      A~ f = sum_k phi_k^E * (w_k . f), its adjoint, matrix entries (eq. 2.3/1.4, Sec. 3)
+  apply      A~ f = sum_k phi_k^E * (w_k . f), its adjoint, matrix entries (eq. (2.5)/(1.6), Sec. 3)
   estimator  randomized a-posteriori estimator eta_C                     (Sec. 2.6)
   direct     ctypes wrapper of a plain C direct-summation core (same sums,
              used where NumPy loops are too slow)

@@ -1,7 +1,7 @@
 """The product-convolution operator and its adjoint, by direct summation.
 
-Forward (eq. 2.3):  (A~ f)[y] = sum_k sum_{x in U_k} w_k[x] f[x] phi_k^E[y - x],  y in Omega.
-Adjoint (eq. 1.4):  (A~* g)[x] = sum_k w_k[x] sum_{y in Omega} phi_k^E[y - x] g[y].
+Forward (eq. (2.5)):  (A~ f)[y] = sum_k sum_{x in U_k} w_k[x] f[x] phi_k^E[y - x],  y in Omega.
+Adjoint (eq. (1.6)):  (A~* g)[x] = sum_k w_k[x] sum_{y in Omega} phi_k^E[y - x] g[y].
 Matrix entries (Sec. 3.1): A~[y, x] = sum_{k : x in U_k} w_k[x] phi_k^E[y - x].
 
 Everything is FP64 and summed over k in ascending order.  The per-patch

@@ -1,7 +1,7 @@
 /* Oracle direct-summation core (TEST INFRASTRUCTURE ONLY).
  *
- * Plain FP64 loops for one patch of the product-convolution sum (eq. 2.3)
- * and of its adjoint (eq. 1.4).  Arrays are row-major boxes in up to three
+ * Plain FP64 loops for one patch of the product-convolution sum (eq. (2.5))
+ * and of its adjoint (eq. (1.6)).  Arrays are row-major boxes in up to three
  * dimensions; unused trailing axes have extent 1.  No FFT, no blocking: every
  * output is the straight sum over the kernel offsets in ascending row-major
  * order.  OpenMP splits the independent output points across threads.

@@ -5,7 +5,7 @@ With probe vectors Z (q columns), Y = A* Z (exact adjoint) and Y~ = A~* Z:
               (C's own point set: points on shared facets count in each cell);
   eta_Omega = q^{-1/2} || Y~ - Y ||_F           (every grid point once);
   eta_rel   = || Y~ - Y ||_F / || Y ||_F.
-The sample-average identity ||M||_F^2 = E ||M zeta||^2 (eq. 2.9) makes
+The sample-average identity ||M||_F^2 = E ||M zeta||^2 (eq. (2.10)) makes
 eta_C^2 an unbiased estimate of e_C^2 = ||(A~ - A)[Omega, C]||_F^2.
 """
 import numpy as np

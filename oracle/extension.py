@@ -6,7 +6,7 @@ that box it is zero (the blur is truncated there).
 
 With the counting function c_k = 1_{Omega-p_k} + sum_{j in nbrs(k), j != k}
 1_{(Omega-p_j) \\ (Omega-p_k)}, v_k = 1/c_k on supp(c_k), and the split
-weights v_k^(j) (eq. for v_k^(j)), the extension is
+weights v_k^(j) (eq. (2.7)), the extension is
 phi_k^E = sum_{j in nbrs(k)} v_k^(j) . phi_j: phi_k itself where defined, the
 plain average of the neighbours defined there elsewhere, 0 where none is.
 
@@ -88,7 +88,7 @@ def extended_kernels(grid, radius, phi, phi_off, extend=True):
 
 
 def split_weights(grid, k, zlo, zshape):
-    """v_k^(j) for j in nbrs(k) on an offset box (eq. for v_k^(j)); used by the
+    """v_k^(j) for j in nbrs(k) on an offset box (eq. (2.7)); used by the
     tests of Lemma 2 and Prop. 1."""
     shape = grid.shape
     own = _defined_mask(shape, grid.points[k], zlo, zshape)

@@ -1,5 +1,5 @@
 // The phases of one convolution work item (a patch or row piece of the
-// product-convolution sum, eq. 2.3, or of its adjoint, eq. 1.4).
+// product-convolution sum, eq. (2.5), or of its adjoint, eq. (1.6)).
 //
 // Work item layout: an n0 x n1 FFT box (n1 = 2m) lives in LDS as n0 rows of
 // m + 1 complex columns (row stride ld).  Each real row of length 2m is

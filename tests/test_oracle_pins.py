@@ -177,7 +177,7 @@ def test_prop1_product_partition_of_unity():
     assert np.abs(S - 1.0).max() < 1e-14
 
 
-# ---------------------------------------------------------------- apply (eq. 2.3)
+# ---------------------------------------------------------------- apply (eq. (2.5))
 @pytest.mark.parametrize("case", ["1d", "2d_uniform", "2d_hanging", "3d"])
 def test_exact_for_convolutions(case):
     """Thm. 1 with F = 0: a restricted convolution is reproduced exactly by any
@@ -259,7 +259,7 @@ def _varying_case(n=11):
 
 def test_dense_entries_and_adjoint_consistency():
     """Matrix entries (Sec. 3.1) times f equal the convolution sum; the adjoint
-    apply equals the transpose (eq. 1.4)."""
+    apply equals the transpose (eq. (1.6))."""
     w = _varying_case()
     op = OracleOperator.from_workload(w)
     A = op.dense()
@@ -357,7 +357,7 @@ def test_estimator_matches_dense_computation():
 
 
 def test_estimator_is_unbiased_for_cell_errors():
-    """eq. 2.9: eta_C^2 -> e_C^2 = ||(A~ - A)[Omega, C]||_F^2 as q grows."""
+    """eq. (2.10): eta_C^2 -> e_C^2 = ||(A~ - A)[Omega, C]||_F^2 as q grows."""
     w = _varying_case(9)
     op = OracleOperator.from_workload(w)
     A, At = w.op.dense(), op.dense()

@@ -7,7 +7,7 @@ Z(x) = sum over the full box |xi_i| <= R_i(x) of exp(-sum_i xi_i^2 / (2 s_i(x)^2
 independent of the domain, so that a constant s gives an exact convolution
 restricted to the domain.
 
-The impulse response at p (Sec. 2.1, eq. for phi_p) is phi_p[z] = A[p+z, p]:
+The impulse response at p (eq. (1.2), (2.6)) is phi_p[z] = A[p+z, p]:
 it is handed to the library on the full box |z_i| <= R_i(p); entries with
 p + z outside the domain are ignored by the consumer.
 """
