@@ -169,6 +169,14 @@ typedef struct {
 } pc_profile;
 
 pc_status   pc_set_profiling(pc_op* op, int enable);
+
+/* Schedule knobs (defaults chosen by the library; an autotuner may override).
+ *  PC_TUNE_CHUNK    vectors per convolution launch (0 = library default)
+ *  PC_TUNE_OVERLAP  1: reduce chunk i on a library stream while chunk i+1
+ *                   convolves; 0: everything on the caller's stream
+ * Results are bitwise identical for every setting. */
+enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2 };
+pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 size_t      pc_device_bytes(const pc_op* op);
 pc_status   pc_destroy(pc_op* op);

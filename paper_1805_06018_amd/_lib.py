@@ -55,6 +55,9 @@ _lib.pc_get_stats.argtypes = [_P, ctypes.POINTER(PcStats)]
 _lib.pc_get_stats.restype = ctypes.c_int
 _lib.pc_set_profiling.argtypes = [_P, ctypes.c_int]
 _lib.pc_set_profiling.restype = ctypes.c_int
+_lib.pc_set_tuning.argtypes = [_P, ctypes.c_int, _I64]
+_lib.pc_set_tuning.restype = ctypes.c_int
+PC_TUNE_CHUNK, PC_TUNE_OVERLAP = 1, 2
 _lib.pc_read_profile.argtypes = [_P, ctypes.POINTER(PcProfile)]
 _lib.pc_read_profile.restype = ctypes.c_int
 _lib.pc_device_bytes.argtypes = [_P]
@@ -67,7 +70,7 @@ _lib.pc_last_error.argtypes = []
 _lib.pc_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["pc_create", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain",
-            "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_read_profile", "pc_device_bytes",
+            "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
 
 
@@ -185,6 +188,9 @@ class PcOperator:
 
     def set_profiling(self, enable=True):
         _check(_lib.pc_set_profiling(self._h, int(bool(enable))))
+
+    def set_tuning(self, key, value):
+        _check(_lib.pc_set_tuning(self._h, int(key), int(value)))
 
     def read_profile(self):
         pr = PcProfile()

@@ -6,6 +6,7 @@
 // the barrier, on exact-size host buffers so that an address sanitizer build
 // reports any out-of-range index.  It checks the kernels' indexing on the CPU
 // before they run on a GPU.
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,13 +25,14 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
     std::vector<T> wts(P.wts.begin(), P.wts.end());
     std::vector<T> tw(P.tw.begin(), P.tw.end());
     const int64_t per = adj ? P.slot_adj : P.slot_fwd;
+    std::vector<T> in((size_t)(B * N));
+    for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * N)], U + b * ldu, sizeof(T) * (size_t)N);
+    std::vector<T> slots((size_t)(B * per), T(0));
     for (int64_t b = 0; b < B; ++b) {
-        std::vector<T> in(U + b * ldu, U + b * ldu + N);
-        std::vector<T> slots((size_t)per, T(0));
         for (const pc::Item& it : P.items) {
             std::vector<C> buf((size_t)it.n0 * it.ld);
             for (auto& v : buf) v = C{T(1e30), T(1e30)};   // poison: unwritten reads show up
-            pc::Ctx<T> c = pc::make_ctx<T>(it, adj, in.data(), slots.data(), wts.data(),
+            pc::Ctx<T> c = pc::make_ctx<T>(it, adj, &in[(size_t)(b * N)], &slots[(size_t)(b * per)], wts.data(),
                                            reinterpret_cast<const C*>(spec.data()),
                                            reinterpret_cast<const C*>(tw.data()), P.cols);
             const int nth = pc::threads_for<T>();
@@ -43,15 +45,15 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
             for (int t = 0; t < nth; ++t) pc::phG(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phH(c, buf.data(), t, nth);
         }
-        std::vector<T> out((size_t)N, T(0));
-        const auto& tiles = adj ? P.tiles_adj : P.tiles_fwd;
-        const auto& contrib = adj ? P.contrib_adj : P.contrib_fwd;
-        const auto& boxes = adj ? P.boxes_adj : P.boxes_fwd;
+    }
+    std::vector<T> out((size_t)(B * N), T(0));
+    const auto& tiles = adj ? P.tiles_adj : P.tiles_fwd;
+    const auto& cboxes = adj ? P.cboxes_adj : P.cboxes_fwd;
+    for (int64_t b = 0; b < B; ++b)
         for (const pc::Tile& t : tiles)
             for (int col = 0; col < pc::kReduceCols; ++col)
-                pc::reduce_tile<T>(t, col, contrib.data(), boxes.data(), slots.data(), out.data(), P.cols);
-        std::memcpy(OUT + b * ldo, out.data(), sizeof(T) * (size_t)N);
-    }
+                pc::reduce_tile<T>(t, col, cboxes.data(), &slots[(size_t)(b * per)], &out[(size_t)(b * N)], P.cols);
+    for (int64_t b = 0; b < B; ++b) std::memcpy(OUT + b * ldo, &out[(size_t)(b * N)], sizeof(T) * (size_t)N);
 }
 }  // namespace
 

@@ -1,6 +1,7 @@
 // C ABI of the product-convolution library (declared in include/pc.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,8 +27,10 @@ pc_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? PC_ERR_OOM : PC_ERR_DEVICE;
 }
 
-// Staging buffers larger than this are split into vector chunks.
+// The staging buffer holds at most this many bytes (split in two halves when
+// the reduction of one vector chunk overlaps the next chunk's convolution).
 constexpr size_t kSlotCapBytes = size_t(2) << 30;
+constexpr int64_t kMinChunks = 4;
 
 }  // namespace
 
@@ -38,8 +41,13 @@ struct pc_op {
     size_t esz = 4;
     std::vector<void*> allocs;
     size_t resident = 0;
-    void* slots = nullptr;
+    void* slots = nullptr;        // two staging buffers of slots_bytes / 2 each
     size_t slots_bytes = 0;
+    int64_t tune_chunk = 0;       // 0: default chunking
+    bool tune_overlap = false;    // reduce on the aux stream while the next chunk convolves
+    hipStream_t aux = nullptr;    // reductions overlap the next chunk's convolution here
+    hipEvent_t ev_conv[2] = {nullptr, nullptr};
+    hipEvent_t ev_red[2] = {nullptr, nullptr};
     void* work = nullptr;     // estimator: Y~ and (if needed) Y
     size_t work_bytes = 0;
     double* est = nullptr;    // estimator sums
@@ -56,6 +64,11 @@ struct pc_op {
     std::vector<hipEvent_t> event_pool;
 
     ~pc_op() {
+        for (int i = 0; i < 2; ++i) {
+            if (ev_conv[i]) hipEventDestroy(ev_conv[i]);
+            if (ev_red[i]) hipEventDestroy(ev_red[i]);
+        }
+        if (aux) hipStreamDestroy(aux);
         for (auto& t : timed) {
             hipEventDestroy(t.a);
             hipEventDestroy(t.b);
@@ -139,6 +152,18 @@ pc_status check_op(const pc_op* op) {
     return PC_OK;
 }
 
+pc_status ensure_aux(pc_op* op) {
+    if (op->aux) return PC_OK;
+    hipError_t e = hipStreamCreateWithFlags(&op->aux, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    for (int i = 0; i < 2; ++i) {
+        e = hipEventCreateWithFlags(&op->ev_conv[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_red[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    return PC_OK;
+}
+
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
                     hipStream_t s) {
     pc_status st = check_op(op);
@@ -150,37 +175,69 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     if (ldu < N || ldo < N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
     const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
-    const size_t per_bytes = (size_t)per * op->esz;
-    int64_t chunk = plain ? 1 : (int64_t)std::max<size_t>(1, kSlotCapBytes / std::max<size_t>(per_bytes, 1));
-    if (chunk > B) chunk = B;
-    st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
+    int64_t chunk = 1;
+    if (!plain) {
+        const size_t cap_bytes = op->tune_overlap ? kSlotCapBytes / 2 : kSlotCapBytes;
+        const int64_t cap = (int64_t)std::max<size_t>(1, cap_bytes / per_bytes);
+        const int64_t want = op->tune_chunk > 0 ? op->tune_chunk
+                             : (op->tune_overlap ? (B + kMinChunks - 1) / kMinChunks : B);
+        chunk = std::min<int64_t>(cap, std::max<int64_t>(1, want));
+    }
+    const int64_t nchunks = (B + chunk - 1) / chunk;
+    const bool overlap = !plain && op->tune_overlap && nchunks > 1;
+    const size_t buf_bytes = (size_t)chunk * per_bytes;
+    st = ensure(&op->slots, &op->slots_bytes, (overlap ? 2 : 1) * buf_bytes, "hipMalloc (staging)");
     if (st != PC_OK) return st;
+    if (overlap && (st = ensure_aux(op)) != PC_OK) return st;
     const char* u = static_cast<const char*>(U);
     char* o = static_cast<char*>(OUT);
     const int n_items = (int)op->plan.items.size();
-    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int64_t b0 = c * chunk;
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        const int pb = overlap ? (int)(c & 1) : 0;
+        void* slots = static_cast<char*>(op->slots) + (size_t)pb * buf_bytes;
         const void* in = u + (size_t)b0 * ldu * op->esz;
         void* out = o + (size_t)b0 * ldo * op->esz;
         hipError_t e;
         hipEvent_t ev;
+        if (overlap && c >= 2) {   // the reduction two chunks back still reads this buffer
+            e = hipStreamWaitEvent(s, op->ev_red[pb], 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        }
         if (plain) {
             for (int it = 0; it < n_items; ++it) {
                 prof_begin(op, s, &ev);
-                e = pc::launch_conv(op->dev, adj, it, it + 1, 1, in, ldu, op->slots, per, s);
+                e = pc::launch_conv(op->dev, adj, it, it + 1, 1, in, ldu, slots, per, s);
                 if (e != hipSuccess) return hip_fail(e, "conv launch");
                 prof_end(op, s, ev, 0, 1);
             }
         } else {
             prof_begin(op, s, &ev);
-            e = pc::launch_conv(op->dev, adj, 0, n_items, nb, in, ldu, op->slots, per, s);
+            e = pc::launch_conv(op->dev, adj, 0, n_items, nb, in, ldu, slots, per, s);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
             prof_end(op, s, ev, 0, nb);
         }
-        prof_begin(op, s, &ev);
-        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s);
+        hipStream_t rs = s;
+        if (overlap) {
+            e = hipEventRecord(op->ev_conv[pb], s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(op->aux, op->ev_conv[pb], 0);
+            if (e != hipSuccess) return hip_fail(e, "event chaining");
+            rs = op->aux;
+        }
+        prof_begin(op, rs, &ev);
+        e = pc::launch_reduce(op->dev, adj, nb, slots, per, out, ldo, rs);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
-        prof_end(op, s, ev, 1, nb);
+        prof_end(op, rs, ev, 1, nb);
+        if (overlap) {
+            e = hipEventRecord(op->ev_red[pb], op->aux);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+    }
+    if (overlap) {   // the caller's stream sees the last reduction (the aux stream is in order)
+        hipError_t e = hipStreamWaitEvent(s, op->ev_red[(nchunks - 1) & 1], 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     return PC_OK;
 }
@@ -236,12 +293,11 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
     }
     op->esz = (dtype == PC_F64) ? 8 : 4;
     pc::Plan& P = op->plan;
-    void *d_items, *d_spec, *d_wts, *d_tw, *d_tf, *d_ta, *d_cf, *d_ca, *d_bf, *d_ba;
+    void *d_items, *d_spec, *d_wts, *d_tw, *d_tf, *d_ta, *d_bf, *d_ba;
     if ((st = upload(op, P.items, &d_items)) != PC_OK || (st = upload_real(op, P.spec, &d_spec)) != PC_OK ||
         (st = upload_real(op, P.wts, &d_wts)) != PC_OK || (st = upload_real(op, P.tw, &d_tw)) != PC_OK ||
         (st = upload(op, P.tiles_fwd, &d_tf)) != PC_OK || (st = upload(op, P.tiles_adj, &d_ta)) != PC_OK ||
-        (st = upload(op, P.contrib_fwd, &d_cf)) != PC_OK || (st = upload(op, P.contrib_adj, &d_ca)) != PC_OK ||
-        (st = upload(op, P.boxes_fwd, &d_bf)) != PC_OK || (st = upload(op, P.boxes_adj, &d_ba)) != PC_OK) {
+        (st = upload(op, P.cboxes_fwd, &d_bf)) != PC_OK || (st = upload(op, P.cboxes_adj, &d_ba)) != PC_OK) {
         delete op;
         return st;
     }
@@ -262,10 +318,8 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
     D.tiles_adj = static_cast<const pc::Tile*>(d_ta);
     D.n_tiles_fwd = (int)P.tiles_fwd.size();
     D.n_tiles_adj = (int)P.tiles_adj.size();
-    D.contrib_fwd = static_cast<const int32_t*>(d_cf);
-    D.contrib_adj = static_cast<const int32_t*>(d_ca);
-    D.boxes_fwd = static_cast<const pc::Box*>(d_bf);
-    D.boxes_adj = static_cast<const pc::Box*>(d_ba);
+    D.cboxes_fwd = static_cast<const pc::Box*>(d_bf);
+    D.cboxes_adj = static_cast<const pc::Box*>(d_ba);
     D.slot_fwd = P.slot_fwd;
     D.slot_adj = P.slot_adj;
     D.max_lds = P.max_lds;
@@ -388,6 +442,21 @@ pc_status pc_set_profiling(pc_op* op, int enable) {
     if (!op) return fail(PC_ERR_ARG, "null operator");
     op->profiling = enable != 0;
     return PC_OK;
+}
+
+pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
+    if (!op) return fail(PC_ERR_ARG, "null operator");
+    switch (key) {
+        case PC_TUNE_CHUNK:
+            if (value < 0 || value > 0x7fff) return fail(PC_ERR_ARG, "chunk out of range");
+            op->tune_chunk = value;
+            return PC_OK;
+        case PC_TUNE_OVERLAP:
+            op->tune_overlap = value != 0;
+            return PC_OK;
+        default:
+            return fail(PC_ERR_ARG, "unknown tuning key");
+    }
 }
 
 pc_status pc_read_profile(pc_op* op, pc_profile* out) {

@@ -16,10 +16,8 @@ struct DevPlan {
     const Tile* tiles_fwd;
     const Tile* tiles_adj;
     int n_tiles_fwd, n_tiles_adj;
-    const int32_t* contrib_fwd;
-    const int32_t* contrib_adj;
-    const Box* boxes_fwd;
-    const Box* boxes_adj;
+    const Box* cboxes_fwd;          // staging box of every tile contributor
+    const Box* cboxes_adj;
     int64_t slot_fwd, slot_adj;     // staging elements per vector
     int max_lds;
     int dtype;                      // 0 = f32, 1 = f64

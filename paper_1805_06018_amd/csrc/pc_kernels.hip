@@ -56,12 +56,11 @@ __global__ __launch_bounds__(threads_for<T>()) void conv_kernel(ConvArgs<T> A) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kReduceCols) void reduce_kernel(const Tile* tiles, const int32_t* contrib, const Box* boxes,
-                                                             const T* slots, int64_t slot_stride, T* out, int64_t ldo,
-                                                             int64_t pitch) {
+__global__ __launch_bounds__(kReduceCols) void reduce_kernel(const Tile* tiles, const Box* cboxes, const T* slots,
+                                                             int64_t slot_stride, T* out, int64_t ldo, int64_t pitch) {
     const Tile t = tiles[blockIdx.x];
     const int rhs = blockIdx.y;
-    reduce_tile<T>(t, threadIdx.x, contrib, boxes, slots + (int64_t)rhs * slot_stride, out + (int64_t)rhs * ldo, pitch);
+    reduce_tile<T>(t, threadIdx.x, cboxes, slots + (int64_t)rhs * slot_stride, out + (int64_t)rhs * ldo, pitch);
 }
 
 // ---------------------------------------------------------------- estimator
@@ -167,15 +166,14 @@ hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slot
     const int nt = adjoint ? P.n_tiles_adj : P.n_tiles_fwd;
     if (nt <= 0 || B <= 0) return hipSuccess;
     const Tile* tiles = adjoint ? P.tiles_adj : P.tiles_fwd;
-    const int32_t* contrib = adjoint ? P.contrib_adj : P.contrib_fwd;
-    const Box* boxes = adjoint ? P.boxes_adj : P.boxes_fwd;
+    const Box* cboxes = adjoint ? P.cboxes_adj : P.cboxes_fwd;
     dim3 grid((unsigned)nt, (unsigned)B);
     if (P.dtype == 1)
-        hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kReduceCols), 0, s, tiles, contrib, boxes,
+        hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
                            static_cast<const double*>(slots), slot_stride, static_cast<double*>(out), ldo,
                            (int64_t)P.cols);
     else
-        hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kReduceCols), 0, s, tiles, contrib, boxes,
+        hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
                            static_cast<const float*>(slots), slot_stride, static_cast<float*>(out), ldo,
                            (int64_t)P.cols);
     return hipGetLastError();

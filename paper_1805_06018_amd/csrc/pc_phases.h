@@ -426,25 +426,46 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 }
 
 // Deterministic reduction of one output tile for one vector: contributors in
-// ascending item order (ascending patch index k).
+// ascending item order (ascending patch index k).  cboxes[ci] is the staging
+// box of the tile's ci-th contributor.  Contributors are taken four at a time:
+// their loads are issued together and then added in ascending order, so the
+// sum order is the same as one at a time.
 template <class T>
-__host__ __device__ inline void reduce_tile(const Tile& t, int col_in_tile, const int32_t* contrib,
-                                            const Box* boxes, const T* slots, T* out, int64_t pitch) {
+__host__ __device__ inline void reduce_tile(const Tile& t, int col_in_tile, const Box* cboxes, const T* slots,
+                                            T* out, int64_t pitch) {
     if (col_in_tile >= t.nc) return;
     const int col = t.c0 + col_in_tile;
+    constexpr int U = 4;
     T acc[kReduceRows];
 #pragma unroll
     for (int rr = 0; rr < kReduceRows; ++rr) acc[rr] = T(0);
-    for (int ci = t.beg; ci < t.end; ++ci) {
-        const Box b = boxes[contrib[ci]];
-        const int cc = col - b.lo1;
-        if ((unsigned)cc >= (unsigned)b.n1) continue;
-        const T* s = slots + b.off + cc;
+    for (int c0 = t.beg; c0 < t.end; c0 += U) {
+        T x[U][kReduceRows];
 #pragma unroll
-        for (int rr = 0; rr < kReduceRows; ++rr) {
-            const int r2 = t.r0 + rr - b.lo0;
-            if (rr < t.nr && (unsigned)r2 < (unsigned)b.n0) acc[rr] += s[(int64_t)r2 * b.n1];
+        for (int u = 0; u < U; ++u) {
+            const int ci = c0 + u;
+            Box b;
+            if (ci < t.end) {
+                b = cboxes[ci];
+            } else {
+                b.lo0 = b.lo1 = 0;
+                b.n0 = b.n1 = 0;
+                b.off = 0;
+            }
+            const int cc = col - b.lo1;
+            const bool colok = (unsigned)cc < (unsigned)b.n1;
+            const T* s = slots + b.off + cc;
+            const int r_lo = t.r0 - b.lo0;
+#pragma unroll
+            for (int rr = 0; rr < kReduceRows; ++rr) {
+                const int r2 = r_lo + rr;
+                x[u][rr] = (colok && (unsigned)r2 < (unsigned)b.n0) ? s[(int64_t)r2 * b.n1] : T(0);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int rr = 0; rr < kReduceRows; ++rr) acc[rr] += x[u][rr];
     }
 #pragma unroll
     for (int rr = 0; rr < kReduceRows; ++rr)

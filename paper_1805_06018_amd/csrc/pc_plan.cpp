@@ -673,6 +673,11 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     };
     build_tiles(false, p.tiles_fwd, p.contrib_fwd, p.boxes_fwd);
     build_tiles(true, p.tiles_adj, p.contrib_adj, p.boxes_adj);
+    // the reduction reads the staging box of each contributor directly
+    p.cboxes_fwd.resize(p.contrib_fwd.size());
+    for (size_t i = 0; i < p.contrib_fwd.size(); ++i) p.cboxes_fwd[i] = p.boxes_fwd[(size_t)p.contrib_fwd[i]];
+    p.cboxes_adj.resize(p.contrib_adj.size());
+    for (size_t i = 0; i < p.contrib_adj.size(); ++i) p.cboxes_adj[i] = p.boxes_adj[(size_t)p.contrib_adj[i]];
     p.leaf_box.resize(4 * L);
     for (int64_t c = 0; c < L; ++c) {
         p.leaf_box[4 * c] = (int32_t)LO[2 * c];

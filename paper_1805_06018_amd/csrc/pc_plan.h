@@ -41,7 +41,8 @@ struct Plan {
     std::vector<double> tw;          // interleaved complex twiddle tables
     std::vector<Tile> tiles_fwd, tiles_adj;
     std::vector<int32_t> contrib_fwd, contrib_adj;
-    std::vector<Box> boxes_fwd, boxes_adj;
+    std::vector<Box> boxes_fwd, boxes_adj;     // staging box of every item
+    std::vector<Box> cboxes_fwd, cboxes_adj;   // staging box of every tile contributor
     std::vector<int32_t> leaf_box;   // [L][4]: lo0, lo1, n0, n1 in the 2-D view
     int64_t slot_fwd = 0, slot_adj = 0;   // staging elements per vector
     int max_lds = 0;
