@@ -5,6 +5,7 @@
 libpc.so      hipcc, gfx950, the product library (C ABI in include/pc.h)
 libpc_emu.so  host-only build of the same kernel phases, for CPU tests
 libpc_emu_asan.so  the same with AddressSanitizer on the host code
+workloads/libblur.so  exact spatially varying blur (the black-box operator)
 """
 import os
 import subprocess
@@ -19,6 +20,8 @@ ARCH = os.environ.get("PC_OFFLOAD_ARCH", "gfx950")
 LIB = os.path.join(HERE, "libpc.so")
 EMU = os.path.join(HERE, "libpc_emu.so")
 EMU_ASAN = os.path.join(HERE, "libpc_emu_asan.so")
+BLUR_SRC = os.path.join(ROOT, "workloads", "csrc")
+BLUR = os.path.join(ROOT, "workloads", "libblur.so")
 
 COMMON = ["-std=c++17", "-fPIC", "-shared", "-I" + os.path.join(ROOT, "include")]
 # packed FP32 instructions are kept out of every device build
@@ -50,8 +53,22 @@ def build_emu(asan=False):
     return _run(cmd, EMU_ASAN if asan else EMU)
 
 
+def build_blur():
+    """The exact blur operator used as the estimator's black-box adjoint."""
+    tmp = BLUR + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared"] + DEVICE_FLAGS + [
+        "blur_direct.hip", "-o", tmp]
+    r = subprocess.run(cmd, cwd=BLUR_SRC, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("build failed: " + " ".join(cmd))
+    os.replace(tmp, BLUR)
+    return BLUR
+
+
 def build_all():
     build_lib()
+    build_blur()
     build_emu(False)
     build_emu(True)
 

@@ -30,8 +30,8 @@ struct Item {
     int32_t in_off0, in_off1, in_n0, in_n1;
     int32_t out_n0, out_n1;
     int32_t patch;       // k
-    int32_t pad_;
-    int64_t w_off;       // weight table (in_n0 x in_n1, row-major)
+    int32_t w_ld;        // row stride of the weight table (the patch's box width)
+    int64_t w_off;       // weight table (in_n0 x in_n1 block, row stride w_ld)
     int64_t spec_off;    // spectrum (n0 x (m+1), slot-permuted)
     int64_t slot_fwd;    // forward staging offset (out_n0 x out_n1)
     int64_t slot_adj;    // adjoint staging offset (in_n0 x in_n1)

@@ -134,7 +134,7 @@ __host__ __device__ inline void phA_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
         const int row = c.s_off0 + q;
         const T* srow = c.src + (int64_t)(c.it.g0 + row) * c.pitch + c.it.g1;
-        const T* wrow = c.w + (int64_t)q * c.s_n1;
+        const T* wrow = c.w + (int64_t)q * c.it.w_ld;
         cx<T> x[A];
 #pragma unroll
         for (int j1 = 0; j1 < A; ++j1) {
@@ -420,7 +420,7 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     for (int t = tid; t < ntask; t += nth) {
         const int q = fdiv(t, inv), e = t - q * n1;
         T v = rows[(int64_t)(c.d_off0 + q) * (2 * c.it.ld) + c.d_off1 + e];
-        if (c.adj) v *= c.w[t];
+        if (c.adj) v *= c.w[(int64_t)q * c.it.w_ld + e];
         c.dst[t] = v;
     }
 }

@@ -515,34 +515,45 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         }
         // choose FFT lengths and the number of row pieces
         const int64_t need1 = m[1] + K[1] - 1;
-        int M = next_fft_size((int)((need1 + 1) / 2));
-        if (M < 0) {
-            err = "patch " + std::to_string(k) + " needs a row FFT longer than 512";
-            return PC_ERR_UNSUPPORTED;
-        }
-        int ldr = M + 1;
-        if (ldr % 2 == 0) ++ldr;
-        int best_P = -1, best_n0 = 0;
+        (void)need1;
+        int M = 0, ldr = 0;
+        // smallest total work over P0 x P1 pieces (rows x columns) that fit LDS
+        int best_P0 = -1, best_P1 = -1, best_n0 = 0, best_M = 0;
         double best_cost = 1e300;
-        const int maxP = (int)std::min<int64_t>(m[0], 64);
-        for (int P = 1; P <= maxP; ++P) {
-            int64_t h = (m[0] + P - 1) / P;
-            int n0 = (d == 1) ? 1 : next_fft_size((int)(h + K[0] - 1));
-            if (n0 < 0) continue;
-            int64_t lds = (int64_t)n0 * ldr * (int64_t)csz;
-            if (lds > kLdsBytes) continue;
-            double nn = (double)n0 * 2.0 * M;
-            double cost = P * nn * std::log2(std::max(nn, 2.0));
-            if (cost < best_cost) {
-                best_cost = cost;
-                best_P = P;
-                best_n0 = n0;
+        const int maxP0 = (int)std::min<int64_t>(m[0], 64), maxP1 = (int)std::min<int64_t>(m[1], 64);
+        for (int P1 = 1; P1 <= maxP1; ++P1) {
+            const int64_t h1 = (m[1] + P1 - 1) / P1;
+            const int Mp = next_fft_size((int)((h1 + K[1] - 1 + 1) / 2));
+            if (Mp < 0 || Mp > 128) continue;
+            int ap, bp;
+            fft_factor(Mp, &ap, &bp);
+            if (bp > 10) continue;
+            int ld_p = Mp + 1;
+            if (ld_p % 2 == 0) ++ld_p;
+            for (int P0 = 1; P0 <= maxP0; ++P0) {
+                const int64_t h0 = (m[0] + P0 - 1) / P0;
+                const int n0p = (d == 1) ? 1 : next_fft_size((int)(h0 + K[0] - 1));
+                if (n0p < 0) continue;
+                if ((int64_t)n0p * ld_p * (int64_t)csz > kLdsBytes) continue;
+                const double nn = (double)n0p * 2.0 * Mp;
+                const double cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_P0 = P0;
+                    best_P1 = P1;
+                    best_n0 = n0p;
+                    best_M = Mp;
+                }
+                break;   // more row pieces only add work once the box fits
             }
         }
-        if (best_P < 0) {
+        if (best_P0 < 0) {
             err = "patch " + std::to_string(k) + " does not fit the LDS-resident FFT";
             return PC_ERR_UNSUPPORTED;
         }
+        M = best_M;
+        ldr = M + 1;
+        if (ldr % 2 == 0) ++ldr;
         const int n0 = best_n0;
         int a0, b0, am, bm;
         fft_factor(n0, &a0, &b0);
@@ -583,51 +594,54 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             p.spec.insert(p.spec.end(), out.begin(), out.end());
         }
         const int t0 = want_tw(n0), tm = want_tw(M), t2m = want_tw(2 * M);
-        // row pieces
-        const int P = best_P;
-        for (int pc_i = 0; pc_i < P; ++pc_i) {
-            int64_t s = (m[0] * pc_i) / P, e = (m[0] * (pc_i + 1)) / P;
-            if (e <= s) continue;
-            int64_t plo0 = I_lo[0] + s, phi0 = I_lo[0] + e - 1;
-            int64_t olo0 = std::max(plo0 + zlo[0], (int64_t)0), ohi0 = std::min(phi0 + zhi[0], nr - 1);
-            int64_t olo1 = std::max(I_lo[1] + zlo[1], (int64_t)0), ohi1 = std::min(I_hi[1] + zhi[1], nc - 1);
-            Item it;
-            std::memset(&it, 0, sizeof(it));
-            it.n0 = n0;
-            it.a0 = a0;
-            it.b0 = b0;
-            it.m = M;
-            it.am = am;
-            it.bm = bm;
-            it.ld = ldr;
-            it.tw0 = t0;
-            it.twm = tm;
-            it.tw2m = t2m;
-            it.g0 = (int32_t)olo0;
-            it.g1 = (int32_t)olo1;
-            it.in_off0 = (int32_t)(plo0 - olo0);
-            it.in_off1 = (int32_t)(I_lo[1] - olo1);
-            it.in_n0 = (int32_t)(e - s);
-            it.in_n1 = (int32_t)m[1];
-            it.out_n0 = (int32_t)(ohi0 - olo0 + 1);
-            it.out_n1 = (int32_t)(ohi1 - olo1 + 1);
-            it.patch = (int32_t)k;
-            it.w_off = w_base[k] + s * m[1];
-            it.spec_off = spec_off;
-            // the FFT box must hold input and output without wrap-around
-            if (it.in_off0 < 0 || it.in_off1 < 0 || it.in_off0 + it.in_n0 > n0 || it.in_off1 + it.in_n1 > n1 ||
-                it.out_n0 > n0 || it.out_n1 > n1) {
-                err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
-                return PC_ERR_ARG;
+        // pieces: P0 row ranges x P1 column ranges of the patch box
+        for (int i0 = 0; i0 < best_P0; ++i0)
+            for (int i1 = 0; i1 < best_P1; ++i1) {
+                const int64_t s0 = (m[0] * i0) / best_P0, e0 = (m[0] * (i0 + 1)) / best_P0;
+                const int64_t s1 = (m[1] * i1) / best_P1, e1 = (m[1] * (i1 + 1)) / best_P1;
+                if (e0 <= s0 || e1 <= s1) continue;
+                const int64_t plo0 = I_lo[0] + s0, phi0 = I_lo[0] + e0 - 1;
+                const int64_t plo1 = I_lo[1] + s1, phi1 = I_lo[1] + e1 - 1;
+                const int64_t olo0 = std::max(plo0 + zlo[0], (int64_t)0), ohi0 = std::min(phi0 + zhi[0], nr - 1);
+                const int64_t olo1 = std::max(plo1 + zlo[1], (int64_t)0), ohi1 = std::min(phi1 + zhi[1], nc - 1);
+                Item it;
+                std::memset(&it, 0, sizeof(it));
+                it.n0 = n0;
+                it.a0 = a0;
+                it.b0 = b0;
+                it.m = M;
+                it.am = am;
+                it.bm = bm;
+                it.ld = ldr;
+                it.tw0 = t0;
+                it.twm = tm;
+                it.tw2m = t2m;
+                it.g0 = (int32_t)olo0;
+                it.g1 = (int32_t)olo1;
+                it.in_off0 = (int32_t)(plo0 - olo0);
+                it.in_off1 = (int32_t)(plo1 - olo1);
+                it.in_n0 = (int32_t)(e0 - s0);
+                it.in_n1 = (int32_t)(e1 - s1);
+                it.out_n0 = (int32_t)(ohi0 - olo0 + 1);
+                it.out_n1 = (int32_t)(ohi1 - olo1 + 1);
+                it.patch = (int32_t)k;
+                it.w_ld = (int32_t)m[1];
+                it.w_off = w_base[k] + s0 * m[1] + s1;
+                it.spec_off = spec_off;
+                // the FFT box must hold input and output without wrap-around
+                if (it.in_off0 < 0 || it.in_off1 < 0 || it.in_off0 + it.in_n0 > n0 || it.in_off1 + it.in_n1 > n1 ||
+                    it.out_n0 > n0 || it.out_n1 > n1) {
+                    err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
+                    return PC_ERR_ARG;
+                }
+                it.slot_fwd = p.slot_fwd;
+                it.slot_adj = p.slot_adj;
+                p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
+                p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
+                p.sum_fft_points += (int64_t)n0 * n1;
+                p.max_lds = std::max(p.max_lds, (int)(n0 * ldr * csz));
+                p.items.push_back(it);
             }
-            it.slot_fwd = p.slot_fwd;
-            it.slot_adj = p.slot_adj;
-            p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
-            p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
-            p.sum_fft_points += (int64_t)n0 * n1;
-            p.max_lds = std::max(p.max_lds, (int)(n0 * ldr * csz));
-            p.items.push_back(it);
-        }
     }
     p.kernel_elems = kernel_elems;
     p.alg_flops = alg_flops;

@@ -1,0 +1,66 @@
+"""Exact blur adjoint on the GPU (the black-box A* of the error estimator).
+
+ctypes wrapper of workloads/libblur.so (built by the package build step).
+Device arrays are torch tensors; torch is imported first so the library binds
+to the same HIP runtime.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libblur.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            raise ImportError(f"{_LIB} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.blur_adjoint.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, P,
+                                     ctypes.c_int64, ctypes.c_int, P]
+        lib.blur_adjoint.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class GpuBlurAdjoint:
+    """Holds the width and radius fields of a BlurOperator on the device."""
+
+    def __init__(self, op, dtype=torch.float32, device="cuda"):
+        if op.d == 1:
+            s0 = np.ones(op.shape)
+            s1 = op.sig[0]
+            r0 = np.zeros(op.shape, dtype=np.int32)
+            r1 = op.radius[0]
+            self.n0, self.n1 = 1, int(op.shape[0])
+        else:
+            s0, s1 = op.sig[0], op.sig[1]
+            r0, r1 = op.radius[0], op.radius[1]
+            self.n0, self.n1 = int(op.shape[0]), int(op.shape[1])
+        self.dtype = dtype
+        self.s0 = torch.from_numpy(np.ascontiguousarray(s0).ravel()).to(device=device, dtype=dtype)
+        self.s1 = torch.from_numpy(np.ascontiguousarray(s1).ravel()).to(device=device, dtype=dtype)
+        self.r0 = torch.from_numpy(np.ascontiguousarray(r0, dtype=np.int32).ravel()).to(device)
+        self.r1 = torch.from_numpy(np.ascontiguousarray(r1, dtype=np.int32).ravel()).to(device)
+        self.code = 1 if dtype == torch.float64 else 0
+
+    def raw(self, B, in_ptr, ldin, out_ptr, ldout, stream_ptr):
+        """Callback form: pointers and leading dimensions as plain ints."""
+        return _load().blur_adjoint(self.code, self.s0.data_ptr(), self.s1.data_ptr(), self.r0.data_ptr(),
+                                    self.r1.data_ptr(), self.n0, self.n1, in_ptr, ldin, out_ptr, ldout, B,
+                                    stream_ptr)
+
+    def __call__(self, V, OUT=None):
+        V = V.reshape(-1, self.n0 * self.n1)
+        if OUT is None:
+            OUT = torch.empty_like(V)
+        rc = self.raw(V.shape[0], V.data_ptr(), V.stride(0), OUT.data_ptr(), OUT.stride(0),
+                      torch.cuda.current_stream().cuda_stream)
+        if rc != 0:
+            raise RuntimeError("blur_adjoint launch failed")
+        return OUT
