@@ -179,3 +179,27 @@ class OracleOperator:
                             for i in range(self.d))
                 out[q] += float(np.sum(self.W[k][wsl] * f[xs] * K[ksl]))
         return out
+
+    def apply_adjoint_at(self, g, xs):
+        """(A~* g)[x] for a list of points x (eq. (1.6)), by direct summation."""
+        g = np.asarray(g, dtype=np.float64).reshape(self.shape)
+        xs = np.asarray(xs, dtype=np.int64).reshape(-1, self.d)
+        n = np.array(self.shape)
+        out = np.zeros(len(xs))
+        for k in range(self.grid.r):
+            ulo, uhi = self.u_lo[k], self.u_hi[k]
+            K, zlo = self.K[k], self.zlo[k]
+            for q in np.nonzero(np.all((xs >= ulo) & (xs <= uhi), axis=1))[0]:
+                x = xs[q]
+                wk = self.W[k][tuple(x - ulo)]
+                if wk == 0.0:
+                    continue
+                # y = x + z for z in the kernel box, y inside Omega
+                a = np.maximum(zlo, -x)
+                b = np.minimum(zlo + np.array(K.shape) - 1, n - 1 - x)
+                if np.any(a > b):
+                    continue
+                ksl = tuple(slice(int(a[i] - zlo[i]), int(b[i] - zlo[i] + 1)) for i in range(self.d))
+                gsl = tuple(slice(int(x[i] + a[i]), int(x[i] + b[i] + 1)) for i in range(self.d))
+                out[q] += wk * float(np.sum(K[ksl] * g[gsl]))
+        return out

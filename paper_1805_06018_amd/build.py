@@ -40,13 +40,13 @@ def _run(cmd, out):
 
 
 def build_lib():
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3"] + COMMON + DEVICE_FLAGS + [
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3", "-fopenmp"] + COMMON + DEVICE_FLAGS + [
         "pc_kernels.hip", "pc_host.cpp", "pc_plan.cpp"]
     return _run(cmd, LIB)
 
 
 def build_emu(asan=False):
-    cmd = [HIPCC, "-x", "hip", "--offload-host-only", "-O1", "-g"] + COMMON
+    cmd = [HIPCC, "-x", "hip", "--offload-host-only", "-O1", "-g", "-fopenmp"] + COMMON
     if asan:
         cmd += ["-Xarch_host", "-fsanitize=address", "-fno-omit-frame-pointer"]
     cmd += ["pc_emu.cpp", "pc_plan.cpp"]

@@ -461,9 +461,21 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     };
     p.items.clear();
     p.spec.clear();
-    int64_t kernel_elems = 0;
-    double alg_flops = 0.0;
+    struct PatchOut {
+        pc_status st = PC_OK;
+        std::string err;
+        std::vector<double> spec;
+        std::vector<Item> items;
+        int n0 = 0, M = 0;
+        double flops = 0.0;
+        int64_t kel = 0;
+    };
+    std::vector<PatchOut> outs((size_t)r);
+    // every patch is independent: extension, sizes, spectrum and pieces are
+    // computed in parallel, then assembled in patch order below
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < r; ++k) {
+        PatchOut& po = outs[(size_t)k];
         const int64_t I_lo[2] = {Ulo[2 * k], Ulo[2 * k + 1]}, I_hi[2] = {Uhi[2 * k], Uhi[2 * k + 1]};
         const int64_t m[2] = {I_hi[0] - I_lo[0] + 1, I_hi[1] - I_lo[1] + 1};
         int64_t Rm[2] = {R2[2 * k], R2[2 * k + 1]};
@@ -477,7 +489,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             zhi[i] = std::min(Rm[i], ndom[i] - 1 - I_lo[i]);
             K[i] = zhi[i] - zlo[i] + 1;
         }
-        kernel_elems += (2 * R2[2 * k] + 1) * (2 * R2[2 * k + 1] + 1);
+        po.kel = (2 * R2[2 * k] + 1) * (2 * R2[2 * k + 1] + 1);
         // extended kernel phi_k^E on the box [zlo, zhi]
         std::vector<double> E((size_t)(K[0] * K[1]), 0.0);
         auto defined = [&](int64_t j, int64_t z0, int64_t z1) {
@@ -511,7 +523,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             int64_t nn = (int64_t)smallest_7smooth(m[0] + K[0] - 1) * smallest_7smooth(m[1] + K[1] - 1);
             int64_t O = (std::min(I_hi[0] + zhi[0], nr - 1) - std::max(I_lo[0] + zlo[0], (int64_t)0) + 1) *
                         (std::min(I_hi[1] + zhi[1], nc - 1) - std::max(I_lo[1] + zlo[1], (int64_t)0) + 1);
-            alg_flops += 5.0 * nn * std::log2((double)nn) + 3.0 * nn + (double)(m[0] * m[1]) + (double)O;
+            po.flops = 5.0 * nn * std::log2((double)nn) + 3.0 * nn + (double)(m[0] * m[1]) + (double)O;
         }
         // choose FFT lengths and the number of row pieces
         const int64_t need1 = m[1] + K[1] - 1;
@@ -548,8 +560,9 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             }
         }
         if (best_P0 < 0) {
-            err = "patch " + std::to_string(k) + " does not fit the LDS-resident FFT";
-            return PC_ERR_UNSUPPORTED;
+            po.err = "patch " + std::to_string(k) + " does not fit the LDS-resident FFT";
+            po.st = PC_ERR_UNSUPPORTED;
+            continue;
         }
         M = best_M;
         ldr = M + 1;
@@ -559,12 +572,14 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         fft_factor(n0, &a0, &b0);
         fft_factor(M, &am, &bm);
         if (M > 128 || bm > 10) {
-            err = "patch " + std::to_string(k) + " needs a row FFT outside the supported lengths";
-            return PC_ERR_UNSUPPORTED;
+            po.err = "patch " + std::to_string(k) + " needs a row FFT outside the supported lengths";
+            po.st = PC_ERR_UNSUPPORTED;
+            continue;
         }
+        po.n0 = n0;
+        po.M = M;
         const int n1 = 2 * M;
         // spectrum of phi_k^E placed circularly, FP64, half spectrum along axis 1
-        const int64_t spec_off = (int64_t)(p.spec.size() / 2);
         {
             std::vector<cd> G((size_t)n0 * n1, cd(0.0));
             for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0)
@@ -591,9 +606,8 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                     out[2 * ((size_t)s0 * (M + 1) + s1) + 1] = colout[k0].imag() * sc;
                 }
             }
-            p.spec.insert(p.spec.end(), out.begin(), out.end());
+            po.spec = std::move(out);
         }
-        const int t0 = want_tw(n0), tm = want_tw(M), t2m = want_tw(2 * M);
         // pieces: P0 row ranges x P1 column ranges of the patch box
         for (int i0 = 0; i0 < best_P0; ++i0)
             for (int i1 = 0; i1 < best_P1; ++i1) {
@@ -613,9 +627,6 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 it.am = am;
                 it.bm = bm;
                 it.ld = ldr;
-                it.tw0 = t0;
-                it.twm = tm;
-                it.tw2m = t2m;
                 it.g0 = (int32_t)olo0;
                 it.g1 = (int32_t)olo1;
                 it.in_off0 = (int32_t)(plo0 - olo0);
@@ -627,21 +638,46 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 it.patch = (int32_t)k;
                 it.w_ld = (int32_t)m[1];
                 it.w_off = w_base[k] + s0 * m[1] + s1;
-                it.spec_off = spec_off;
                 // the FFT box must hold input and output without wrap-around
                 if (it.in_off0 < 0 || it.in_off1 < 0 || it.in_off0 + it.in_n0 > n0 || it.in_off1 + it.in_n1 > n1 ||
                     it.out_n0 > n0 || it.out_n1 > n1) {
-                    err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
-                    return PC_ERR_ARG;
+                    po.err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
+                    po.st = PC_ERR_ARG;
+                    continue;
                 }
-                it.slot_fwd = p.slot_fwd;
-                it.slot_adj = p.slot_adj;
-                p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
-                p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
-                p.sum_fft_points += (int64_t)n0 * n1;
-                p.max_lds = std::max(p.max_lds, (int)(n0 * ldr * csz));
-                p.items.push_back(it);
+                po.items.push_back(it);
             }
+    }
+    // assembly in patch order: spectra, twiddle tables, staging offsets
+    int64_t kernel_elems = 0;
+    double alg_flops = 0.0;
+    for (int64_t k = 0; k < r; ++k) {
+        PatchOut& po = outs[(size_t)k];
+        if (po.st != PC_OK) {
+            err = po.err;
+            return po.st;
+        }
+        kernel_elems += po.kel;
+        alg_flops += po.flops;
+        const int64_t spec_off = (int64_t)(p.spec.size() / 2);
+        p.spec.insert(p.spec.end(), po.spec.begin(), po.spec.end());
+        std::vector<double>().swap(po.spec);
+        const int t0 = want_tw(po.n0), tm = want_tw(po.M), t2m = want_tw(2 * po.M);
+        int ldr = po.M + 1;
+        if (ldr % 2 == 0) ++ldr;
+        for (Item it : po.items) {
+            it.tw0 = t0;
+            it.twm = tm;
+            it.tw2m = t2m;
+            it.spec_off = spec_off;
+            it.slot_fwd = p.slot_fwd;
+            it.slot_adj = p.slot_adj;
+            p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
+            p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
+            p.sum_fft_points += (int64_t)po.n0 * 2 * po.M;
+            p.max_lds = std::max(p.max_lds, (int)(po.n0 * ldr * csz));
+            p.items.push_back(it);
+        }
     }
     p.kernel_elems = kernel_elems;
     p.alg_flops = alg_flops;

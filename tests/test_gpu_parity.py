@@ -194,3 +194,34 @@ def test_apply_argument_errors(lib):
     with pytest.raises(TypeError):
         op.apply_batch(torch.zeros((1, w.N), dtype=torch.float32, device="cuda"),
                        torch.zeros((1, w.N), dtype=torch.float32, device="cuda"))
+
+
+def test_large_pieces_blur2048_start_grid(lib):
+    """2048^2 start grid (16 points, cells 683 wide, kernels up to 129^2): every
+    patch is cut into a grid of row x column pieces.  Forward and adjoint at
+    sampled outputs against the oracle."""
+    w = make_config(3)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    _note(f"blur2048 start: items={op.stats()['n_items']}")
+    U = w.vectors(2, dtype=np.float32)
+    Ud = torch.from_numpy(U).cuda()
+    fwd = torch.zeros_like(Ud)
+    adj = torch.zeros_like(Ud)
+    op.apply_batch(Ud, fwd)
+    op.apply_adjoint_batch(Ud, adj)
+    torch.cuda.synchronize()
+    fwd, adj = fwd.cpu().numpy(), adj.cpu().numpy()
+    ora = OracleOperator.from_workload(w)
+    rng = np.random.default_rng(11)
+    n = w.shape[0]
+    ys = np.stack([rng.integers(0, n, 20), rng.integers(0, n, 20)], axis=1)
+    ys = np.vstack([ys, [[0, 0], [n - 1, n - 1], [682, 1365], [1365, 682], [681, 683]]])
+    flat = ys[:, 0] * n + ys[:, 1]
+    for j in range(2):
+        u = U[j].astype(np.float64)
+        rf = ora.apply_at(u, ys)
+        ra = ora.apply_adjoint_at(u, ys)
+        sf = np.abs(fwd[j]).max()
+        sa = np.abs(adj[j]).max()
+        assert np.abs(fwd[j, flat] - rf).max() <= 1e-5 * sf, (j, np.abs(fwd[j, flat] - rf).max() / sf)
+        assert np.abs(adj[j, flat] - ra).max() <= 1e-5 * sa, (j, np.abs(adj[j, flat] - ra).max() / sa)

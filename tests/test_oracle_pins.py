@@ -410,3 +410,14 @@ def test_c_core_matches_numpy_loops():
     assert np.abs(op.apply_adjoint(u, backend="numpy") - op.apply_adjoint(u, backend="c")).max() < 1e-13
     ys = np.array([[0, 0], [63, 63], [31, 7], [5, 60]])
     assert np.abs(op.apply_at(u, ys) - a.reshape(64, 64)[ys[:, 0], ys[:, 1]]).max() < 1e-13
+
+
+def test_sampled_adjoint_matches_full_adjoint():
+    """apply_adjoint_at (used for full-size sampled checks) against the full
+    adjoint, itself pinned by the transpose and exactness tests."""
+    w = _varying_case(13)
+    op = OracleOperator.from_workload(w)
+    v = np.random.default_rng(21).standard_normal(op.N)
+    full = op.apply_adjoint(v).reshape(op.shape)
+    xs = np.array([[0, 0], [12, 12], [3, 7], [12, 0], [6, 6]])
+    assert np.abs(op.apply_adjoint_at(v, xs) - full[xs[:, 0], xs[:, 1]]).max() < 1e-13
