@@ -1,0 +1,267 @@
+"""Continuous-batching request loop over resident product-convolution
+operators.
+
+Requests (apply, or error-estimate with probe vectors) arrive on a Poisson
+clock for one of several resident operators.  The server keeps every
+operator's spectra on the device and runs a loop that
+  - moves arrived requests into a queue;
+  - retires finished batches (their events have fired);
+  - admits work while a stream slot is free and the HBM budget allows it: all
+    queued apply requests for the operator with the oldest waiting request are
+    merged into one fused pc_apply_batch launch (continuous batching across
+    requests; the apply of each vector is independent of the batch, so every
+    result is bitwise the same alone and in the mix); an estimate request runs
+    pc_error_estimate.
+Batches for different operators run on different streams and overlap on the
+device; one operator has at most one batch in flight (its work buffers are
+shared).  Modes: "batched" (the above), "sequential" (one request at a time,
+fused kernels) and "plain" (one request at a time, one launch per patch and
+vector).  Latency = completion time observed by the loop - arrival time.
+"""
+import json
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Request:
+    rid: int
+    op: int
+    kind: str            # "apply" or "estimate"
+    B: int
+    arrival: float       # seconds after the start of the run
+    t_done: float = None
+    result: object = None
+
+
+@dataclass
+class Resident:
+    name: str
+    pc: object           # _lib.PcOperator
+    N: int
+    U: torch.Tensor      # (32, N) input pool: request j uses the first B rows
+    Z: torch.Tensor      # (q, N) probes for estimate requests
+    Y: torch.Tensor      # (q, N) exact adjoint of Z
+    work_bytes: int = 0  # resident operator data + staging estimate
+
+
+def poisson_requests(n_req, n_ops, rate, seed=104, max_b=32, p_estimate=0.2, q=8):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_req):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        op = int(rng.integers(0, n_ops))
+        kind = "estimate" if rng.uniform() < p_estimate else "apply"
+        B = q if kind == "estimate" else int(rng.integers(1, max_b + 1))
+        out.append(Request(i, op, kind, B, t))
+    return out
+
+
+class _Batch:
+    def __init__(self, op, reqs, stream, nbytes):
+        self.op, self.reqs, self.stream, self.nbytes = op, reqs, stream, nbytes
+        self.event = torch.cuda.Event()
+
+
+class Server:
+    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=2):
+        self.ops = residents
+        self.budget = hbm_budget
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.resident_bytes = sum(r.work_bytes for r in residents)
+        if self.resident_bytes > self.budget:
+            raise ValueError("resident operators exceed the HBM budget")
+
+    def _launch_apply(self, op, reqs, stream, plain=False):
+        r = self.ops[op]
+        Bt = sum(q.B for q in reqs)
+        with torch.cuda.stream(stream):
+            if len(reqs) == 1:
+                inp = r.U[:Bt]
+            else:
+                inp = torch.cat([r.U[:q.B] for q in reqs], dim=0)
+            out = torch.empty((Bt, r.N), dtype=torch.float32, device="cuda")
+            (r.pc.apply_batch_plain if plain else r.pc.apply_batch)(inp, out, stream=stream)
+        o = 0
+        for q in reqs:
+            q.result = out[o:o + q.B]
+            o += q.B
+        b = _Batch(op, reqs, stream, 2 * Bt * r.N * 4)
+        b.event.record(stream)
+        return b
+
+    def _run_estimate(self, q, stream):
+        r = self.ops[q.op]
+        with torch.cuda.stream(stream):
+            q.result = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B], stream=stream)
+
+    def run(self, requests, mode="batched"):
+        reqs = sorted(requests, key=lambda q: q.arrival)
+        pending = deque()
+        inflight = []
+        busy_ops = set()
+        inflight_bytes = 0
+        peak = self.resident_bytes
+        batches = []
+        i = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        while i < len(reqs) or pending or inflight:
+            t = now()
+            while i < len(reqs) and reqs[i].arrival <= t:
+                pending.append(reqs[i])
+                i += 1
+            for b in list(inflight):
+                if b.event.query():
+                    td = now()
+                    for q in b.reqs:
+                        q.t_done = td
+                    inflight.remove(b)
+                    busy_ops.discard(b.op)
+                    inflight_bytes -= b.nbytes
+            if mode != "batched" and inflight:
+                continue
+            if not pending:
+                if not inflight and i < len(reqs):
+                    time.sleep(max(0.0, min(reqs[i].arrival - now(), 1e-3)))
+                continue
+            if len(inflight) >= len(self.streams):
+                continue
+            free = [s for s in self.streams if all(b.stream is not s for b in inflight)]
+            stream = free[0]
+            if mode != "batched":
+                q = pending.popleft()
+                if q.kind == "estimate":
+                    self._run_estimate(q, stream)
+                    q.t_done = now()
+                    batches.append(1)
+                    continue
+                b = self._launch_apply(q.op, [q], stream, plain=(mode == "plain"))
+                inflight.append(b)
+                batches.append(1)
+                continue
+            # batched: the operator of the oldest waiting request that is free
+            head = next((q for q in pending if q.op not in busy_ops), None)
+            if head is None:
+                continue
+            if head.kind == "estimate":
+                pending.remove(head)
+                self._run_estimate(head, stream)
+                head.t_done = now()
+                batches.append(1)
+                continue
+            r = self.ops[head.op]
+            take, vecs = [], 0
+            for q in pending:
+                if q.op != head.op or q.kind != "apply":
+                    continue
+                nb = 2 * (vecs + q.B) * r.N * 4
+                if vecs + q.B > self.max_batch or self.resident_bytes + inflight_bytes + nb > self.budget:
+                    break
+                take.append(q)
+                vecs += q.B
+            if not take:
+                if not inflight:   # it cannot fit even with nothing else admitted
+                    pending.remove(head)
+                    head.result = "rejected: exceeds the HBM budget"
+                    head.t_done = now()
+                # otherwise wait until in-flight batches free memory
+                continue
+            for q in take:
+                pending.remove(q)
+            b = self._launch_apply(head.op, take, stream)
+            inflight.append(b)
+            busy_ops.add(head.op)
+            inflight_bytes += b.nbytes
+            peak = max(peak, self.resident_bytes + inflight_bytes)
+            batches.append(len(take))
+        t_end = now()
+        out = summarize(reqs, t_end, batches, self.ops)
+        out["peak_admitted_bytes"] = int(peak)
+        return out
+
+
+def summarize(reqs, t_end, batches, ops):
+    lat = {k: [] for k in ("apply", "estimate")}
+    vec = 0
+    pts = 0
+    rejected = 0
+    for q in reqs:
+        if isinstance(q.result, str):
+            rejected += 1
+            continue
+        lat[q.kind].append(q.t_done - q.arrival)
+        vec += q.B
+        pts += q.B * ops[q.op].N
+    out = {"requests": len(reqs), "wall_s": t_end, "req_per_s": len(reqs) / t_end,
+           "grid_points_per_s": pts / t_end, "vectors_per_s": vec / t_end,
+           "mean_batch_requests": float(np.mean(batches)) if batches else 0.0, "rejected": rejected}
+    for k, v in lat.items():
+        if v:
+            out[f"{k}_p50_ms"] = 1e3 * float(np.percentile(v, 50))
+            out[f"{k}_p99_ms"] = 1e3 * float(np.percentile(v, 99))
+    return out
+
+
+def build_residents(workloads, q=8, dtype=_lib.PC_F32):
+    from workloads.blur_gpu import GpuBlurAdjoint
+    res = []
+    for w in workloads:
+        op = _lib.PcOperator.from_workload(w, dtype=dtype)
+        U = torch.from_numpy(w.vectors(32, dtype=np.float32)).cuda()
+        Z = torch.from_numpy(w.rademacher(q, w.vec_seed + 1000).astype(np.float32)).cuda()
+        Y = GpuBlurAdjoint(w.op)(Z)
+        st = op.stats()
+        staging = min(32 * st["slot_elems_fwd"], (2 << 30) // 4) * 4
+        res.append(Resident(w.name, op, w.N, U, Z, Y, op.device_bytes() + staging))
+    torch.cuda.synchronize()
+    return res
+
+
+def main(argv=None):
+    import argparse
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from workloads import make_serving_ops
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--plain-requests", type=int, default=40)
+    ap.add_argument("--loads", type=str, default="0.5,0.8,1.0")
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    res = build_residents(make_serving_ops())
+    print(json.dumps({"ops": [r.name for r in res], "setup_s": time.time() - t0,
+                      "resident_gib": sum(r.work_bytes for r in res) / 2**30}), flush=True)
+    srv = Server(res, hbm_budget=int(args.budget_gib * 2**30))
+    # warm-up, then the saturated rate of one-request-at-a-time fused applies
+    srv.run(poisson_requests(24, len(res), 0.0), mode="sequential")
+    sat = srv.run(poisson_requests(args.requests // 4, len(res), 0.0), mode="sequential")
+    rate = sat["req_per_s"]
+    print(json.dumps({"mode": "sequential", "load": "saturated", **sat}), flush=True)
+    satb = srv.run(poisson_requests(args.requests // 4, len(res), 0.0), mode="batched")
+    print(json.dumps({"mode": "batched", "load": "saturated", **satb}), flush=True)
+    if args.plain_requests > 0:
+        pl = srv.run(poisson_requests(args.plain_requests, len(res), 0.0), mode="plain")
+        print(json.dumps({"mode": "plain", "load": "saturated", **pl}), flush=True)
+    for f in [float(x) for x in args.loads.split(",")]:
+        for mode in ("sequential", "batched"):
+            out = srv.run(poisson_requests(args.requests, len(res), f * rate), mode=mode)
+            print(json.dumps({"mode": mode, "load": f, "rate_req_per_s": f * rate, **out}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,54 @@
+"""GPU tests of the continuous-batching request loop."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def served():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible HIP device")
+    from paper_1805_06018_amd import serve
+    from workloads import make_serving_ops
+    res = serve.build_residents(make_serving_ops(sizes=(256, 512, 768)))
+    return serve, res
+
+
+def test_results_same_alone_and_in_the_mix(served):
+    serve, res = served
+    srv = serve.Server(res, hbm_budget=16 << 30)
+    reqs = serve.poisson_requests(60, len(res), 0.0, seed=5)
+    out = srv.run(reqs, mode="batched")
+    assert out["mean_batch_requests"] > 1.0          # requests were merged
+    for q in reqs:
+        r = res[q.op]
+        if q.kind == "apply":
+            alone = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
+            r.pc.apply_batch(r.U[:q.B], alone)
+            torch.cuda.synchronize()
+            assert torch.equal(alone, q.result), q.rid
+        else:
+            eta, ea, er = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B])
+            assert np.array_equal(eta, q.result[0]) and ea == q.result[1] and er == q.result[2]
+
+
+def test_hbm_budget_admission(served):
+    serve, res = served
+    resident = sum(r.work_bytes for r in res)
+    with pytest.raises(ValueError):
+        serve.Server(res, hbm_budget=resident // 2)
+    # room for about eight vectors of the largest grid in flight
+    room = 2 * 8 * max(r.N for r in res) * 4
+    srv = serve.Server(res, hbm_budget=resident + room)
+    reqs = serve.poisson_requests(40, len(res), 0.0, seed=6, max_b=8)
+    out = srv.run(reqs, mode="batched")
+    assert all(q.t_done is not None for q in reqs)
+    assert out["peak_admitted_bytes"] <= resident + room
+    for q in reqs:
+        if q.kind == "apply":
+            alone = torch.empty((q.B, res[q.op].N), dtype=torch.float32, device="cuda")
+            res[q.op].pc.apply_batch(res[q.op].U[:q.B], alone)
+            torch.cuda.synchronize()
+            assert torch.equal(alone, q.result)

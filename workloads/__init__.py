@@ -16,10 +16,10 @@ from .fields import cosine_field, cfg0_sigma
 from .grids import (uniform_nodes, tensor_leaves, quadtree_leaves,
                     corner_points, tune_quadtree)
 from .blur import BlurOperator
-from .configs import make_config, Workload
+from .configs import make_config, make_serving_ops, Workload
 
 __all__ = [
     "cosine_field", "cfg0_sigma", "uniform_nodes", "tensor_leaves",
     "quadtree_leaves", "corner_points", "tune_quadtree", "BlurOperator",
-    "make_config", "Workload",
+    "make_config", "make_serving_ops", "Workload",
 ]

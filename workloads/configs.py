@@ -101,3 +101,26 @@ def make_config(idx, scale=1.0):
         return _finish(f"blur2d_{n}_start4x4", np.stack([s, s]), lo, hi, 32, 103,
                        {"modes": modes, "nodes": nodes})
     raise ValueError(f"unknown config {idx}")
+
+
+def make_serving_ops(sizes=None):
+    """The resident 2-D operators of the serving workload: grids 256^2 to
+    2048^2 with 25 to about 2000 sample points (s in [2, 12], s in [2, 16] on
+    the largest), uniform grids for the two smallest, quadtrees otherwise."""
+    specs = [(256, 25, 0), (512, 100, 0), (768, 300, 1), (1024, 600, 1), (1536, 1000, 1), (2048, 2000, 1)]
+    out = []
+    for i, (n, r_target, adaptive) in enumerate(specs):
+        if sizes is not None and n not in sizes:
+            continue
+        hi_s = 16.0 if n == 2048 else 12.0
+        s, modes = cosine_field((n, n), 2.0, hi_s, 2, 3, seed=40 + i)
+        if not adaptive:
+            m = int(round(np.sqrt(r_target)))
+            nodes = uniform_nodes(n, m)
+            lo, hi = tensor_leaves([nodes, nodes])
+            name = f"blur2d_{n}_uniform{m}x{m}"
+        else:
+            _, lo, hi, _ = tune_quadtree(s, int(r_target * 0.9), int(r_target * 1.1) + 1)
+            name = f"blur2d_{n}_quadtree"
+        out.append(_finish(name, np.stack([s, s]), lo, hi, 32, 104 + i, {"modes": modes}))
+    return out
