@@ -10,9 +10,9 @@
  * (Sec. 2.6) on top of the adjoint.
  *
  * Conventions
- *  - The domain Omega is the box prod_i [0, shape[i]-1] in Z^d, d in {1, 2}
- *    (d = 3 is rejected with PC_ERR_UNSUPPORTED).  Grid functions are stored
- *    row-major over Omega (axis 0 slowest), N = prod shape.
+ *  - The domain Omega is the box prod_i [0, shape[i]-1] in Z^d, d in
+ *    {1, 2, 3}.  Grid functions are stored row-major over Omega (axis 0
+ *    slowest), N = prod shape.
  *  - Boxes are inclusive integer boxes [lo, hi]; arrays of boxes and points
  *    are row-major [count][d] int64.
  *  - Batched vectors are contiguous: vector j of a batch starts at
@@ -82,6 +82,12 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *  out                  : receives the operator.
  * Weights w_k are the harmonic partition of unity of Sec. 2.4 (multilinear
  * hats on cells without hanging nodes); 2-D hanging nodes are supported.
+ * For d = 3 every leaf must carry only its own corners (a conforming
+ * tiling, trilinear weights); a 3-D leaf with hanging nodes on its faces or
+ * edges gives PC_ERR_UNSUPPORTED.  PC_ERR_UNSUPPORTED is also returned when
+ * a patch's FFT box exceeds the kernels' limits (FFT lengths up to 256 along
+ * axis 0 (and axis 1 in 3-D), real length up to 256 along the last axis,
+ * one LDS-resident plane per workgroup).
  */
 pc_status pc_create(int d, const int64_t* shape,
                     int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
@@ -174,8 +180,12 @@ pc_status   pc_set_profiling(pc_op* op, int enable);
  *  PC_TUNE_CHUNK    vectors per convolution launch (0 = library default)
  *  PC_TUNE_OVERLAP  1: reduce chunk i on a library stream while chunk i+1
  *                   convolves; 0: everything on the caller's stream
+ *                   (2-D operators only)
+ *  PC_TUNE_SCRATCH  3-D operators: bytes of plane-spectrum scratch per item
+ *                   group (0 = library default, 512 MiB); one item group runs
+ *                   its three kernels before the next group starts
  * Results are bitwise identical for every setting. */
-enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2 };
+enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 size_t      pc_device_bytes(const pc_op* op);

@@ -41,7 +41,7 @@ def _run(cmd, out):
 
 def build_lib():
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3", "-fopenmp"] + COMMON + DEVICE_FLAGS + [
-        "pc_kernels.hip", "pc_host.cpp", "pc_plan.cpp"]
+        "pc_kernels.hip", "pc_host.cpp", "pc_plan.cpp", "pc_plan3.cpp"]
     return _run(cmd, LIB)
 
 
@@ -49,7 +49,7 @@ def build_emu(asan=False):
     cmd = [HIPCC, "-x", "hip", "--offload-host-only", "-O1", "-g", "-fopenmp"] + COMMON
     if asan:
         cmd += ["-Xarch_host", "-fsanitize=address", "-fno-omit-frame-pointer"]
-    cmd += ["pc_emu.cpp", "pc_plan.cpp"]
+    cmd += ["pc_emu.cpp", "pc_plan.cpp", "pc_plan3.cpp"]
     return _run(cmd, EMU_ASAN if asan else EMU)
 
 

@@ -11,11 +11,14 @@
 #include <string>
 #include <vector>
 
-#include "pc_phases.h"
+#include "pc_phases3.h"
 #include "pc_plan.h"
 
 namespace {
 thread_local std::string g_emu_err;
+
+template <class T>
+void reduce_all(const pc::Plan& P, bool adj, int64_t B, const std::vector<T>& slots, int64_t per, T* OUT, int64_t ldo);
 
 template <class T>
 void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
@@ -46,6 +49,13 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
             for (int t = 0; t < nth; ++t) pc::phH(c, buf.data(), t, nth);
         }
     }
+    reduce_all(P, adj, B, slots, per, OUT, ldo);
+}
+
+template <class T>
+void reduce_all(const pc::Plan& P, bool adj, int64_t B, const std::vector<T>& slots, int64_t per, T* OUT,
+                int64_t ldo) {
+    const int64_t N = P.N;
     std::vector<T> out((size_t)(B * N), T(0));
     const auto& tiles = adj ? P.tiles_adj : P.tiles_fwd;
     const auto& cboxes = adj ? P.cboxes_adj : P.cboxes_fwd;
@@ -55,6 +65,70 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
                 pc::reduce_tile<T>(t, col, cboxes.data(), &slots[(size_t)(b * per)], &out[(size_t)(b * N)], P.cols);
     for (int64_t b = 0; b < B; ++b) std::memcpy(OUT + b * ldo, &out[(size_t)(b * N)], sizeof(T) * (size_t)N);
 }
+
+// 3-D: the three kernels of pc_phases3.h, one simulated block after another,
+// on one scratch area holding every item and vector (the layout of a launch
+// over all items with B vectors).
+template <class T>
+void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
+    using C = pc::cx<T>;
+    const int64_t N = P.N;
+    std::vector<T> spec(P.spec.begin(), P.spec.end());
+    std::vector<T> wts(P.wts.begin(), P.wts.end());
+    std::vector<T> tw(P.tw.begin(), P.tw.end());
+    const C* specc = reinterpret_cast<const C*>(spec.data());
+    const C* twc = reinterpret_cast<const C*>(tw.data());
+    const int64_t per = adj ? P.slot_adj : P.slot_fwd;
+    std::vector<T> in((size_t)(B * N));
+    for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * N)], U + b * ldu, sizeof(T) * (size_t)N);
+    std::vector<T> slots((size_t)(B * per), T(0));
+    std::vector<C> scratch((size_t)(P.scratch_per_vec * B), C{T(1e30), T(1e30)});
+    const int NT = pc::threads_for<T>();
+    const int COLS = pc::axis_cols(P.dtype), LDA = pc::axis_ld(COLS);
+    const int64_t pitch = P.cols, plane_pitch = (int64_t)P.prow * P.cols;
+    for (const pc::Item3& I : P.items3) {
+        const pc::Planes pl = pc::planes_of(I, adj);
+        const int64_t pe = pc::plane_elems(I);
+        for (int64_t b = 0; b < B; ++b) {
+            const T* iv = &in[(size_t)(b * N)];
+            T* sv = &slots[(size_t)(b * per)];
+            C* sc = pc::item_scratch(scratch.data(), 0, I, (int)B, (int)b);
+            for (int q = 0; q < pl.s_n; ++q) {
+                std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
+                const pc::Ctx<T> c =
+                    pc::plane_ctx_gather<T>(I, adj, q, iv, sv, wts.data(), specc, twc, pitch, plane_pitch);
+                for (int t = 0; t < NT; ++t) pc::phA(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phB(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phC(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phD_fwd(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::plane_store(c, buf.data(), sc + (int64_t)(pl.s_off + q) * pe, t, NT);
+            }
+            for (int64_t c_lo = 0; c_lo < pe; c_lo += COLS) {
+                const int ncols = (int)std::min<int64_t>(COLS, pe - c_lo);
+                std::vector<C> buf((size_t)I.nz * LDA, C{T(1e30), T(1e30)});
+                const pc::Ctx<T> c = pc::axis_ctx<T>(I, adj, (int)c_lo, ncols, LDA, specc, twc);
+                const int AT = pc::kAxisThreads;
+                for (int t = 0; t < AT; ++t) pc::axis_load(c, buf.data(), sc + c_lo, pe, t, AT);
+                for (int t = 0; t < AT; ++t) pc::phC(c, buf.data(), t, AT);
+                for (int t = 0; t < AT; ++t) pc::phD(c, buf.data(), t, AT);
+                for (int t = 0; t < AT; ++t) pc::phE(c, buf.data(), t, AT);
+                for (int t = 0; t < AT; ++t) pc::axis_store(c, buf.data(), sc + c_lo, pe, t, AT);
+            }
+            for (int q = 0; q < pl.d_n; ++q) {
+                std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
+                const pc::Ctx<T> c = pc::plane_ctx_write<T>(I, adj, q, iv, sv, wts.data(), specc, twc, pitch);
+                for (int t = 0; t < NT; ++t) pc::plane_load(c, buf.data(), sc + (int64_t)(pl.d_off + q) * pe, t, NT);
+                for (int t = 0; t < NT; ++t) pc::phD_inv(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phE(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phF(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phG(c, buf.data(), t, NT);
+                for (int t = 0; t < NT; ++t) pc::phH(c, buf.data(), t, NT);
+            }
+        }
+    }
+    reduce_all(P, adj, B, slots, per, OUT, ldo);
+}
+
 }  // namespace
 
 struct pc_emu {
@@ -81,6 +155,15 @@ int pc_emu_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* 
 }
 
 int pc_emu_apply(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo) {
+    if (e->plan.d == 3) {
+        if (e->plan.dtype == PC_F64)
+            emu_apply_3d<double>(e->plan, adj != 0, B, static_cast<const double*>(U), ldu, static_cast<double*>(OUT),
+                                 ldo);
+        else
+            emu_apply_3d<float>(e->plan, adj != 0, B, static_cast<const float*>(U), ldu, static_cast<float*>(OUT),
+                                ldo);
+        return 0;
+    }
     if (e->plan.dtype == PC_F64)
         emu_apply<double>(e->plan, adj != 0, B, static_cast<const double*>(U), ldu, static_cast<double*>(OUT), ldo);
     else
@@ -90,7 +173,7 @@ int pc_emu_apply(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void
 
 int pc_emu_stats(pc_emu* e, int64_t* out8) {
     const pc::Plan& P = e->plan;
-    out8[0] = (int64_t)P.items.size();
+    out8[0] = (int64_t)(P.d == 3 ? P.items3.size() : P.items.size());
     out8[1] = P.sum_fft_points;
     out8[2] = P.slot_fwd;
     out8[3] = P.slot_adj;

@@ -11,6 +11,7 @@
 
 #include "../../include/pc.h"
 #include "pc_kernels.h"
+#include "pc_phases3.h"
 #include "pc_plan.h"
 
 namespace {
@@ -31,6 +32,9 @@ pc_status hip_fail(hipError_t e, const char* what) {
 // the reduction of one vector chunk overlaps the next chunk's convolution).
 constexpr size_t kSlotCapBytes = size_t(2) << 30;
 constexpr int64_t kMinChunks = 4;
+// 3-D operators: default scratch bytes of one item group (all vectors of a
+// chunk), the plane spectra between the three kernels of the group.
+constexpr size_t kScratchCapBytes = size_t(512) << 20;
 
 }  // namespace
 
@@ -44,6 +48,9 @@ struct pc_op {
     void* slots = nullptr;        // two staging buffers of slots_bytes / 2 each
     size_t slots_bytes = 0;
     int64_t tune_chunk = 0;       // 0: default chunking
+    int64_t tune_scratch = 0;     // 3-D: scratch bytes per item group, 0: default
+    void* scratch = nullptr;      // 3-D plane spectra of one item group
+    size_t scratch_bytes = 0;
     bool tune_overlap = false;    // reduce on the aux stream while the next chunk convolves
     hipStream_t aux = nullptr;    // reductions overlap the next chunk's convolution here
     hipEvent_t ev_conv[2] = {nullptr, nullptr};
@@ -52,7 +59,7 @@ struct pc_op {
     size_t work_bytes = 0;
     double* est = nullptr;    // estimator sums
     size_t est_bytes = 0;
-    int32_t* leaf_box = nullptr;   // [L][4] leaf boxes (2-D view), device
+    int32_t* leaf_box = nullptr;   // [L][6] leaf boxes, device
     // profiling: event pairs of launches not yet read
     bool profiling = false;
     struct Timed {
@@ -76,6 +83,7 @@ struct pc_op {
         for (hipEvent_t e : event_pool) hipEventDestroy(e);
         for (void* p : allocs) hipFree(p);
         if (slots) hipFree(slots);
+        if (scratch) hipFree(scratch);
         if (work) hipFree(work);
         if (est) hipFree(est);
     }
@@ -164,6 +172,84 @@ pc_status ensure_aux(pc_op* op) {
     return PC_OK;
 }
 
+// 3-D: vector chunks sized by the staging buffer; within a chunk, contiguous
+// item groups sized by the scratch buffer each run the three kernels of
+// pc_phases3.h; one reduction per chunk.
+pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                       hipStream_t s) {
+    const pc::Plan& P = op->plan;
+    const int64_t per = adj ? P.slot_adj : P.slot_fwd;
+    const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
+    const size_t cx_bytes = 2 * op->esz;
+    int64_t chunk = 1;
+    if (!plain) {
+        const int64_t cap = (int64_t)std::max<size_t>(1, kSlotCapBytes / per_bytes);
+        chunk = std::min<int64_t>(cap, std::max<int64_t>(1, op->tune_chunk > 0 ? op->tune_chunk : B));
+    }
+    const size_t scap = op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
+    const int n = (int)P.items3.size();
+    const int cols = pc::axis_cols(P.dtype);
+    auto scratch_of = [&](int i) { return P.items3[(size_t)i].scratch_off; };
+    auto scratch_end = [&](int i) {
+        const pc::Item3& I = P.items3[(size_t)i];
+        return I.scratch_off + (int64_t)I.nz * I.p.n0 * (I.p.m + 1);
+    };
+    // item groups for chunk vectors (smaller chunks reuse them)
+    std::vector<pc::Conv3Launch> groups;
+    size_t scratch_need = 0;
+    for (int i = 0; i < n;) {
+        int j = i + 1;
+        if (!plain)
+            while (j < n && (size_t)(scratch_end(j) - scratch_of(i)) * (size_t)chunk * cx_bytes <= scap) ++j;
+        pc::Conv3Launch L{};
+        L.adjoint = adj;
+        L.item_lo = i;
+        L.item_hi = j;
+        L.scratch_base = scratch_of(i);
+        for (int k = i; k < j; ++k) {
+            const pc::Item3& I = P.items3[(size_t)k];
+            const pc::Planes pl = pc::planes_of(I, adj);
+            L.max_gather = std::max(L.max_gather, pl.s_n);
+            L.max_write = std::max(L.max_write, pl.d_n);
+            L.max_tiles = std::max(L.max_tiles, (int)(((int64_t)I.p.n0 * (I.p.m + 1) + cols - 1) / cols));
+        }
+        scratch_need = std::max(scratch_need, (size_t)(scratch_end(j - 1) - scratch_of(i)) * (size_t)chunk * cx_bytes);
+        groups.push_back(L);
+        i = j;
+    }
+    pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    if (st != PC_OK) return st;
+    st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)");
+    if (st != PC_OK) return st;
+    const char* u = static_cast<const char*>(U);
+    char* o = static_cast<char*>(OUT);
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        const void* in = u + (size_t)b0 * ldu * op->esz;
+        void* out = o + (size_t)b0 * ldo * op->esz;
+        hipError_t e;
+        hipEvent_t ev;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            pc::Conv3Launch L = groups[g];
+            L.B = nb;
+            L.in = in;
+            L.ld_in = ldu;
+            L.slots = op->slots;
+            L.slot_stride = per;
+            L.scratch = op->scratch;
+            prof_begin(op, s, &ev);
+            e = pc::launch_conv3(op->dev, L, s);
+            if (e != hipSuccess) return hip_fail(e, "3-D conv launch");
+            prof_end(op, s, ev, 0, g == 0 ? nb : 0);
+        }
+        prof_begin(op, s, &ev);
+        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s);
+        if (e != hipSuccess) return hip_fail(e, "reduce launch");
+        prof_end(op, s, ev, 1, nb);
+    }
+    return PC_OK;
+}
+
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
                     hipStream_t s) {
     pc_status st = check_op(op);
@@ -174,6 +260,7 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
     if (ldu < N || ldo < N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
+    if (op->plan.d == 3) return run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s);
     const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     int64_t chunk = 1;
@@ -281,10 +368,11 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
         delete op;
         return hip_fail(e, "hipDeviceGetAttribute");
     }
-    if (op->plan.max_lds > lds_max) {
+    if (std::max(op->plan.max_lds, op->plan.max_lds_axis) > lds_max) {
         delete op;
         return fail(PC_ERR_UNSUPPORTED, "device LDS per workgroup (" + std::to_string(lds_max) +
-                                            " B) is below the plan's need (" + std::to_string(op->plan.max_lds) + " B)");
+                                            " B) is below the plan's need (" +
+                                            std::to_string(std::max(op->plan.max_lds, op->plan.max_lds_axis)) + " B)");
     }
     e = pc::set_kernel_attributes();
     if (e != hipSuccess) {
@@ -301,16 +389,20 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
         delete op;
         return st;
     }
-    void* d_leaf;
-    if ((st = upload(op, P.leaf_box, &d_leaf)) != PC_OK) {
+    void *d_leaf, *d_items3;
+    if ((st = upload(op, P.leaf_box, &d_leaf)) != PC_OK || (st = upload(op, P.items3, &d_items3)) != PC_OK) {
         delete op;
         return st;
     }
     pc::DevPlan& D = op->dev;
     D.items = static_cast<const pc::Item*>(d_items);
     D.n_items = (int)P.items.size();
+    D.items3 = static_cast<const pc::Item3*>(d_items3);
+    D.n_items3 = (int)P.items3.size();
     D.rows = P.rows;
     D.cols = P.cols;
+    D.planes = P.planes;
+    D.prow = P.prow;
     D.spec = d_spec;
     D.wts = d_wts;
     D.tw = d_tw;
@@ -323,6 +415,7 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
     D.slot_fwd = P.slot_fwd;
     D.slot_adj = P.slot_adj;
     D.max_lds = P.max_lds;
+    D.max_lds_axis = P.max_lds_axis;
     D.dtype = (int)dtype;
     op->leaf_box = static_cast<int32_t*>(d_leaf);
     e = hipDeviceSynchronize();
@@ -387,8 +480,8 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, co
     st = ensure(&est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 * n_part), "hipMalloc (estimator sums)");
     op->est = static_cast<double*>(est);
     if (st != PC_OK) return st;
-    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, N, Y, ldY, op->plan.rows, op->plan.cols, op->est,
-                       op->est + L, n_part, s);
+    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, N, Y, ldY, op->plan.planes, op->plan.prow,
+                                      op->plan.cols, op->est, op->est + L, n_part, s);
     if (e != hipSuccess) return hip_fail(e, "estimator launch");
     std::vector<double> h((size_t)L + 2 * n_part);
     e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
@@ -414,11 +507,12 @@ pc_status pc_get_stats(const pc_op* op, pc_stats* st) {
     st->n = P.N;
     st->r = P.r;
     st->n_leaves = P.L;
-    st->n_items = (int64_t)P.items.size();
+    st->n_items = (int64_t)(P.d == 3 ? P.items3.size() : P.items.size());
     st->sum_fft_points = P.sum_fft_points;
     st->alg_flops_per_rhs = P.alg_flops;
     st->kernel_elems = P.kernel_elems;
     int64_t spec_elems = 0;
+    for (const auto& I : P.items3) spec_elems += (int64_t)I.nz * I.p.n0 * (I.p.m + 1);
     {
         // one spectrum per patch: n0 x (m + 1) complex
         int last = -1;
@@ -453,6 +547,10 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
             return PC_OK;
         case PC_TUNE_OVERLAP:
             op->tune_overlap = value != 0;
+            return PC_OK;
+        case PC_TUNE_SCRATCH:
+            if (value < 0) return fail(PC_ERR_ARG, "scratch size out of range");
+            op->tune_scratch = value;
             return PC_OK;
         default:
             return fail(PC_ERR_ARG, "unknown tuning key");

@@ -12,6 +12,11 @@ constexpr int kMaxRadix = 16;
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kReduceCols = 256;       // reduce tile width (threads)
 constexpr int kReduceRows = 8;         // reduce tile height (accumulators per thread)
+constexpr int kAxisThreads = 256;      // threads of the 3-D axis-0 kernel
+
+// Columns (flattened axis-1 x axis-2 frequencies) per block of the 3-D
+// axis-0 kernel: the block holds nz x (cols + 1) complex values in LDS.
+constexpr int axis_cols(int dtype) { return dtype == 1 ? 32 : 64; }
 
 // One convolution work item: a patch (or a row piece of a patch) of the
 // 2-D product-convolution sum.  FFT index (i0, i1) <-> Omega point
@@ -35,6 +40,20 @@ struct Item {
     int64_t spec_off;    // spectrum (n0 x (m+1), slot-permuted)
     int64_t slot_fwd;    // forward staging offset (out_n0 x out_n1)
     int64_t slot_adj;    // adjoint staging offset (in_n0 x in_n1)
+};
+
+// 3-D work item: the patch's FFT box nz x n1 x n2 (n2 = 2m) is handled as
+// 2-D FFTs of its planes along axes 1 and 2 (in LDS, described by 'p', whose
+// boxes, weights strides and Omega origins refer to axes 1 and 2) plus an
+// axis-0 pass over the planes' spectra, which sit in a global scratch area of
+// nz x n1 x (m+1) complex values per vector.
+struct Item3 {
+    Item p;
+    int32_t nz, az, bz, twz;                 // axis-0 FFT length, radices, twiddle table
+    int32_t gz, in_offz, in_nz, out_nz;      // axis-0 origin, input box offset/extent, output extent
+    int32_t w_plane;                         // weight table plane stride (m1 * m2)
+    int32_t pad_;
+    int64_t scratch_off;                     // complex elements, per vector
 };
 
 // Output tile of the deterministic reduction and the staging boxes that

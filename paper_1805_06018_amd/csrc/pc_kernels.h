@@ -9,7 +9,10 @@ namespace pc {
 struct DevPlan {
     const Item* items;
     int n_items;
-    int rows, cols;                 // 2-D view of Omega
+    const Item3* items3;            // 3-D operators
+    int n_items3;
+    int rows, cols;                 // 2-D view of Omega (reduction)
+    int planes, prow;               // Omega as planes x prow x cols
     const void* spec;               // complex dtype
     const void* wts;                // dtype
     const void* tw;                 // complex dtype
@@ -20,7 +23,23 @@ struct DevPlan {
     const Box* cboxes_adj;
     int64_t slot_fwd, slot_adj;     // staging elements per vector
     int max_lds;
+    int max_lds_axis;               // 3-D axis-0 kernel
     int dtype;                      // 0 = f32, 1 = f64
+};
+
+// One 3-D launch set (plane-forward, axis-0, plane-inverse) over items
+// [item_lo, item_hi) and B vectors; the grids cover max_gather / max_write
+// planes and max_tiles column tiles per item.
+struct Conv3Launch {
+    bool adjoint;
+    int item_lo, item_hi, B;
+    const void* in;
+    int64_t ld_in;
+    void* slots;
+    int64_t slot_stride;
+    void* scratch;
+    int64_t scratch_base;
+    int max_gather, max_write, max_tiles;
 };
 
 // Convolution items -> staging (one workgroup per item and vector).
@@ -30,15 +49,18 @@ hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride,
                        hipStream_t s);
 
+// 3-D convolution items -> staging (three kernels, see pc_phases3.h).
+hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s);
+
 // Deterministic reduction of the staging boxes into the outputs.
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride,
                          void* out, int64_t ldo, hipStream_t s);
 
-// Estimator: per-leaf FP64 sums of squares of (Yt - Y) over q vectors and
+// Estimator: per-leaf (leaf_box [L][6]) FP64 sums of squares of (Yt - Y) over q vectors and
 // the totals sum (Yt - Y)^2 and sum Y^2 (per row-block partials).
 hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q,
                       const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
-                      int rows, int cols, double* leaf_sq, double* partials, int n_part,
+                      int planes, int prow, int cols, double* leaf_sq, double* partials, int n_part,
                       hipStream_t s);
 
 hipError_t set_kernel_attributes();

@@ -1,6 +1,6 @@
 // HIP kernels of the product-convolution apply for gfx950.
 #include "pc_kernels.h"
-#include "pc_phases.h"
+#include "pc_phases3.h"
 
 namespace pc {
 
@@ -55,6 +55,160 @@ __global__ __launch_bounds__(threads_for<T>()) void conv_kernel(ConvArgs<T> A) {
     phH(c, buf, tid, NT);
 }
 
+// ------------------------------------------------------------------- 3-D
+template <class T>
+struct Conv3Args {
+    const Item3* items;
+    int item_lo, n_items;   // items [item_lo, item_lo + n_items)
+    int B;
+    int adj;
+    int maxp;               // planes (plane kernels) or column tiles (axis kernel) per item in the grid
+    const cx<T>* spec;
+    const T* wts;
+    const cx<T>* tw;
+    const T* in;
+    int64_t ld_in;
+    T* slots;
+    int64_t slot_stride;
+    cx<T>* scratch;
+    int64_t scratch_base;   // scratch offset of item item_lo
+    int64_t pitch;          // Omega row pitch (n2)
+    int64_t plane_pitch;    // n1 * n2
+};
+
+// One workgroup per (item, vector, gathered plane), plane fastest.
+template <class T>
+__global__ __launch_bounds__(threads_for<T>()) void plane_fwd_kernel(Conv3Args<T> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    constexpr int NT = threads_for<T>();
+    const int q = blockIdx.x % A.maxp, l = blockIdx.x / A.maxp;
+    const int rhs = l % A.B, item = l / A.B;
+    if (item >= A.n_items) return;
+    const Item3 I = A.items[A.item_lo + item];
+    const bool adj = A.adj != 0;
+    const Planes pl = planes_of(I, adj);
+    if (q >= pl.s_n) return;
+    const Ctx<T> c = plane_ctx_gather<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
+                                         A.wts, A.spec, A.tw, A.pitch, A.plane_pitch);
+    const int tid = threadIdx.x;
+    phA(c, buf, tid, NT);
+    __syncthreads();
+    phB(c, buf, tid, NT);
+    __syncthreads();
+    phC(c, buf, tid, NT);
+    __syncthreads();
+    phD_fwd(c, buf, tid, NT);
+    __syncthreads();
+    plane_store(c, buf, item_scratch(A.scratch, A.scratch_base, I, A.B, rhs) + (int64_t)(pl.s_off + q) * plane_elems(I),
+                tid, NT);
+}
+
+// One workgroup per (item, column tile, vector); tiles are dealt to the
+// XCDs whole, with all their vectors, so a tile's spectrum columns are
+// fetched into one XCD's L2 and reused by every vector.
+template <class T>
+__global__ __launch_bounds__(kAxisThreads) void axis_kernel(Conv3Args<T> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    constexpr int NT = kAxisThreads;
+    constexpr int COLS = axis_cols(sizeof(T) == 8 ? 1 : 0);
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, l = bid >> 3;
+    const int task = xcd + 8 * (l / A.B), rhs = l % A.B;
+    const int item = task / A.maxp, tile = task - item * A.maxp;
+    if (item >= A.n_items) return;
+    const Item3 I = A.items[A.item_lo + item];
+    const int64_t pe = plane_elems(I);
+    const int c_lo = tile * COLS;
+    if (c_lo >= pe) return;
+    const int ncols = (int)(pe - c_lo < COLS ? pe - c_lo : COLS);
+    const Ctx<T> c = axis_ctx<T>(I, A.adj != 0, c_lo, ncols, axis_ld(COLS), A.spec, A.tw);
+    cx<T>* sc = item_scratch(A.scratch, A.scratch_base, I, A.B, rhs) + c_lo;
+    const int tid = threadIdx.x;
+    axis_load(c, buf, sc, pe, tid, NT);
+    __syncthreads();
+    phC(c, buf, tid, NT);
+    __syncthreads();
+    phD(c, buf, tid, NT);
+    __syncthreads();
+    phE(c, buf, tid, NT);
+    __syncthreads();
+    axis_store(c, buf, sc, pe, tid, NT);
+}
+
+// One workgroup per (item, vector, written plane), plane fastest.
+template <class T>
+__global__ __launch_bounds__(threads_for<T>()) void plane_inv_kernel(Conv3Args<T> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    constexpr int NT = threads_for<T>();
+    const int q = blockIdx.x % A.maxp, l = blockIdx.x / A.maxp;
+    const int rhs = l % A.B, item = l / A.B;
+    if (item >= A.n_items) return;
+    const Item3 I = A.items[A.item_lo + item];
+    const bool adj = A.adj != 0;
+    const Planes pl = planes_of(I, adj);
+    if (q >= pl.d_n) return;
+    const Ctx<T> c = plane_ctx_write<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
+                                        A.wts, A.spec, A.tw, A.pitch);
+    const int tid = threadIdx.x;
+    plane_load(c, buf, item_scratch(A.scratch, A.scratch_base, I, A.B, rhs) + (int64_t)(pl.d_off + q) * plane_elems(I),
+               tid, NT);
+    __syncthreads();
+    phD_inv(c, buf, tid, NT);
+    __syncthreads();
+    phE(c, buf, tid, NT);
+    __syncthreads();
+    phF(c, buf, tid, NT);
+    __syncthreads();
+    phG(c, buf, tid, NT);
+    __syncthreads();
+    phH(c, buf, tid, NT);
+}
+
+template <class T>
+static hipError_t conv3_t(const DevPlan& P, const Conv3Launch& L, hipStream_t s) {
+    Conv3Args<T> A;
+    A.items = P.items3;
+    A.item_lo = L.item_lo;
+    A.n_items = L.item_hi - L.item_lo;
+    A.B = L.B;
+    A.adj = L.adjoint ? 1 : 0;
+    A.spec = static_cast<const cx<T>*>(P.spec);
+    A.wts = static_cast<const T*>(P.wts);
+    A.tw = static_cast<const cx<T>*>(P.tw);
+    A.in = static_cast<const T*>(L.in);
+    A.ld_in = L.ld_in;
+    A.slots = static_cast<T*>(L.slots);
+    A.slot_stride = L.slot_stride;
+    A.scratch = static_cast<cx<T>*>(L.scratch);
+    A.scratch_base = L.scratch_base;
+    A.pitch = P.cols;
+    A.plane_pitch = (int64_t)P.prow * P.cols;
+    if (A.n_items <= 0 || A.B <= 0) return hipSuccess;
+    const int64_t per = (int64_t)A.n_items * A.B;
+    const int64_t g_fwd = per * L.max_gather, g_inv = per * L.max_write;
+    const int64_t g_axis = 8 * (((int64_t)A.n_items * L.max_tiles + 7) / 8) * A.B;
+    if (g_fwd > 0x7fffffff || g_inv > 0x7fffffff || g_axis > 0x7fffffff) return hipErrorInvalidValue;
+    A.maxp = L.max_gather;
+    hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3((unsigned)g_fwd), dim3(threads_for<T>()), P.max_lds, s, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    A.maxp = L.max_tiles;
+    hipLaunchKernelGGL(axis_kernel<T>, dim3((unsigned)g_axis), dim3(kAxisThreads), P.max_lds_axis, s, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    A.maxp = L.max_write;
+    hipLaunchKernelGGL(plane_inv_kernel<T>, dim3((unsigned)g_inv), dim3(threads_for<T>()), P.max_lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s) {
+    if (P.dtype == 1) return conv3_t<double>(P, L, s);
+    return conv3_t<float>(P, L, s);
+}
+
 template <class T>
 __global__ __launch_bounds__(kReduceCols) void reduce_kernel(const Tile* tiles, const Box* cboxes, const T* slots,
                                                              int64_t slot_stride, T* out, int64_t ldo, int64_t pitch) {
@@ -80,22 +234,28 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // One block per leaf: sum over probes i and leaf points x of (Yt - Y)^2, in
-// FP64, in a fixed order (thread-strided loop, then a fixed tree).
+// FP64, in a fixed order (probe, plane, then a thread-strided loop over the
+// plane's box, then a fixed tree).  Omega is planes x prow x cols.
 template <class T>
 __global__ __launch_bounds__(kEstThreads) void est_leaf_kernel(const int32_t* leaf_box, int q, const T* Yt, int64_t ldt,
-                                                               const T* Y, int64_t ldy, int64_t pitch, double* leaf_sq) {
+                                                               const T* Y, int64_t ldy, int64_t prow, int64_t pitch,
+                                                               double* leaf_sq) {
     __shared__ double sh[kEstThreads];
     const int c = blockIdx.x;
-    const int lo0 = leaf_box[4 * c], lo1 = leaf_box[4 * c + 1], n0 = leaf_box[4 * c + 2], n1 = leaf_box[4 * c + 3];
+    const int32_t* b = leaf_box + 6 * c;
+    const int lz = b[0], lo0 = b[1], lo1 = b[2], nz = b[3], n0 = b[4], n1 = b[5];
     const int64_t cnt = (int64_t)n0 * n1;
     double acc = 0.0;
     for (int i = 0; i < q; ++i) {
         const T* a = Yt + (int64_t)i * ldt;
-        const T* b = Y + (int64_t)i * ldy;
-        for (int64_t e = threadIdx.x; e < cnt; e += kEstThreads) {
-            const int64_t idx = (int64_t)(lo0 + e / n1) * pitch + lo1 + e % n1;
-            const double dv = (double)a[idx] - (double)b[idx];
-            acc += dv * dv;
+        const T* y = Y + (int64_t)i * ldy;
+        for (int z = 0; z < nz; ++z) {
+            const int64_t base = ((int64_t)(lz + z) * prow + lo0) * pitch + lo1;
+            for (int64_t e = threadIdx.x; e < cnt; e += kEstThreads) {
+                const int64_t idx = base + (e / n1) * pitch + e % n1;
+                const double dv = (double)a[idx] - (double)y[idx];
+                acc += dv * dv;
+            }
         }
     }
     const double s = block_sum(acc, sh);
@@ -180,20 +340,20 @@ hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slot
 }
 
 hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, const void* Yt, int64_t ldt,
-                      const void* Y, int64_t ldy, int rows, int cols, double* leaf_sq, double* partials, int n_part,
-                      hipStream_t s) {
-    const int64_t n_total = (int64_t)rows * cols;
+                      const void* Y, int64_t ldy, int planes, int prow, int cols, double* leaf_sq, double* partials,
+                      int n_part, hipStream_t s) {
+    const int64_t n_total = (int64_t)planes * prow * cols;
     if (dtype == 1) {
         hipLaunchKernelGGL(est_leaf_kernel<double>, dim3(n_leaves), dim3(kEstThreads), 0, s, leaf_box, q,
-                           static_cast<const double*>(Yt), ldt, static_cast<const double*>(Y), ldy, (int64_t)cols,
-                           leaf_sq);
+                           static_cast<const double*>(Yt), ldt, static_cast<const double*>(Y), ldy, (int64_t)prow,
+                           (int64_t)cols, leaf_sq);
         hipLaunchKernelGGL(est_total_kernel<double>, dim3(n_part), dim3(kEstThreads), 0, s, q,
                            static_cast<const double*>(Yt), ldt, static_cast<const double*>(Y), ldy, n_total, n_part,
                            partials);
     } else {
         hipLaunchKernelGGL(est_leaf_kernel<float>, dim3(n_leaves), dim3(kEstThreads), 0, s, leaf_box, q,
-                           static_cast<const float*>(Yt), ldt, static_cast<const float*>(Y), ldy, (int64_t)cols,
-                           leaf_sq);
+                           static_cast<const float*>(Yt), ldt, static_cast<const float*>(Y), ldy, (int64_t)prow,
+                           (int64_t)cols, leaf_sq);
         hipLaunchKernelGGL(est_total_kernel<float>, dim3(n_part), dim3(kEstThreads), 0, s, q,
                            static_cast<const float*>(Yt), ldt, static_cast<const float*>(Y), ldy, n_total, n_part,
                            partials);
@@ -202,11 +362,16 @@ hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, c
 }
 
 hipError_t set_kernel_attributes() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&conv_kernel<float>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&conv_kernel<double>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&conv_kernel<float>),      reinterpret_cast<const void*>(&conv_kernel<double>),
+        reinterpret_cast<const void*>(&plane_fwd_kernel<float>), reinterpret_cast<const void*>(&plane_fwd_kernel<double>),
+        reinterpret_cast<const void*>(&axis_kernel<float>),      reinterpret_cast<const void*>(&axis_kernel<double>),
+        reinterpret_cast<const void*>(&plane_inv_kernel<float>), reinterpret_cast<const void*>(&plane_inv_kernel<double>)};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pc

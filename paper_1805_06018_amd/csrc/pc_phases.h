@@ -53,6 +53,7 @@ struct Ctx {
     T* dst;                           // staging box of this item and vector
     const T* w;                       // weight table of the item's input box
     const cx<T>* spec;
+    int64_t spec_ld;                  // spectrum row stride (m + 1 for 2-D items)
     const cx<T>* tw0;                 // w_{n0}^e
     const cx<T>* twm;                 // w_m^e
     const cx<T>* tw2m;                // w_{2m}^e
@@ -82,6 +83,7 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
     c.src = in_vec;
     c.w = wts + it.w_off;
     c.spec = spec + it.spec_off;
+    c.spec_ld = it.m + 1;
     c.tw0 = tw + it.tw0;
     c.twm = tw + it.twm;
     c.tw2m = tw + it.tw2m;
@@ -274,30 +276,57 @@ __host__ __device__ inline void phC(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 }
 
 // ---------------------------------------------------------------- phase D
-template <int B0, class T>
+// MODE 0: column pass 2, product with the spectrum, inverse column pass 2;
+// MODE 1: column pass 2 only (forward 2-D FFT of a plane);
+// MODE 2: inverse column pass 2 only (inverse 2-D FFT of a plane).
+template <int MODE, int B0, class T>
 __host__ __device__ inline void phD_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
     const int a0 = c.it.a0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * a0;
     for (int t = tid; t < ntask; t += nth) {
         const int k1 = fdiv(t, c.inv_nc), col = t - k1 * NC;
         cx<T>* p = buf + (int64_t)(B0 * k1) * ld + col;
-        const cx<T>* sp = c.spec + (int64_t)(B0 * k1) * NC + col;
-        cx<T> s[B0], x[B0];
+        cx<T> x[B0];
+        if (MODE == 0) {
+            const cx<T>* sp = c.spec + (int64_t)(B0 * k1) * c.spec_ld + col;
+            cx<T> s[B0];
 #pragma unroll
-        for (int k0 = 0; k0 < B0; ++k0) s[k0] = sp[(int64_t)k0 * NC];
+            for (int k0 = 0; k0 < B0; ++k0) s[k0] = sp[(int64_t)k0 * c.spec_ld];
 #pragma unroll
-        for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
-        Dft<B0, -1>::run(x);
+            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
+            Dft<B0, -1>::run(x);
 #pragma unroll
-        for (int k0 = 0; k0 < B0; ++k0) x[k0] = c.adj ? cmulc(x[k0], s[k0]) : cmul(x[k0], s[k0]);
-        Dft<B0, 1>::run(x);
+            for (int k0 = 0; k0 < B0; ++k0) x[k0] = c.adj ? cmulc(x[k0], s[k0]) : cmul(x[k0], s[k0]);
+            Dft<B0, 1>::run(x);
+        } else {
+#pragma unroll
+            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
+            if (MODE == 1)
+                Dft<B0, -1>::run(x);
+            else
+                Dft<B0, 1>::run(x);
+        }
 #pragma unroll
         for (int k0 = 0; k0 < B0; ++k0) p[(int64_t)k0 * ld] = x[k0];
     }
 }
+template <int B0, class T>
+__host__ __device__ inline void phD0_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) { phD_r<0, B0>(c, buf, tid, nth); }
+template <int B0, class T>
+__host__ __device__ inline void phD1_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) { phD_r<1, B0>(c, buf, tid, nth); }
+template <int B0, class T>
+__host__ __device__ inline void phD2_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) { phD_r<2, B0>(c, buf, tid, nth); }
 template <class T>
 __host__ __device__ inline void phD(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    PC_RADIX_SWITCH(c.it.b0, phD_r, c, buf, tid, nth);
+    PC_RADIX_SWITCH(c.it.b0, phD0_r, c, buf, tid, nth);
+}
+template <class T>
+__host__ __device__ inline void phD_fwd(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.b0, phD1_r, c, buf, tid, nth);
+}
+template <class T>
+__host__ __device__ inline void phD_inv(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    PC_RADIX_SWITCH(c.it.b0, phD2_r, c, buf, tid, nth);
 }
 
 // ---------------------------------------------------------------- phase E

@@ -13,8 +13,6 @@ namespace pc {
 
 namespace {
 
-using cd = std::complex<double>;
-constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // ------------------------------------------------------------------ FFT sizes
 const int kRadices[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16};
@@ -47,8 +45,6 @@ int next_fft_size(int need) {
     }
     return -1;
 }
-
-namespace {
 
 int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
 
@@ -99,6 +95,8 @@ std::vector<cd> twiddles(int n) {
     }
     return W;
 }
+
+namespace {
 
 // -------------------------------------------------------- harmonic weights
 // Hat of point 'pos' among sorted cut positions, evaluated on [c0, c1].
@@ -221,7 +219,61 @@ void leaf_weights_2d(const int64_t* lo, const int64_t* hi, const std::vector<int
     }
 }
 
+
 }  // namespace
+
+// Reduction tiles of the rows x cols view and, for every tile, the staging
+// boxes that overlap it in ascending box order (boxes are listed in ascending
+// item order, so every tile sums its contributors in ascending patch order).
+static bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<Tile>& tiles,
+                 std::vector<int32_t>& contrib, std::string& err) {
+    const int ntr = (rows + kReduceRows - 1) / kReduceRows, ntc = (cols + kReduceCols - 1) / kReduceCols;
+    std::vector<std::vector<int32_t>> per((size_t)ntr * ntc);
+    for (size_t i = 0; i < boxes.size(); ++i) {
+        const Box& b = boxes[i];
+        if (b.n0 <= 0 || b.n1 <= 0) continue;
+        for (int tr = b.lo0 / kReduceRows; tr <= (b.lo0 + b.n0 - 1) / kReduceRows; ++tr)
+            for (int tc = b.lo1 / kReduceCols; tc <= (b.lo1 + b.n1 - 1) / kReduceCols; ++tc)
+                per[(size_t)tr * ntc + tc].push_back((int32_t)i);
+    }
+    tiles.clear();
+    contrib.clear();
+    size_t total = 0;
+    for (const auto& v : per) total += v.size();
+    if (total > (size_t)INT32_MAX) {
+        err = "too many staging contributions for the reduction tables";
+        return false;
+    }
+    contrib.reserve(total);
+    for (int tr = 0; tr < ntr; ++tr)
+        for (int tc = 0; tc < ntc; ++tc) {
+            Tile t;
+            t.r0 = tr * kReduceRows;
+            t.c0 = tc * kReduceCols;
+            t.nr = std::min(kReduceRows, rows - t.r0);
+            t.nc = std::min(kReduceCols, cols - t.c0);
+            t.beg = (int32_t)contrib.size();
+            const auto& v = per[(size_t)tr * ntc + tc];
+            contrib.insert(contrib.end(), v.begin(), v.end());
+            t.end = (int32_t)contrib.size();
+            tiles.push_back(t);
+        }
+    return true;
+}
+
+// Tiles, contributor lists and per-contributor boxes of both directions.
+bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err) {
+    if (!build_tiles(bf, p.rows, p.cols, p.tiles_fwd, p.contrib_fwd, err) ||
+        !build_tiles(ba, p.rows, p.cols, p.tiles_adj, p.contrib_adj, err))
+        return false;
+    p.boxes_fwd = std::move(bf);
+    p.boxes_adj = std::move(ba);
+    p.cboxes_fwd.resize(p.contrib_fwd.size());
+    for (size_t i = 0; i < p.contrib_fwd.size(); ++i) p.cboxes_fwd[i] = p.boxes_fwd[(size_t)p.contrib_fwd[i]];
+    p.cboxes_adj.resize(p.contrib_adj.size());
+    for (size_t i = 0; i < p.contrib_adj.size(); ++i) p.cboxes_adj[i] = p.boxes_adj[(size_t)p.contrib_adj[i]];
+    return true;
+}
 
 // ======================================================================
 pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
@@ -365,10 +417,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             }
         }
     }
-    if (d == 3) {
-        err = "3-D operators are not implemented by this build";
-        return PC_ERR_UNSUPPORTED;
-    }
+    if (d == 3) return build_plan_3d(a, p, err);
 
     // ------------------------------------------------------- 2-D view
     // d = 1 is handled as a single row: axis 0 of the view has extent 1.
@@ -682,58 +731,24 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     p.kernel_elems = kernel_elems;
     p.alg_flops = alg_flops;
     // --------------------------------------------------- reduction tiles
-    auto build_tiles = [&](bool adj, std::vector<Tile>& tiles, std::vector<int32_t>& contrib, std::vector<Box>& boxes) {
-        boxes.resize(p.items.size());
-        for (size_t i = 0; i < p.items.size(); ++i) {
-            const Item& it = p.items[i];
-            Box b;
-            if (!adj) {
-                b.lo0 = it.g0;
-                b.lo1 = it.g1;
-                b.n0 = it.out_n0;
-                b.n1 = it.out_n1;
-                b.off = it.slot_fwd;
-            } else {
-                b.lo0 = it.g0 + it.in_off0;
-                b.lo1 = it.g1 + it.in_off1;
-                b.n0 = it.in_n0;
-                b.n1 = it.in_n1;
-                b.off = it.slot_adj;
-            }
-            boxes[i] = b;
-        }
-        tiles.clear();
-        contrib.clear();
-        for (int r0 = 0; r0 < nr; r0 += kReduceRows)
-            for (int cc0 = 0; cc0 < nc; cc0 += kReduceCols) {
-                Tile t;
-                t.r0 = r0;
-                t.c0 = cc0;
-                t.nr = (int)std::min<int64_t>(kReduceRows, nr - r0);
-                t.nc = (int)std::min<int64_t>(kReduceCols, nc - cc0);
-                t.beg = (int32_t)contrib.size();
-                for (size_t i = 0; i < boxes.size(); ++i) {
-                    const Box& b = boxes[i];
-                    if (b.lo0 < r0 + t.nr && b.lo0 + b.n0 > r0 && b.lo1 < cc0 + t.nc && b.lo1 + b.n1 > cc0)
-                        contrib.push_back((int32_t)i);
-                }
-                t.end = (int32_t)contrib.size();
-                tiles.push_back(t);
-            }
-    };
-    build_tiles(false, p.tiles_fwd, p.contrib_fwd, p.boxes_fwd);
-    build_tiles(true, p.tiles_adj, p.contrib_adj, p.boxes_adj);
-    // the reduction reads the staging box of each contributor directly
-    p.cboxes_fwd.resize(p.contrib_fwd.size());
-    for (size_t i = 0; i < p.contrib_fwd.size(); ++i) p.cboxes_fwd[i] = p.boxes_fwd[(size_t)p.contrib_fwd[i]];
-    p.cboxes_adj.resize(p.contrib_adj.size());
-    for (size_t i = 0; i < p.contrib_adj.size(); ++i) p.cboxes_adj[i] = p.boxes_adj[(size_t)p.contrib_adj[i]];
-    p.leaf_box.resize(4 * L);
+    std::vector<Box> bf(p.items.size()), ba(p.items.size());
+    for (size_t i = 0; i < p.items.size(); ++i) {
+        const Item& it = p.items[i];
+        bf[i] = Box{it.g0, it.g1, it.out_n0, it.out_n1, it.slot_fwd};
+        ba[i] = Box{it.g0 + it.in_off0, it.g1 + it.in_off1, it.in_n0, it.in_n1, it.slot_adj};
+    }
+    if (!finish_tiles(p, bf, ba, err)) return PC_ERR_UNSUPPORTED;
+    p.planes = 1;
+    p.prow = p.rows;
+    p.leaf_box.resize(6 * L);
     for (int64_t c = 0; c < L; ++c) {
-        p.leaf_box[4 * c] = (int32_t)LO[2 * c];
-        p.leaf_box[4 * c + 1] = (int32_t)LO[2 * c + 1];
-        p.leaf_box[4 * c + 2] = (int32_t)(HI[2 * c] - LO[2 * c] + 1);
-        p.leaf_box[4 * c + 3] = (int32_t)(HI[2 * c + 1] - LO[2 * c + 1] + 1);
+        int32_t* b = &p.leaf_box[6 * c];
+        b[0] = 0;
+        b[1] = (int32_t)LO[2 * c];
+        b[2] = (int32_t)LO[2 * c + 1];
+        b[3] = 1;
+        b[4] = (int32_t)(HI[2 * c] - LO[2 * c] + 1);
+        b[5] = (int32_t)(HI[2 * c + 1] - LO[2 * c + 1] + 1);
     }
     return PC_OK;
 }

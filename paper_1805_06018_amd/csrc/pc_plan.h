@@ -5,6 +5,7 @@
 // emulation build.
 #pragma once
 #include <stdint.h>
+#include <complex>
 #include <string>
 #include <vector>
 #include "../../include/pc.h"
@@ -31,11 +32,15 @@ struct Plan {
     int d = 0;
     int64_t shape[3] = {1, 1, 1};
     int64_t N = 0;
-    int rows = 1, cols = 1;          // 2-D view of Omega (d = 1: one row)
+    int rows = 1, cols = 1;          // 2-D view of Omega (d = 1: one row; d = 3: rows = n0 * n1)
+    int planes = 1, prow = 1;        // Omega as planes x prow x cols (d < 3: one plane of 'rows' rows)
     int dtype = 0;
     uint32_t flags = 0;
     int64_t r = 0, L = 0;
-    std::vector<Item> items;
+    std::vector<Item> items;         // d = 1, 2
+    std::vector<Item3> items3;       // d = 3
+    int64_t scratch_per_vec = 0;     // d = 3: complex scratch elements per vector over all items
+    int max_lds_axis = 0;            // d = 3: LDS of the axis-0 kernel
     std::vector<double> spec;        // interleaved complex, FP64, pre-scaled
     std::vector<double> wts;         // FP64 weight tables
     std::vector<double> tw;          // interleaved complex twiddle tables
@@ -43,7 +48,7 @@ struct Plan {
     std::vector<int32_t> contrib_fwd, contrib_adj;
     std::vector<Box> boxes_fwd, boxes_adj;     // staging box of every item
     std::vector<Box> cboxes_fwd, cboxes_adj;   // staging box of every tile contributor
-    std::vector<int32_t> leaf_box;   // [L][4]: lo0, lo1, n0, n1 in the 2-D view
+    std::vector<int32_t> leaf_box;   // [L][6]: plane, row, col origin and extents (planes x prow x cols view)
     int64_t slot_fwd = 0, slot_adj = 0;   // staging elements per vector
     int max_lds = 0;
     // statistics
@@ -58,5 +63,20 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err);
 // FFT lengths usable by the kernels: n = a * b with a, b radices.
 bool fft_factor(int n, int* a, int* b);
 int next_fft_size(int need);
+
+// ---- planner internals shared by the 2-D and 3-D planners
+using cd = std::complex<double>;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+// slot of frequency k in the two-pass order of a length a * b transform
+int perm_slot(int k, int a, int b);
+int smallest_7smooth(int64_t need);
+// y[k] = sum_j x[j stride] w_n^(j k) (FP64, any length; W = twiddles(Wn), n | Wn)
+void fft_rec(const cd* x, int64_t stride, int n, cd* y, const std::vector<cd>& W, int Wn, std::vector<cd>& scratch);
+std::vector<cd> twiddles(int n);
+// reduction tiles and contributor boxes of both directions from the
+// per-item staging boxes (ascending item order)
+bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);
+// 3-D operators (called by build_plan after the argument checks)
+pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err);
 
 }  // namespace pc

@@ -1,0 +1,350 @@
+// Host planner of 3-D product-convolution operators (see pc_plan.h).
+//
+// Conforming leaves only: every leaf carries exactly its 2^d' corners (d' the
+// number of axes along which it has positive width), so the harmonic weights
+// of Sec. 2.4 are the trilinear hats of the leaf.  Tilings with hanging nodes
+// in 3-D are rejected with PC_ERR_UNSUPPORTED.
+//
+// One work item per patch, no pieces: the FFT box nz x n1 x 2m is processed
+// plane by plane (2-D FFTs along axes 1, 2 in LDS) with an axis-0 pass over
+// the planes' spectra in a global scratch area.
+#include "pc_plan.h"
+#include "pc_phases3.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+
+namespace pc {
+
+namespace {
+
+// complex row length m of the real axis-2 transform: m <= 128 and the
+// second radix at most 10 (row pass 2 of the kernels)
+int next_row_len(int need) {
+    for (int m = std::max(need, 1); m <= 128; ++m) {
+        int a, b;
+        if (fft_factor(m, &a, &b) && b <= 10) return m;
+    }
+    return -1;
+}
+
+struct Geo3 {
+    pc_status st = PC_OK;
+    std::string err;
+    Item3 it;
+    int64_t I_lo[3], m[3], zlo[3], zhi[3];
+    double flops = 0.0;
+    int64_t kel = 0;
+    int lds_plane = 0, lds_axis = 0;
+};
+
+}  // namespace
+
+pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
+    const int64_t* n = a.shape;
+    const int64_t L = a.n_leaves, r = a.r;
+    if (n[0] * n[1] > INT32_MAX || n[2] > INT32_MAX) {
+        err = "3-D domain too large for the reduction view";
+        return PC_ERR_ARG;
+    }
+    p.rows = (int)(n[0] * n[1]);
+    p.cols = (int)n[2];
+    p.planes = (int)n[0];
+    p.prow = (int)n[1];
+    const int64_t* Pt = a.points;
+    const int64_t* Rd = a.radius;
+    auto lo = [&](int64_t c, int i) { return a.leaf_lo[c * 3 + i]; };
+    auto hi = [&](int64_t c, int i) { return a.leaf_hi[c * 3 + i]; };
+    // ------------------------------------------------ cells and neighbours
+    std::vector<std::vector<int64_t>> leaf_pts(L), cells(r);
+    for (int64_t c = 0; c < L; ++c)
+        for (int64_t k = 0; k < r; ++k) {
+            bool in = true;
+            for (int i = 0; i < 3 && in; ++i) in = Pt[k * 3 + i] >= lo(c, i) && Pt[k * 3 + i] <= hi(c, i);
+            if (in) {
+                leaf_pts[c].push_back(k);
+                cells[k].push_back(c);
+            }
+        }
+    for (int64_t c = 0; c < L; ++c) {
+        int live = 0;
+        for (int i = 0; i < 3; ++i) live += hi(c, i) > lo(c, i);
+        if ((int64_t)leaf_pts[c].size() != (int64_t)(1 << live)) {
+            err = "leaf " + std::to_string(c) +
+                  " has hanging nodes: 3-D operators need a conforming tiling (trilinear weights)";
+            return PC_ERR_UNSUPPORTED;
+        }
+    }
+    std::vector<std::vector<int64_t>> nbrs(r);
+    std::vector<int64_t> Ulo(3 * r, INT64_MAX), Uhi(3 * r, INT64_MIN);
+    for (int64_t k = 0; k < r; ++k) {
+        std::set<int64_t> s;
+        for (int64_t c : cells[k]) {
+            for (int64_t j : leaf_pts[c]) s.insert(j);
+            for (int i = 0; i < 3; ++i) {
+                Ulo[3 * k + i] = std::min(Ulo[3 * k + i], lo(c, i));
+                Uhi[3 * k + i] = std::max(Uhi[3 * k + i], hi(c, i));
+            }
+        }
+        nbrs[k].assign(s.begin(), s.end());
+    }
+    // ----------------------------------------- weights: trilinear hats
+    std::vector<int64_t> w_base(r + 1, 0);
+    for (int64_t k = 0; k < r; ++k) {
+        int64_t v = 1;
+        for (int i = 0; i < 3; ++i) v *= Uhi[3 * k + i] - Ulo[3 * k + i] + 1;
+        w_base[k + 1] = w_base[k] + v;
+    }
+    std::vector<double> W((size_t)w_base[r], 0.0);
+    for (int64_t c = 0; c < L; ++c) {
+        double H[3];
+        for (int i = 0; i < 3; ++i) H[i] = (double)(hi(c, i) - lo(c, i));
+        for (int64_t k : leaf_pts[c]) {
+            const int64_t um1 = Uhi[3 * k + 1] - Ulo[3 * k + 1] + 1, um2 = Uhi[3 * k + 2] - Ulo[3 * k + 2] + 1;
+            for (int64_t y0 = lo(c, 0); y0 <= hi(c, 0); ++y0) {
+                const double f0 = H[0] > 0 ? 1.0 - std::fabs((double)(y0 - Pt[k * 3])) / H[0] : 1.0;
+                for (int64_t y1 = lo(c, 1); y1 <= hi(c, 1); ++y1) {
+                    const double f1 = H[1] > 0 ? 1.0 - std::fabs((double)(y1 - Pt[k * 3 + 1])) / H[1] : 1.0;
+                    double* row = &W[(size_t)(w_base[k] + ((y0 - Ulo[3 * k]) * um1 + (y1 - Ulo[3 * k + 1])) * um2)];
+                    for (int64_t y2 = lo(c, 2); y2 <= hi(c, 2); ++y2) {
+                        const double f2 =
+                            H[2] > 0 ? 1.0 - std::fabs((double)(y2 - Pt[k * 3 + 2])) / H[2] : 1.0;
+                        row[y2 - Ulo[3 * k + 2]] = f0 * f1 * f2;
+                    }
+                }
+            }
+        }
+    }
+    p.wts = std::move(W);
+    // ------------------------------------------- geometry of every patch
+    const bool extend = !(a.flags & PC_NO_EXTEND);
+    const size_t csz = (a.dtype == PC_F64) ? 16 : 8;
+    const int acols = axis_cols(a.dtype);
+    const int ld_axis = axis_ld(acols);
+    std::vector<Geo3> geo((size_t)r);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < r; ++k) {
+        Geo3& g = geo[(size_t)k];
+        int64_t K[3], Rm[3], olo[3], ohi[3];
+        for (int i = 0; i < 3; ++i) {
+            g.I_lo[i] = Ulo[3 * k + i];
+            g.m[i] = Uhi[3 * k + i] - Ulo[3 * k + i] + 1;
+            Rm[i] = Rd[k * 3 + i];
+        }
+        if (extend)
+            for (int64_t j : nbrs[k])
+                for (int i = 0; i < 3; ++i) Rm[i] = std::max(Rm[i], Rd[j * 3 + i]);
+        g.kel = 1;
+        for (int i = 0; i < 3; ++i) {
+            g.zlo[i] = std::max(-Rm[i], -(Uhi[3 * k + i]));
+            g.zhi[i] = std::min(Rm[i], n[i] - 1 - g.I_lo[i]);
+            K[i] = g.zhi[i] - g.zlo[i] + 1;
+            olo[i] = std::max(g.I_lo[i] + g.zlo[i], (int64_t)0);
+            ohi[i] = std::min(Uhi[3 * k + i] + g.zhi[i], n[i] - 1);
+            g.kel *= 2 * Rd[k * 3 + i] + 1;
+        }
+        const int nz = next_fft_size((int)std::min<int64_t>(g.m[0] + K[0] - 1, 1 << 20));
+        const int n1 = next_fft_size((int)std::min<int64_t>(g.m[1] + K[1] - 1, 1 << 20));
+        const int M = next_row_len((int)std::min<int64_t>((g.m[2] + K[2]) / 2, 1 << 20));
+        if (nz < 0 || n1 < 0 || M < 0) {
+            g.st = PC_ERR_UNSUPPORTED;
+            g.err = "patch " + std::to_string(k) + " needs an FFT longer than the kernels support";
+            continue;
+        }
+        int ld = M + 1;
+        if (ld % 2 == 0) ++ld;
+        g.lds_plane = (int)((size_t)n1 * ld * csz);
+        g.lds_axis = (int)((size_t)nz * ld_axis * csz);
+        if (g.lds_plane > kLdsBytes || g.lds_axis > kLdsBytes) {
+            g.st = PC_ERR_UNSUPPORTED;
+            g.err = "patch " + std::to_string(k) + " does not fit the LDS-resident plane FFT";
+            continue;
+        }
+        Item3& it = g.it;
+        std::memset(&it, 0, sizeof(it));
+        Item& q = it.p;
+        q.n0 = n1;
+        fft_factor(n1, &q.a0, &q.b0);
+        q.m = M;
+        fft_factor(M, &q.am, &q.bm);
+        q.ld = ld;
+        q.g0 = (int32_t)olo[1];
+        q.g1 = (int32_t)olo[2];
+        q.in_off0 = (int32_t)(g.I_lo[1] - olo[1]);
+        q.in_off1 = (int32_t)(g.I_lo[2] - olo[2]);
+        q.in_n0 = (int32_t)g.m[1];
+        q.in_n1 = (int32_t)g.m[2];
+        q.out_n0 = (int32_t)(ohi[1] - olo[1] + 1);
+        q.out_n1 = (int32_t)(ohi[2] - olo[2] + 1);
+        q.patch = (int32_t)k;
+        q.w_ld = (int32_t)g.m[2];
+        q.w_off = w_base[k];
+        it.nz = nz;
+        fft_factor(nz, &it.az, &it.bz);
+        it.gz = (int32_t)olo[0];
+        it.in_offz = (int32_t)(g.I_lo[0] - olo[0]);
+        it.in_nz = (int32_t)g.m[0];
+        it.out_nz = (int32_t)(ohi[0] - olo[0] + 1);
+        it.w_plane = (int32_t)(g.m[1] * g.m[2]);
+        if (it.in_offz < 0 || it.in_offz + it.in_nz > nz || it.out_nz > nz || q.in_off0 < 0 ||
+            q.in_off0 + q.in_n0 > n1 || q.out_n0 > n1 || q.in_off1 < 0 || q.in_off1 + q.in_n1 > 2 * M ||
+            q.out_n1 > 2 * M) {
+            g.st = PC_ERR_ARG;
+            g.err = "internal planning error (FFT box too small) at patch " + std::to_string(k);
+            continue;
+        }
+        int64_t nn = 1, I = 1, O = 1;
+        for (int i = 0; i < 3; ++i) {
+            nn *= smallest_7smooth(g.m[i] + K[i] - 1);
+            I *= g.m[i];
+            O *= ohi[i] - olo[i] + 1;
+        }
+        g.flops = 5.0 * nn * std::log2((double)nn) + 3.0 * nn + (double)I + (double)O;
+    }
+    // ----------------------------------- offsets (patch order) and tables
+    std::map<int, int> tw_off;
+    auto want_tw = [&](int len) {
+        auto f = tw_off.find(len);
+        if (f != tw_off.end()) return f->second;
+        int off = (int)(p.tw.size() / 2);
+        tw_off[len] = off;
+        for (int e = 0; e < len; ++e) {
+            double ang = 2.0 * kPi * (double)e / (double)len;
+            p.tw.push_back(std::cos(ang));
+            p.tw.push_back(-std::sin(ang));
+        }
+        return off;
+    };
+    int64_t spec_total = 0;
+    for (int64_t k = 0; k < r; ++k) {
+        Geo3& g = geo[(size_t)k];
+        if (g.st != PC_OK) {
+            err = g.err;
+            return g.st;
+        }
+        Item3& it = g.it;
+        Item& q = it.p;
+        q.tw0 = want_tw(q.n0);
+        q.twm = want_tw(q.m);
+        q.tw2m = want_tw(2 * q.m);
+        it.twz = want_tw(it.nz);
+        const int64_t plane = (int64_t)q.n0 * (q.m + 1);
+        q.spec_off = spec_total;
+        spec_total += (int64_t)it.nz * plane;
+        it.scratch_off = p.scratch_per_vec;
+        p.scratch_per_vec += (int64_t)it.nz * plane;
+        q.slot_fwd = p.slot_fwd;
+        q.slot_adj = p.slot_adj;
+        p.slot_fwd += (int64_t)it.out_nz * q.out_n0 * q.out_n1;
+        p.slot_adj += (int64_t)it.in_nz * q.in_n0 * q.in_n1;
+        p.sum_fft_points += (int64_t)it.nz * q.n0 * 2 * q.m;
+        p.alg_flops += g.flops;
+        p.kernel_elems += g.kel;
+        p.max_lds = std::max(p.max_lds, g.lds_plane);
+        p.max_lds_axis = std::max(p.max_lds_axis, g.lds_axis);
+        p.items3.push_back(it);
+    }
+    // ------------------------------------------- FP64 spectra, in place
+    p.spec.assign((size_t)(2 * spec_total), 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < r; ++k) {
+        const Geo3& g = geo[(size_t)k];
+        const Item3& it = p.items3[(size_t)k];
+        const int nz = it.nz, n1 = it.p.n0, M = it.p.m, n2 = 2 * M;
+        // extended kernel phi_k^E (Sec. 2.5) on [zlo, zhi], placed circularly
+        auto defined = [&](int64_t j, const int64_t* z) {
+            for (int i = 0; i < 3; ++i) {
+                const int64_t y = Pt[j * 3 + i] + z[i];
+                if (y < 0 || y >= n[i]) return false;
+            }
+            return true;
+        };
+        auto val = [&](int64_t j, const int64_t* z) -> double {
+            const int64_t R0 = Rd[j * 3], R1 = Rd[j * 3 + 1], R2 = Rd[j * 3 + 2];
+            if (z[0] < -R0 || z[0] > R0 || z[1] < -R1 || z[1] > R1 || z[2] < -R2 || z[2] > R2) return 0.0;
+            return a.phi[a.phi_off[j] + ((z[0] + R0) * (2 * R1 + 1) + (z[1] + R1)) * (2 * R2 + 1) + (z[2] + R2)];
+        };
+        std::vector<cd> G((size_t)nz * n1 * n2, cd(0.0));
+        std::vector<char> live((size_t)nz * n1, 0);
+        int64_t z[3];
+        for (z[0] = g.zlo[0]; z[0] <= g.zhi[0]; ++z[0])
+            for (z[1] = g.zlo[1]; z[1] <= g.zhi[1]; ++z[1])
+                for (z[2] = g.zlo[2]; z[2] <= g.zhi[2]; ++z[2]) {
+                    double v = 0.0;
+                    if (defined(k, z)) {
+                        v = val(k, z);
+                    } else if (extend) {
+                        int cnt = 0;
+                        double s = 0.0;
+                        for (int64_t j : nbrs[k]) {
+                            if (j == k || !defined(j, z)) continue;
+                            ++cnt;
+                            s += val(j, z);
+                        }
+                        if (cnt) v = s / (double)cnt;
+                    }
+                    const int64_t i0 = ((z[0] % nz) + nz) % nz, i1 = ((z[1] % n1) + n1) % n1,
+                                  i2 = ((z[2] % n2) + n2) % n2;
+                    G[(size_t)((i0 * n1 + i1) * n2 + i2)] += v;
+                    live[(size_t)(i0 * n1 + i1)] = 1;
+                }
+        // axis 2 (real length 2M, keep 0..M), axis 1, axis 0
+        const int NC = M + 1;
+        std::vector<cd> H((size_t)nz * n1 * NC, cd(0.0)), buf_in(std::max({n1, nz, n2})),
+            buf_out(std::max({n1, nz, n2})), scratch;
+        std::vector<cd> W2 = twiddles(n2), W1 = twiddles(n1), W0 = twiddles(nz);
+        for (int i0 = 0; i0 < nz; ++i0)
+            for (int i1 = 0; i1 < n1; ++i1) {
+                if (!live[(size_t)(i0 * n1 + i1)]) continue;
+                fft_rec(&G[(size_t)((i0 * n1 + i1) * n2)], 1, n2, buf_out.data(), W2, n2, scratch);
+                for (int kk = 0; kk < NC; ++kk) H[(size_t)((i0 * n1 + i1) * NC + kk)] = buf_out[kk];
+            }
+        std::vector<cd>().swap(G);
+        for (int i0 = 0; i0 < nz; ++i0)
+            for (int kk = 0; kk < NC; ++kk) {
+                for (int i1 = 0; i1 < n1; ++i1) buf_in[i1] = H[(size_t)((i0 * n1 + i1) * NC + kk)];
+                fft_rec(buf_in.data(), 1, n1, buf_out.data(), W1, n1, scratch);
+                for (int k1 = 0; k1 < n1; ++k1) H[(size_t)((i0 * n1 + k1) * NC + kk)] = buf_out[k1];
+            }
+        const double sc = 1.0 / ((double)nz * (double)n1 * (double)M);
+        double* out = &p.spec[(size_t)(2 * it.p.spec_off)];
+        for (int k1 = 0; k1 < n1; ++k1)
+            for (int kk = 0; kk < NC; ++kk) {
+                for (int i0 = 0; i0 < nz; ++i0) buf_in[i0] = H[(size_t)((i0 * n1 + k1) * NC + kk)];
+                fft_rec(buf_in.data(), 1, nz, buf_out.data(), W0, nz, scratch);
+                const int s1 = perm_slot(k1, it.p.a0, it.p.b0);
+                const int s2 = (kk < M) ? perm_slot(kk, it.p.am, it.p.bm) : M;
+                for (int kz = 0; kz < nz; ++kz) {
+                    const int s0 = perm_slot(kz, it.az, it.bz);
+                    const size_t e = (size_t)(((int64_t)s0 * n1 + s1) * NC + s2);
+                    out[2 * e] = buf_out[kz].real() * sc;
+                    out[2 * e + 1] = buf_out[kz].imag() * sc;
+                }
+            }
+    }
+    // ------------------------------------------------ reduction view boxes
+    const int64_t N1 = n[1];
+    std::vector<Box> bf, ba;
+    for (const Item3& it : p.items3) {
+        const Item& q = it.p;
+        const int64_t pf = (int64_t)q.out_n0 * q.out_n1, pa = (int64_t)q.in_n0 * q.in_n1;
+        for (int z = 0; z < it.out_nz; ++z)
+            bf.push_back(Box{(int32_t)((it.gz + z) * N1 + q.g0), q.g1, q.out_n0, q.out_n1, q.slot_fwd + z * pf});
+        for (int z = 0; z < it.in_nz; ++z)
+            ba.push_back(Box{(int32_t)((it.gz + it.in_offz + z) * N1 + q.g0 + q.in_off0), q.g1 + q.in_off1, q.in_n0,
+                             q.in_n1, q.slot_adj + z * pa});
+    }
+    if (!finish_tiles(p, bf, ba, err)) return PC_ERR_UNSUPPORTED;
+    p.leaf_box.resize(6 * L);
+    for (int64_t c = 0; c < L; ++c)
+        for (int i = 0; i < 3; ++i) {
+            p.leaf_box[6 * c + i] = (int32_t)lo(c, i);
+            p.leaf_box[6 * c + 3 + i] = (int32_t)(hi(c, i) - lo(c, i) + 1);
+        }
+    return PC_OK;
+}
+
+}  // namespace pc

@@ -1,7 +1,7 @@
 """Helpers for the library tests (inputs, tolerances, tiny cases)."""
 import numpy as np
 
-from workloads import make_config
+from workloads import make_config, cosine_field
 from tests.tilings import hanging_2d, const_blur, workload_from, tensor
 
 # Per-vector relative L2 bars against the FP64 oracle.
@@ -35,4 +35,22 @@ def small_cases():
     s = 2.0 + 3.0 * (x0 / 69.0)
     cases.append(("oneleaf70", workload_from(np.stack([s, s]), lo, hi)))
     cases.append(("cfg1_small", make_config(1, scale=0.25)))
+    return cases
+
+
+def small_cases_3d():
+    """3-D (name, workload) pairs: a rectangular box with per-axis widths
+    varying along their own axes, and a cube with cosine width fields (the
+    3-D workload's recipe at 24^3, 4 x 4 x 4 points)."""
+    lo, hi = tensor((12, 17, 23), 3)
+    x0, x1, x2 = np.meshgrid(np.arange(12), np.arange(17), np.arange(23), indexing="ij")
+    s0 = 0.7 + 0.8 * x0 / 11
+    s1 = 1.0 + 0.5 * np.cos(x1 / 4.0)
+    s2 = 0.9 + 0.6 * x2 / 22
+    cases = [("rect3d", workload_from(np.stack([s0, s1, s2]), lo, hi))]
+    n = 24
+    rng = np.random.default_rng(2)
+    f = [cosine_field((n, n, n), 0.8, 3.0, 2, 2, rng=rng)[0] for _ in range(3)]
+    lo, hi = tensor((n, n, n), 4)
+    cases.append(("cube24", workload_from(np.stack(f), lo, hi)))
     return cases

@@ -225,3 +225,115 @@ def test_large_pieces_blur2048_start_grid(lib):
         sa = np.abs(adj[j]).max()
         assert np.abs(fwd[j, flat] - rf).max() <= 1e-5 * sf, (j, np.abs(fwd[j, flat] - rf).max() / sf)
         assert np.abs(adj[j, flat] - ra).max() <= 1e-5 * sa, (j, np.abs(adj[j, flat] - ra).max() / sa)
+
+
+# ------------------------------------------------------------------- 3-D
+@pytest.mark.parametrize("idx", range(2))
+def test_small_cases_3d_parity(lib, idx):
+    from tests.libhelpers import small_cases_3d
+    name, w = small_cases_3d()[idx]
+    rng = np.random.default_rng(300 + idx)
+    U = rng.standard_normal((3, w.N))
+    for flags in (0, lib.PC_NO_EXTEND):
+        ora = OracleOperator.from_workload(w, extend=(flags == 0))
+        for dtype in (lib.PC_F64, lib.PC_F32):
+            _note(f"case={name} flags={flags} dtype={dtype}")
+            tdt, ndt = _dt(dtype)
+            op = lib.PcOperator.from_workload(w, dtype=dtype, flags=flags)
+            Ur = U.astype(ndt)
+            Ud = torch.from_numpy(Ur).cuda()
+            for adj in (False, True):
+                out = torch.full_like(Ud, float("nan"))
+                (op.apply_adjoint_batch if adj else op.apply_batch)(Ud, out)
+                torch.cuda.synchronize()
+                ref = ora.apply_batch(Ur.astype(np.float64), adjoint=adj)
+                e = relerr(out.cpu().numpy(), ref)
+                assert e.max() <= TOL[dtype], (name, flags, dtype, adj, e)
+            op.close()
+
+
+def test_3d_schedules_are_bitwise_equal(lib):
+    """Batch vs single vector, plain per-item launches, vector chunks of one
+    and item groups of one item (tiny scratch) all give the same bits."""
+    from tests.libhelpers import small_cases_3d
+    _, w = small_cases_3d()[1]
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    U = torch.from_numpy(np.random.default_rng(4).standard_normal((4, w.N)).astype(np.float32)).cuda()
+    for adj in (False, True):
+        fn = op.apply_adjoint_batch if adj else op.apply_batch
+        ref = torch.zeros_like(U)
+        fn(U, ref)
+        torch.cuda.synchronize()
+        if not adj:
+            plain = torch.zeros_like(U)
+            op.apply_batch_plain(U, plain)
+            single = torch.zeros(w.N, dtype=torch.float32, device="cuda")
+            op.apply(U[2].contiguous(), single)
+            torch.cuda.synchronize()
+            assert torch.equal(plain, ref)
+            assert torch.equal(single, ref[2])
+        op.set_tuning(lib.PC_TUNE_SCRATCH, 1)     # every group holds one item
+        op.set_tuning(lib.PC_TUNE_CHUNK, 1)
+        other = torch.zeros_like(U)
+        fn(U, other)
+        torch.cuda.synchronize()
+        op.set_tuning(lib.PC_TUNE_SCRATCH, 0)
+        op.set_tuning(lib.PC_TUNE_CHUNK, 0)
+        assert torch.equal(other, ref), adj
+
+
+def test_error_estimate_3d_matches_oracle(lib):
+    from tests.libhelpers import small_cases_3d
+    _, w = small_cases_3d()[0]
+    ora = OracleOperator.from_workload(w)
+    q = 4
+    Z = np.random.default_rng(41).standard_normal((q, w.N))
+    Y = np.stack([w.op.apply(z, adjoint=True) for z in Z])
+    eta_o, eom_o, erel_o, _ = estimate(ora, Z, Y)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F64)
+    eta, eom, erel = op.error_estimate(torch.from_numpy(Z).cuda(), torch.from_numpy(Y).cuda())
+    assert eta.shape == eta_o.shape
+    assert np.abs(eta - eta_o).max() <= 1e-10 * eta_o.max()
+    assert abs(erel - erel_o) <= 1e-10 * erel_o
+
+
+def _sample_points_3d(n, count, seed):
+    rng = np.random.default_rng(seed)
+    ys = rng.integers(0, n, (count, 3))
+    corners = np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1], [63, 64, 65]])
+    return np.vstack([ys, corners])
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_full_size_blur3d_128(lib, dtype):
+    """The 3-D workload (128^3, 9^3 points): FP32 with B = 16 in the batched
+    launch configuration, FP64 with B = 2; forward and adjoint at sampled
+    outputs against the oracle (a full oracle apply is out of reach)."""
+    w = make_config(2)
+    B = 16 if dtype == 0 else 2
+    tdt, ndt = _dt(dtype)
+    op = lib.PcOperator.from_workload(w, dtype=dtype)
+    _note(f"blur3d: dtype={dtype} items={op.stats()['n_items']}")
+    U = w.vectors(B, dtype=ndt)
+    Ud = torch.from_numpy(U).cuda()
+    fwd = torch.zeros_like(Ud)
+    adj = torch.zeros_like(Ud)
+    op.apply_batch(Ud, fwd)
+    op.apply_adjoint_batch(Ud[:2], adj[:2])
+    torch.cuda.synchronize()
+    fwd, adj = fwd.cpu().numpy(), adj.cpu().numpy()
+    assert np.all(np.isfinite(fwd))
+    ora = OracleOperator.from_workload(w)
+    n = w.shape[0]
+    ys = _sample_points_3d(n, 40, 13)
+    flat = (ys[:, 0] * n + ys[:, 1]) * n + ys[:, 2]
+    tol = TOL[dtype]
+    for j in sorted({0, 1, B // 2, B - 1}):
+        u = U[j].astype(np.float64)
+        rf = ora.apply_at(u, ys)
+        sf = np.abs(fwd[j]).max()
+        assert np.abs(fwd[j, flat] - rf).max() <= tol * sf, (j, np.abs(fwd[j, flat] - rf).max() / sf)
+        if j < 2:
+            ra = ora.apply_adjoint_at(u, ys)
+            sa = np.abs(adj[j]).max()
+            assert np.abs(adj[j, flat] - ra).max() <= tol * sa, (j, np.abs(adj[j, flat] - ra).max() / sa)

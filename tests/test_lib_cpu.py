@@ -12,7 +12,8 @@ import pytest
 
 from oracle import OracleOperator
 from workloads import make_config
-from tests.libhelpers import small_cases, relerr, TOL
+from tests.libhelpers import small_cases, small_cases_3d, relerr, TOL
+from tests.tilings import refine, workload_from
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PKG = os.path.join(ROOT, "paper_1805_06018_amd")
@@ -70,9 +71,13 @@ def test_create_rejects_bad_input():
     assert st == PC_ERR_ARG, msg
     st, msg = raw_create(**a, flags=1 << 5)
     assert st == PC_ERR_ARG, msg
-    w3 = make_config(2, scale=0.125)
-    st, msg = raw_create(**_args(w3))
-    assert st == PC_ERR_UNSUPPORTED, msg                   # 3-D apply not built
+    # 3-D tiling with hanging nodes (one octant refined): trilinear weights
+    # need a conforming tiling
+    lo3, hi3 = refine((9, 9, 9), lambda l, h: max(b - a for a, b in zip(l, h)) >= 8 or
+                      (max(b - a for a, b in zip(l, h)) >= 4 and max(l) == 0))
+    x = np.full((3, 9, 9, 9), 1.2)
+    st, msg = raw_create(**_args(workload_from(x, lo3, hi3)))
+    assert st == PC_ERR_UNSUPPORTED and "hanging" in msg, msg
 
 
 # ------------------------------------------------------------- CPU emulation
@@ -104,9 +109,9 @@ def emu_apply(lib, w, U, dtype, flags=0, adj=False):
     return out
 
 
-@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("idx", range(8))
 def test_emulated_kernels_match_oracle(idx):
-    name, w = small_cases()[idx]
+    name, w = (small_cases() + small_cases_3d())[idx]
     lib = _emu_lib()
     rng = np.random.default_rng(100 + idx)
     U = rng.standard_normal((3, w.N))
@@ -131,9 +136,9 @@ def test_emulated_kernels_under_address_sanitizer():
     code = (
         "import sys, numpy as np; sys.path.insert(0, %r)\n"
         "from tests.test_lib_cpu import _emu_lib, emu_apply\n"
-        "from tests.libhelpers import small_cases\n"
+        "from tests.libhelpers import small_cases, small_cases_3d\n"
         "lib = _emu_lib(%r)\n"
-        "for name, w in small_cases():\n"
+        "for name, w in small_cases() + small_cases_3d():\n"
         "    U = np.random.default_rng(1).standard_normal((2, w.N))\n"
         "    for dt in (0, 1):\n"
         "        for fl in (0, 1):\n"
