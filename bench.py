@@ -1,11 +1,14 @@
 """Benchmark of the product-convolution apply on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                [--workload blur1024|blur3d] [--dtype f32|f64]
 
 A step is one pc_apply_batch of the whole hot path (gather with weights,
-forward FFT, spectral product, inverse FFT, deterministic scatter-add) on the
-1024^2 spatially varying blur with ~600 adaptive sample points and 64
-right-hand sides in FP32, inputs resident in HBM.  Prints one JSON line.
+forward FFT, spectral product, inverse FFT, deterministic scatter-add) with
+inputs resident in HBM.  Default workload: the 1024^2 spatially varying blur
+with ~600 adaptive sample points and 64 right-hand sides in FP32.  blur3d:
+the 128^3 blur with a 9^3 sample grid and 16 right-hand sides.  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -19,6 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector FLOP/s
+PEAK_FP64_VALU = 78.6e12       # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E B/s
 
 
@@ -29,6 +33,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--workload", choices=["blur1024", "blur3d"], default="blur1024")
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the 256 MiB input (a known-size "
                          "reference for hardware byte counters)")
@@ -45,13 +51,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
-    w = make_config(1)
+    three_d = args.workload == "blur3d"
+    w = make_config(2 if three_d else 1)
     B = w.batch
+    f64 = args.dtype == "f64"
+    ndt = np.float64 if f64 else np.float32
+    esz = 8 if f64 else 4
     t0 = time.time()
-    op = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F32)
+    op = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F64 if f64 else _lib.PC_F32)
     t_create = time.time() - t0
     st = op.stats()
-    U = torch.from_numpy(w.vectors(B, dtype=np.float32)).to(dev)
+    U = torch.from_numpy(w.vectors(B, dtype=ndt)).to(dev)
     OUT = torch.empty_like(U)
     print(f"# workload {w.name}: N={w.N} r={w.r} B={B} items={st['n_items']} create={t_create:.2f}s",
           file=sys.stderr, flush=True)
@@ -77,12 +87,12 @@ def main():
     ms_step = ms_total / args.steps
     value = w.N * B / (ms_step * 1e-3)
 
-    # dominant kernel: the fused convolution launch
+    # dominant kernel: the convolution launches (2-D: one fused launch per
+    # vector chunk; 3-D: the plane / axis-0 / plane kernels of each item group)
     conv_avg_s = prof["conv_ms"] / max(prof["conv_launches"], 1) * 1e-3
-    vec_per_launch = prof["conv_vectors"] / max(prof["conv_launches"], 1)
-    flops_launch = st["alg_flops_per_rhs"] * vec_per_launch
-    achieved = flops_launch / conv_avg_s
-    alg_bytes_step = 8.0 * w.N * B + 4.0 * st["kernel_elems"]
+    achieved = st["alg_flops_per_rhs"] * prof["conv_vectors"] / (prof["conv_ms"] * 1e-3)
+    peak = PEAK_FP64_VALU if f64 else PEAK_FP32_VALU
+    alg_bytes_step = 2.0 * esz * w.N * B + esz * st["kernel_elems"]
 
     if args.copy_probe:
         probe = torch.empty_like(U)
@@ -105,6 +115,10 @@ def main():
     else:
         same = None
 
+    if three_d:
+        wl = f"blur3d_128x128x128_tensor9_r{w.r}_b{B}"
+    else:
+        wl = f"blur2d_1024x1024_quadtree_r{w.r}_b{B}"
     rec = {
         "metric": "PC apply grid-points/s (FP32, 1e-5 rel.L2) vs plain apply",
         "value": value,
@@ -116,13 +130,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": "blur2d_1024x1024_quadtree_r579_b64", "grid": list(w.shape), "r": w.r,
-                   "batch": B, "items": st["n_items"]},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None},
+        "config": {"workload": wl, "grid": list(w.shape), "r": w.r, "batch": B, "items": st["n_items"]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
         "kernels": {"conv_ms_per_launch": conv_avg_s * 1e3, "conv_launches_per_step": prof["conv_launches"] / args.steps,
+                    "conv_ms_per_step": prof["conv_ms"] / args.steps,
                     "reduce_ms_per_step": prof["reduce_ms"] / args.steps,
                     "alg_flops_per_vector": st["alg_flops_per_rhs"]},
         "hbm_alg_frac": alg_bytes_step / (ms_step * 1e-3) / PEAK_HBM,
@@ -130,7 +144,7 @@ def main():
                   "bitwise_equal_to_fused": same},
     }
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not three_d:
         from oracle import OracleOperator
         ora = OracleOperator.from_workload(w)
         u0 = U[0].cpu().numpy().astype(np.float64)
@@ -140,8 +154,25 @@ def main():
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         got = OUT[0].cpu().numpy().astype(np.float64)
         rec["cpu_baseline"] = {"value": w.N / t_cpu, "unit": "grid-points/s", "cores": cores, "kind": "oracle",
-                               "sample": "1 of 64 vectors, full 1024^2 output, FP64 direct summation (C core)"}
+                               "sample": f"1 of {B} vectors, full 1024^2 output, FP64 direct summation (C core)"}
         rec["rel_l2_vs_oracle_vec0"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    elif not args.no_cpu_baseline:
+        # a full FP64 oracle apply of one 3-D vector is ~3e12 multiply-adds:
+        # time the oracle's direct summation at a bounded set of outputs
+        from oracle import OracleOperator
+        ora = OracleOperator.from_workload(w)
+        u0 = U[0].cpu().numpy().astype(np.float64)
+        n = w.shape[0]
+        ys = np.random.default_rng(17).integers(0, n, (2000, 3))
+        t2 = time.time()
+        ref = ora.apply_at(u0, ys)
+        t_cpu = time.time() - t2
+        flat = (ys[:, 0] * n + ys[:, 1]) * n + ys[:, 2]
+        got = OUT[0].cpu().numpy().astype(np.float64)[flat]
+        rec["cpu_baseline"] = {"value": len(ys) / t_cpu, "unit": "grid-points/s", "cores": 1, "kind": "oracle",
+                               "sample": f"2000 random output points of 1 of {B} vectors, FP64 direct "
+                                         "summation (NumPy, one thread)"}
+        rec["rel_l2_vs_oracle_vec0_sampled"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print(json.dumps(rec))
 
 

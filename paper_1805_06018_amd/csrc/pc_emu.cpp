@@ -83,7 +83,7 @@ void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ld
     for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * N)], U + b * ldu, sizeof(T) * (size_t)N);
     std::vector<T> slots((size_t)(B * per), T(0));
     std::vector<C> scratch((size_t)(P.scratch_per_vec * B), C{T(1e30), T(1e30)});
-    const int NT = pc::threads_for<T>();
+    const int NT = pc::kPlaneThreads;
     const int COLS = pc::axis_cols(P.dtype), LDA = pc::axis_ld(COLS);
     const int64_t pitch = P.cols, plane_pitch = (int64_t)P.prow * P.cols;
     for (const pc::Item3& I : P.items3) {

@@ -183,8 +183,9 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
     const size_t cx_bytes = 2 * op->esz;
     int64_t chunk = 1;
     if (!plain) {
+        // an explicit chunk overrides the default staging cap
         const int64_t cap = (int64_t)std::max<size_t>(1, kSlotCapBytes / per_bytes);
-        chunk = std::min<int64_t>(cap, std::max<int64_t>(1, op->tune_chunk > 0 ? op->tune_chunk : B));
+        chunk = op->tune_chunk > 0 ? std::min<int64_t>(op->tune_chunk, B) : std::min<int64_t>(cap, B);
     }
     const size_t scap = op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
     const int n = (int)P.items3.size();

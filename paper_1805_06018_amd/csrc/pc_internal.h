@@ -13,6 +13,7 @@ constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kReduceCols = 256;       // reduce tile width (threads)
 constexpr int kReduceRows = 8;         // reduce tile height (accumulators per thread)
 constexpr int kAxisThreads = 256;      // threads of the 3-D axis-0 kernel
+constexpr int kPlaneThreads = 256;     // threads of the 3-D plane kernels (one plane per workgroup)
 
 // Columns (flattened axis-1 x axis-2 frequencies) per block of the 3-D
 // axis-0 kernel: the block holds nz x (cols + 1) complex values in LDS.

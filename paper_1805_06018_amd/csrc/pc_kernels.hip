@@ -78,10 +78,10 @@ struct Conv3Args {
 
 // One workgroup per (item, vector, gathered plane), plane fastest.
 template <class T>
-__global__ __launch_bounds__(threads_for<T>()) void plane_fwd_kernel(Conv3Args<T> A) {
+__global__ __launch_bounds__(kPlaneThreads) void plane_fwd_kernel(Conv3Args<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    constexpr int NT = threads_for<T>();
+    constexpr int NT = kPlaneThreads;
     const int q = blockIdx.x % A.maxp, l = blockIdx.x / A.maxp;
     const int rhs = l % A.B, item = l / A.B;
     if (item >= A.n_items) return;
@@ -139,10 +139,10 @@ __global__ __launch_bounds__(kAxisThreads) void axis_kernel(Conv3Args<T> A) {
 
 // One workgroup per (item, vector, written plane), plane fastest.
 template <class T>
-__global__ __launch_bounds__(threads_for<T>()) void plane_inv_kernel(Conv3Args<T> A) {
+__global__ __launch_bounds__(kPlaneThreads) void plane_inv_kernel(Conv3Args<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    constexpr int NT = threads_for<T>();
+    constexpr int NT = kPlaneThreads;
     const int q = blockIdx.x % A.maxp, l = blockIdx.x / A.maxp;
     const int rhs = l % A.B, item = l / A.B;
     if (item >= A.n_items) return;
@@ -192,7 +192,7 @@ static hipError_t conv3_t(const DevPlan& P, const Conv3Launch& L, hipStream_t s)
     const int64_t g_axis = 8 * (((int64_t)A.n_items * L.max_tiles + 7) / 8) * A.B;
     if (g_fwd > 0x7fffffff || g_inv > 0x7fffffff || g_axis > 0x7fffffff) return hipErrorInvalidValue;
     A.maxp = L.max_gather;
-    hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3((unsigned)g_fwd), dim3(threads_for<T>()), P.max_lds, s, A);
+    hipLaunchKernelGGL(plane_fwd_kernel<T>, dim3((unsigned)g_fwd), dim3(kPlaneThreads), P.max_lds, s, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     A.maxp = L.max_tiles;
@@ -200,7 +200,7 @@ static hipError_t conv3_t(const DevPlan& P, const Conv3Launch& L, hipStream_t s)
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     A.maxp = L.max_write;
-    hipLaunchKernelGGL(plane_inv_kernel<T>, dim3((unsigned)g_inv), dim3(threads_for<T>()), P.max_lds, s, A);
+    hipLaunchKernelGGL(plane_inv_kernel<T>, dim3((unsigned)g_inv), dim3(kPlaneThreads), P.max_lds, s, A);
     return hipGetLastError();
 }
 
