@@ -25,6 +25,30 @@ PEAK_FP32_VALU = 157.3e12      # MI355X FP32 vector FLOP/s
 PEAK_FP64_VALU = 78.6e12       # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E B/s
 
+# HBM bytes per convolution launch from the committed counter runs (FETCH_SIZE
+# x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy); valid only while the
+# kernel and planner sources hash to the recorded value.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_kernel_blur1024_b64.md")
+TRAFFIC_SOURCES = ["paper_1805_06018_amd/csrc/" + f
+                   for f in ("pc_kernels.hip", "pc_phases.h", "pc_fft.h", "pc_internal.h", "pc_plan.cpp")]
+
+
+def measured_traffic():
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=([0-9.eE+]+) sources_sha256=([0-9a-f]{64})", text)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -134,7 +158,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "grid": list(w.shape), "r": w.r, "batch": B, "items": st["n_items"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None if (three_d or f64) else measured_traffic()},
         "kernels": {"conv_ms_per_launch": conv_avg_s * 1e3, "conv_launches_per_step": prof["conv_launches"] / args.steps,
                     "conv_ms_per_step": prof["conv_ms"] / args.steps,
                     "reduce_ms_per_step": prof["reduce_ms"] / args.steps,
