@@ -190,6 +190,10 @@ pc_status   pc_set_profiling(pc_op* op, int enable);
 enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
+/* pc_device_bytes -- device bytes the operator holds now: its resident data
+ * (spectra, weights, tables) plus the work buffers grown by earlier calls
+ * (staging, 3-D scratch, estimator buffers), which it keeps until
+ * pc_destroy.  For HBM-budget admission; 0 for a null operator. */
 size_t      pc_device_bytes(const pc_op* op);
 pc_status   pc_destroy(pc_op* op);
 const char* pc_status_string(pc_status st);

@@ -582,7 +582,10 @@ pc_status pc_read_profile(pc_op* op, pc_profile* out) {
     return st;
 }
 
-size_t pc_device_bytes(const pc_op* op) { return op ? op->resident : 0; }
+size_t pc_device_bytes(const pc_op* op) {
+    if (!op) return 0;
+    return op->resident + op->slots_bytes + op->scratch_bytes + op->work_bytes + op->est_bytes;
+}
 
 pc_status pc_destroy(pc_op* op) {
     if (!op) return PC_OK;

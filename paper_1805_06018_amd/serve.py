@@ -214,7 +214,11 @@ def summarize(reqs, t_end, batches, ops):
     return out
 
 
-def build_residents(workloads, q=8, dtype=_lib.PC_F32):
+def build_residents(workloads, q=8, dtype=_lib.PC_F32, max_batch=64, log=None):
+    """Creates every operator, its input pool, probes and exact adjoint, and
+    runs one apply of max_batch vectors and one estimate so that the work
+    buffers reach their full size; work_bytes is then the operator's whole
+    device footprint (pc_device_bytes)."""
     from workloads.blur_gpu import GpuBlurAdjoint
     res = []
     for w in workloads:
@@ -222,9 +226,14 @@ def build_residents(workloads, q=8, dtype=_lib.PC_F32):
         U = torch.from_numpy(w.vectors(32, dtype=np.float32)).cuda()
         Z = torch.from_numpy(w.rademacher(q, w.vec_seed + 1000).astype(np.float32)).cuda()
         Y = GpuBlurAdjoint(w.op)(Z)
-        st = op.stats()
-        staging = min(32 * st["slot_elems_fwd"], (2 << 30) // 4) * 4
-        res.append(Resident(w.name, op, w.N, U, Z, Y, op.device_bytes() + staging))
+        tmp = torch.zeros((max_batch, w.N), dtype=torch.float32, device="cuda")
+        op.apply_batch(tmp, tmp.clone())
+        op.error_estimate(Z, Y)
+        torch.cuda.synchronize()
+        del tmp
+        res.append(Resident(w.name, op, w.N, U, Z, Y, op.device_bytes()))
+        if log:
+            log({"op": w.name, "points": w.r, "device_gib": res[-1].work_bytes / 2**30})
     torch.cuda.synchronize()
     return res
 
@@ -238,15 +247,20 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--budget-gib", type=float, default=0.0,
+                    help="HBM budget (operators + in-flight); 0: resident footprint + 4 GiB")
+    ap.add_argument("--ops", choices=["2d", "all"], default="all")
     ap.add_argument("--plain-requests", type=int, default=40)
     ap.add_argument("--loads", type=str, default="0.5,0.8,1.0")
     args = ap.parse_args(argv)
     t0 = time.time()
-    res = build_residents(make_serving_ops())
+    res = build_residents(make_serving_ops(with_3d=(args.ops == "all")),
+                          log=lambda r: print(json.dumps(r), flush=True))
+    resident = sum(r.work_bytes for r in res)
+    budget = int(args.budget_gib * 2**30) if args.budget_gib > 0 else resident + (4 << 30)
     print(json.dumps({"ops": [r.name for r in res], "setup_s": time.time() - t0,
-                      "resident_gib": sum(r.work_bytes for r in res) / 2**30}), flush=True)
-    srv = Server(res, hbm_budget=int(args.budget_gib * 2**30))
+                      "resident_gib": resident / 2**30, "budget_gib": budget / 2**30}), flush=True)
+    srv = Server(res, hbm_budget=budget)
     # warm-up, then the saturated rate of one-request-at-a-time fused applies
     srv.run(poisson_requests(24, len(res), 0.0), mode="sequential")
     sat = srv.run(poisson_requests(args.requests // 4, len(res), 0.0), mode="sequential")

@@ -35,6 +35,21 @@ def test_exact_blur_adjoint_matches_cpu(mods):
         assert err < tol, (dt, err)
 
 
+def test_exact_blur_adjoint_3d_matches_cpu(mods):
+    _, _, GpuBlurAdjoint = mods
+    n = (9, 11, 13)
+    x0, x1, x2 = np.meshgrid(*(np.arange(v) for v in n), indexing="ij")
+    sig = np.stack([0.7 + 0.9 * x0 / 8, 1.1 + 0.4 * np.sin(x1 / 3.0), 0.8 + 0.7 * x2 / 12])
+    op = BlurOperator(sig)
+    V = np.random.default_rng(4).standard_normal((10, int(np.prod(n))))
+    ref = np.stack([op.apply(v, adjoint=True) for v in V])
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        g = GpuBlurAdjoint(op, dtype=dt)
+        out = g(torch.from_numpy(V).to(device="cuda", dtype=dt)).cpu().numpy()
+        err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+        assert err < tol, (dt, err)
+
+
 def test_refinement_loop_converges_and_matches_oracle(mods):
     _lib, refine, GpuBlurAdjoint = mods
     # 256^2 with widths scaled like the grid (s in [1, 4]), 4 x 4 start

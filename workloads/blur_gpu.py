@@ -24,6 +24,9 @@ def _load():
         lib.blur_adjoint.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, P,
                                      ctypes.c_int64, ctypes.c_int, P]
         lib.blur_adjoint.restype = ctypes.c_int
+        lib.blur_adjoint3.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                                      ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int, P]
+        lib.blur_adjoint3.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -32,6 +35,17 @@ class GpuBlurAdjoint:
     """Holds the width and radius fields of a BlurOperator on the device."""
 
     def __init__(self, op, dtype=torch.float32, device="cuda"):
+        self.d3 = op.d == 3
+        if self.d3:
+            self.n = tuple(int(v) for v in op.shape)
+            self.N = int(np.prod(self.n))
+            self.s = [torch.from_numpy(np.ascontiguousarray(op.sig[i]).ravel()).to(device=device, dtype=dtype)
+                      for i in range(3)]
+            self.r = [torch.from_numpy(np.ascontiguousarray(op.radius[i], dtype=np.int32).ravel()).to(device)
+                      for i in range(3)]
+            self.dtype = dtype
+            self.code = 1 if dtype == torch.float64 else 0
+            return
         if op.d == 1:
             s0 = np.ones(op.shape)
             s1 = op.sig[0]
@@ -42,6 +56,7 @@ class GpuBlurAdjoint:
             s0, s1 = op.sig[0], op.sig[1]
             r0, r1 = op.radius[0], op.radius[1]
             self.n0, self.n1 = int(op.shape[0]), int(op.shape[1])
+        self.N = self.n0 * self.n1
         self.dtype = dtype
         self.s0 = torch.from_numpy(np.ascontiguousarray(s0).ravel()).to(device=device, dtype=dtype)
         self.s1 = torch.from_numpy(np.ascontiguousarray(s1).ravel()).to(device=device, dtype=dtype)
@@ -51,12 +66,15 @@ class GpuBlurAdjoint:
 
     def raw(self, B, in_ptr, ldin, out_ptr, ldout, stream_ptr):
         """Callback form: pointers and leading dimensions as plain ints."""
+        if self.d3:
+            return _load().blur_adjoint3(self.code, *(t.data_ptr() for t in self.s), *(t.data_ptr() for t in self.r),
+                                         *self.n, in_ptr, ldin, out_ptr, ldout, B, stream_ptr)
         return _load().blur_adjoint(self.code, self.s0.data_ptr(), self.s1.data_ptr(), self.r0.data_ptr(),
                                     self.r1.data_ptr(), self.n0, self.n1, in_ptr, ldin, out_ptr, ldout, B,
                                     stream_ptr)
 
     def __call__(self, V, OUT=None):
-        V = V.reshape(-1, self.n0 * self.n1)
+        V = V.reshape(-1, self.N)
         if OUT is None:
             OUT = torch.empty_like(V)
         rc = self.raw(V.shape[0], V.data_ptr(), V.stride(0), OUT.data_ptr(), OUT.stride(0),

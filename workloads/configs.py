@@ -103,10 +103,16 @@ def make_config(idx, scale=1.0):
     raise ValueError(f"unknown config {idx}")
 
 
-def make_serving_ops(sizes=None):
-    """The resident 2-D operators of the serving workload: grids 256^2 to
-    2048^2 with 25 to about 2000 sample points (s in [2, 12], s in [2, 16] on
-    the largest), uniform grids for the two smallest, quadtrees otherwise."""
+def make_serving_ops(sizes=None, with_3d=False, sizes3=None):
+    """The resident operators of the serving workload.
+
+    2-D: grids 256^2 to 2048^2 with 25 to about 2000 sample points (s in
+    [2, 12], s in [2, 16] on the largest), uniform grids for the two smallest,
+    quadtrees otherwise (seeds 40 + i).
+    3-D (with_3d): tensor grids 64^3 / 3^3, 80^3 / 5^3, 96^3 / 7^3, 128^3 / 9^3
+    (the 3-D workload's operator), 144^3 / 10^3 and 160^3 / 12^3 points, per-axis
+    widths in [1.5, 6] (one two-mode field per axis, kmax 2, seeds 50 + i).
+    ``sizes`` / ``sizes3`` keep only the listed grid sizes."""
     specs = [(256, 25, 0), (512, 100, 0), (768, 300, 1), (1024, 600, 1), (1536, 1000, 1), (2048, 2000, 1)]
     out = []
     for i, (n, r_target, adaptive) in enumerate(specs):
@@ -123,4 +129,20 @@ def make_serving_ops(sizes=None):
             _, lo, hi, _ = tune_quadtree(s, int(r_target * 0.9), int(r_target * 1.1) + 1)
             name = f"blur2d_{n}_quadtree"
         out.append(_finish(name, np.stack([s, s]), lo, hi, 32, 104 + i, {"modes": modes}))
+    if not with_3d:
+        return out
+    specs3 = [(64, 3), (80, 5), (96, 7), (128, 9), (144, 10), (160, 12)]
+    for i, (n, m) in enumerate(specs3):
+        if sizes3 is not None and n not in sizes3:
+            continue
+        if n == 128:
+            w = make_config(2)
+            w.batch, w.vec_seed = 32, 110 + i
+            out.append(w)
+            continue
+        rng = np.random.default_rng(50 + i)
+        fields = [cosine_field((n, n, n), 1.5, 6.0, 2, 2, rng=rng)[0] for _ in range(3)]
+        nodes = uniform_nodes(n, m)
+        lo, hi = tensor_leaves([nodes, nodes, nodes])
+        out.append(_finish(f"blur3d_{n}_tensor{m}", np.stack(fields), lo, hi, 32, 110 + i, {}))
     return out

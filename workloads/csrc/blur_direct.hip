@@ -5,9 +5,10 @@
 // A[y, x] = exp(-sum_i (y_i - x_i)^2 / (2 s_i(x)^2)) / Z(x) for |y_i - x_i| <=
 // R_i(x) = ceil(4 s_i(x)), Z(x) the sum of the same Gaussian over the full box.
 // blur_adjoint computes (A^T v)[x] = sum_z g_x(z) v[x + z] over x + z in Omega
-// for B vectors (the exact adjoint the error estimator needs).  2-D domains
-// (d = 1 is a single row).  Widths and radii come from the host so that the
-// radii match the supplied impulse responses exactly.
+// for B vectors (the exact adjoint the error estimator needs).  blur_adjoint
+// takes 2-D domains (d = 1 is a single row), blur_adjoint3 3-D ones.  Widths
+// and radii come from the host so that the radii match the supplied impulse
+// responses exactly.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -56,6 +57,58 @@ __global__ __launch_bounds__(kThreads) void blur_adjoint_kernel(const T* s0, con
     }
 }
 
+// 3-D: one thread per x; the axis-2 Gaussian factors come from the exact
+// recurrence g(z+1) = g(z) r(z), r(z+1) = r(z) exp(-1/s^2) in FP64 (no exp
+// per tap), the axis-0 and axis-1 factors from exp.
+template <class T>
+__global__ __launch_bounds__(kThreads) void blur_adjoint3_kernel(const T* s0, const T* s1, const T* s2,
+                                                                 const int32_t* r0, const int32_t* r1,
+                                                                 const int32_t* r2, int n0, int n1, int n2,
+                                                                 const T* in, int64_t ldin, T* out, int64_t ldout,
+                                                                 int B) {
+    const int64_t plane = (int64_t)n1 * n2;
+    const int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (x >= (int64_t)n0 * plane) return;
+    const int x0 = (int)(x / plane);
+    const int64_t rem = x - (int64_t)x0 * plane;
+    const int x1 = (int)(rem / n2), x2 = (int)(rem - (int64_t)x1 * n2);
+    const double sa = (double)s0[x], sb = (double)s1[x], sc = (double)s2[x];
+    const int Ra = r0[x], Rb = r1[x], Rc = r2[x];
+    const double inv = 1.0 / (gauss_norm(sa, Ra) * gauss_norm(sb, Rb) * gauss_norm(sc, Rc));
+    const int z2lo = -x2 > -Rc ? -x2 : -Rc;
+    const int z2hi = n2 - 1 - x2 < Rc ? n2 - 1 - x2 : Rc;
+    const double g_lo = exp(-(double)z2lo * z2lo / (2 * sc * sc));
+    const double r_lo = exp(-(double)(2 * z2lo + 1) / (2 * sc * sc));
+    const double q2 = exp(-1.0 / (sc * sc));
+    for (int v0 = 0; v0 < B; v0 += kVec) {
+        T acc[kVec];
+        for (int v = 0; v < kVec; ++v) acc[v] = T(0);
+        for (int z0 = -Ra; z0 <= Ra; ++z0) {
+            const int y0 = x0 + z0;
+            if (y0 < 0 || y0 >= n0) continue;
+            const double w0 = exp(-(double)(z0 * z0) / (2 * sa * sa));
+            for (int z1 = -Rb; z1 <= Rb; ++z1) {
+                const int y1 = x1 + z1;
+                if (y1 < 0 || y1 >= n1) continue;
+                const double w01 = w0 * exp(-(double)(z1 * z1) / (2 * sb * sb));
+                const int64_t ybase = (int64_t)y0 * plane + (int64_t)y1 * n2 + x2;
+                double g = g_lo, r = r_lo;
+                for (int z2 = z2lo; z2 <= z2hi; ++z2) {
+                    const T w = (T)(w01 * g);
+                    const int64_t y = ybase + z2;
+#pragma unroll
+                    for (int v = 0; v < kVec; ++v)
+                        if (v0 + v < B) acc[v] += w * in[(int64_t)(v0 + v) * ldin + y];
+                    g *= r;
+                    r *= q2;
+                }
+            }
+        }
+        for (int v = 0; v < kVec; ++v)
+            if (v0 + v < B) out[(int64_t)(v0 + v) * ldout + x] = (T)((double)acc[v] * inv);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -75,6 +128,26 @@ int blur_adjoint(int dtype, const void* s0, const void* s1, const int32_t* r0, c
         hipLaunchKernelGGL(blur_adjoint_kernel<float>, dim3(grid), dim3(kThreads), 0, stream,
                            static_cast<const float*>(s0), static_cast<const float*>(s1), r0, r1, n0, n1,
                            static_cast<const float*>(in), ldin, static_cast<float*>(out), ldout, B);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+// 3-D: s0, s1, s2 widths and r0, r1, r2 radii along axes 0, 1, 2 (device,
+// n0*n1*n2 each); otherwise as blur_adjoint.
+int blur_adjoint3(int dtype, const void* s0, const void* s1, const void* s2, const int32_t* r0, const int32_t* r1,
+                  const int32_t* r2, int n0, int n1, int n2, const void* in, int64_t ldin, void* out, int64_t ldout,
+                  int B, hipStream_t stream) {
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    const unsigned grid = (unsigned)((N + kThreads - 1) / kThreads);
+    if (dtype == 1)
+        hipLaunchKernelGGL(blur_adjoint3_kernel<double>, dim3(grid), dim3(kThreads), 0, stream,
+                           static_cast<const double*>(s0), static_cast<const double*>(s1),
+                           static_cast<const double*>(s2), r0, r1, r2, n0, n1, n2, static_cast<const double*>(in),
+                           ldin, static_cast<double*>(out), ldout, B);
+    else
+        hipLaunchKernelGGL(blur_adjoint3_kernel<float>, dim3(grid), dim3(kThreads), 0, stream,
+                           static_cast<const float*>(s0), static_cast<const float*>(s1),
+                           static_cast<const float*>(s2), r0, r1, r2, n0, n1, n2, static_cast<const float*>(in),
+                           ldin, static_cast<float*>(out), ldout, B);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
