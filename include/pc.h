@@ -57,6 +57,12 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  * Sec. 2.5 (the plain scheme whose boundary artifacts Fig. 2 shows). */
 #define PC_NO_EXTEND (1u << 0)
 
+/* Plan 1-D/2-D work items within half of a CU's LDS (80 KB) and run them in
+ * 512-thread workgroups, two per CU, instead of up to 160 KB in 1024-thread
+ * workgroups (FP32; FP64 items always use 512 threads).  Same results to
+ * rounding; a scheduling choice. */
+#define PC_PLAN_HALF_LDS (1u << 1)
+
 /* pc_create -- build the operator (Sec. 2.2, 2.4, 2.5) and its device data.
  *
  *  d, shape[d]          : Omega.
@@ -76,7 +82,7 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *                         phi_k is taken as 0 outside the supplied box.
  *  dtype                : arithmetic of the apply (FP32 or FP64).  Setup is
  *                         FP64; the spectra are rounded once to dtype.
- *  flags                : PC_NO_EXTEND or 0.
+ *  flags                : PC_NO_EXTEND, PC_PLAN_HALF_LDS, or 0.
  *  s                    : stream used for the uploads (synchronised before
  *                         return).
  *  out                  : receives the operator.

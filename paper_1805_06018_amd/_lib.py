@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpc.so")
 PC_OK, PC_ERR_ARG, PC_ERR_GRID, PC_ERR_OOM, PC_ERR_BUDGET, PC_ERR_DEVICE, PC_ERR_CALLBACK, PC_ERR_UNSUPPORTED = range(8)
 PC_F32, PC_F64 = 0, 1
 PC_NO_EXTEND = 1
+PC_PLAN_HALF_LDS = 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "

@@ -38,7 +38,8 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
             pc::Ctx<T> c = pc::make_ctx<T>(it, adj, &in[(size_t)(b * N)], &slots[(size_t)(b * per)], wts.data(),
                                            reinterpret_cast<const C*>(spec.data()),
                                            reinterpret_cast<const C*>(tw.data()), P.cols);
-            const int nth = pc::threads_for<T>();
+            const int nth = P.conv_threads;
+            for (int t = 0; t < nth; ++t) pc::phA0(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phA(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phB(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phC(c, buf.data(), t, nth);
@@ -97,6 +98,7 @@ void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ld
                 std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
                 const pc::Ctx<T> c =
                     pc::plane_ctx_gather<T>(I, adj, q, iv, sv, wts.data(), specc, twc, pitch, plane_pitch);
+                for (int t = 0; t < NT; ++t) pc::phA0(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phA(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phB(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phC(c, buf.data(), t, NT);
@@ -182,6 +184,19 @@ int pc_emu_stats(pc_emu* e, int64_t* out8) {
     out8[6] = (int64_t)P.contrib_fwd.size();
     out8[7] = P.kernel_elems;
     return 0;
+}
+
+// Per-item geometry (d <= 2): n0, m, ld, in_n0, in_n1, out_n0, out_n1, patch
+// for each item, into out[8 * n_items]; returns the item count.
+int64_t pc_emu_items(pc_emu* e, int32_t* out) {
+    const auto& its = e->plan.items;
+    if (out)
+        for (size_t i = 0; i < its.size(); ++i) {
+            const pc::Item& it = its[i];
+            const int32_t v[8] = {it.n0, it.m, it.ld, it.in_n0, it.in_n1, it.out_n0, it.out_n1, it.patch};
+            std::memcpy(out + 8 * i, v, sizeof(v));
+        }
+    return (int64_t)its.size();
 }
 
 void pc_emu_destroy(pc_emu* e) { delete e; }

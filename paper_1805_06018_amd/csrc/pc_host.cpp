@@ -416,6 +416,7 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
     D.slot_fwd = P.slot_fwd;
     D.slot_adj = P.slot_adj;
     D.max_lds = P.max_lds;
+    D.conv_threads = P.conv_threads;
     D.max_lds_axis = P.max_lds_axis;
     D.dtype = (int)dtype;
     op->leaf_box = static_cast<int32_t*>(d_leaf);

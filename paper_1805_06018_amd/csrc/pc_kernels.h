@@ -23,6 +23,7 @@ struct DevPlan {
     const Box* cboxes_adj;
     int64_t slot_fwd, slot_adj;     // staging elements per vector
     int max_lds;
+    int conv_threads;               // 1-D/2-D convolution workgroup size (1024 or 512)
     int max_lds_axis;               // 3-D axis-0 kernel
     int dtype;                      // 0 = f32, 1 = f64
 };

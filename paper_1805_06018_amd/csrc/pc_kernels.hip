@@ -24,11 +24,10 @@ struct ConvArgs {
 // XCDs (block id mod 8); the mapping below gives every XCD whole items with
 // all their vectors in sequence, so a patch's spectrum is fetched into one
 // XCD's L2 and reused there by every vector.
-template <class T>
-__global__ __launch_bounds__(threads_for<T>()) void conv_kernel(ConvArgs<T> A) {
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
-    constexpr int NT = threads_for<T>();
     const int bid = blockIdx.x;
     const int xcd = bid & 7, l = bid >> 3;
     const int item = xcd + 8 * (l / A.B);
@@ -38,6 +37,8 @@ __global__ __launch_bounds__(threads_for<T>()) void conv_kernel(ConvArgs<T> A) {
     const Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
                                  A.wts, A.spec, A.tw, A.pitch);
     const int tid = threadIdx.x;
+    phA0(c, buf, tid, NT);
+    __syncthreads();
     phA(c, buf, tid, NT);
     __syncthreads();
     phB(c, buf, tid, NT);
@@ -92,6 +93,8 @@ __global__ __launch_bounds__(kPlaneThreads) void plane_fwd_kernel(Conv3Args<T> A
     const Ctx<T> c = plane_ctx_gather<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
                                          A.wts, A.spec, A.tw, A.pitch, A.plane_pitch);
     const int tid = threadIdx.x;
+    phA0(c, buf, tid, NT);
+    __syncthreads();
     phA(c, buf, tid, NT);
     __syncthreads();
     phB(c, buf, tid, NT);
@@ -311,7 +314,14 @@ static hipError_t conv_t(const DevPlan& P, bool adj, int item_lo, int item_hi, i
     const int64_t per_xcd = (int64_t)((A.n_items + 7) / 8) * B;
     const int64_t nblk = 8 * per_xcd;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(conv_kernel<T>, dim3((unsigned)nblk), dim3(threads_for<T>()), P.max_lds, s, A);
+    if (P.conv_threads == 512) {
+        hipLaunchKernelGGL((conv_kernel<T, 512>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
+    } else {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((conv_kernel<T, 1024>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+        else
+            return hipErrorInvalidValue;   // FP64 items always use 512 threads
+    }
     return hipGetLastError();
 }
 
@@ -363,7 +373,8 @@ hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, c
 
 hipError_t set_kernel_attributes() {
     const void* fns[] = {
-        reinterpret_cast<const void*>(&conv_kernel<float>),      reinterpret_cast<const void*>(&conv_kernel<double>),
+        reinterpret_cast<const void*>(&conv_kernel<float, 1024>), reinterpret_cast<const void*>(&conv_kernel<float, 512>),
+        reinterpret_cast<const void*>(&conv_kernel<double, 512>),
         reinterpret_cast<const void*>(&plane_fwd_kernel<float>), reinterpret_cast<const void*>(&plane_fwd_kernel<double>),
         reinterpret_cast<const void*>(&axis_kernel<float>),      reinterpret_cast<const void*>(&axis_kernel<double>),
         reinterpret_cast<const void*>(&plane_inv_kernel<float>), reinterpret_cast<const void*>(&plane_inv_kernel<double>)};

@@ -13,7 +13,8 @@
 // transform undoes the passes in reverse, so no reordering pass is needed.
 //
 // Phases (one barrier between consecutive phases):
-//   A gather (weighted for the forward sum) + row pass 1
+//   A0 coalesced gather into LDS (weighted for the forward sum)
+//   A  row pass 1 in place
 //   B row pass 2 fused with the real-row post-processing: a task owns the
 //     slot groups k1 and m-k1's group, which hold every pair Z[k], Z[m-k]
 //   C column pass 1 (only the gathered rows are non-zero)
@@ -32,11 +33,6 @@
 #include "pc_internal.h"
 
 namespace pc {
-
-template <class T>
-constexpr int threads_for() {
-    return sizeof(T) == 4 ? 1024 : 512;
-}
 
 // floor(x / d) for 0 <= x < 2^22 with inv = 1.0f / d (exact: the fraction
 // (x + 1/2) / d stays at least 1/(2d) away from an integer).
@@ -128,35 +124,56 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
 constexpr int kMaxRowPass2Radix = 10;
 
 // ---------------------------------------------------------------- phase A
+// A0: coalesced copy of the gathered box into LDS, weighted for the forward
+// sum: each gathered row holds the real samples 0..2m-1 (zero outside the
+// box) as m complex (even, odd) pairs.  A fixed set of threads owns each
+// column, so consecutive lanes read consecutive input columns.
+template <class T>
+__host__ __device__ inline void phA0(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+    constexpr int U = 8;                 // rows whose loads are in flight together
+    const int n = 2 * c.it.m;            // real samples per row
+    const int rps = nth / n;             // rows per sweep (n <= 256 <= nth)
+    const int r0 = tid / n, col = tid - r0 * n;
+    if (r0 >= rps) return;
+    const int e = col - c.s_off1;        // column inside the gathered box
+    const bool live = (unsigned)e < (unsigned)c.s_n1;
+    const bool wgt = live && !c.adj;
+    T* rows = reinterpret_cast<T*>(buf) + (int64_t)c.s_off0 * (2 * c.it.ld) + col;
+    const int64_t rstride = 2 * (int64_t)c.it.ld;
+    const T* src = c.src + (int64_t)(c.it.g0 + c.s_off0) * c.pitch + c.it.g1 + col;
+    const T* w = c.w + e;
+    int q = r0;
+    for (; q + (U - 1) * rps < c.s_n0; q += U * rps) {
+        T v[U], f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = live ? src[(int64_t)(q + u * rps) * c.pitch] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) f[u] = wgt ? w[(int64_t)(q + u * rps) * c.it.w_ld] : T(1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) rows[(q + u * rps) * rstride] = v[u] * f[u];
+    }
+    for (; q < c.s_n0; q += rps) {
+        T v = live ? src[(int64_t)q * c.pitch] : T(0);
+        if (wgt) v *= w[(int64_t)q * c.it.w_ld];
+        rows[q * rstride] = v;
+    }
+}
+
+// A1: row pass 1 in place on the gathered rows: the thread that reads slots
+// bm j1 + j0 writes the twiddled DFT_am outputs back to slots bm k1 + j0.
 template <int A, class T>
 __host__ __device__ inline void phA_r(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
     const int bm = c.it.bm, ld = c.it.ld;
     const int ntask = c.s_n0 * bm;
     for (int t = tid; t < ntask; t += nth) {
         const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
-        const int row = c.s_off0 + q;
-        const T* srow = c.src + (int64_t)(c.it.g0 + row) * c.pitch + c.it.g1;
-        const T* wrow = c.w + (int64_t)q * c.it.w_ld;
+        cx<T>* p = buf + (int64_t)(c.s_off0 + q) * ld + j0;
         cx<T> x[A];
 #pragma unroll
-        for (int j1 = 0; j1 < A; ++j1) {
-            const int j = bm * j1 + j0;
-            const int e0 = 2 * j - c.s_off1, e1 = e0 + 1;
-            T v0 = T(0), v1 = T(0);
-            if ((unsigned)e0 < (unsigned)c.s_n1) {
-                v0 = srow[2 * j];
-                if (!c.adj) v0 *= wrow[e0];
-            }
-            if ((unsigned)e1 < (unsigned)c.s_n1) {
-                v1 = srow[2 * j + 1];
-                if (!c.adj) v1 *= wrow[e1];
-            }
-            x[j1] = {v0, v1};
-        }
+        for (int j1 = 0; j1 < A; ++j1) x[j1] = p[bm * j1];
         Dft<A, -1>::run(x);
-        cx<T>* out = buf + (int64_t)row * ld + j0;
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) out[bm * k1] = cmul(x[k1], c.twm[j0 * k1]);
+        for (int k1 = 0; k1 < A; ++k1) p[bm * k1] = cmul(x[k1], c.twm[j0 * k1]);
     }
 }
 template <class T>
@@ -439,18 +456,35 @@ __host__ __device__ inline void phG(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 }
 
 // ---------------------------------------------------------------- phase H
-// Copy of the written box from LDS to the staging buffer, consecutive lanes on
-// consecutive columns (weighted for the adjoint).
+// Copy of the written box from LDS to the staging buffer (weighted for the
+// adjoint).  A fixed set of threads owns each column of the box, so
+// consecutive lanes write consecutive staging elements and no index is
+// divided per element.
 template <class T>
 __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    const int n1 = c.d_n1, ntask = c.d_n0 * n1;
-    const float inv = 1.0f / (float)n1;
-    const T* rows = reinterpret_cast<const T*>(buf);
-    for (int t = tid; t < ntask; t += nth) {
-        const int q = fdiv(t, inv), e = t - q * n1;
-        T v = rows[(int64_t)(c.d_off0 + q) * (2 * c.it.ld) + c.d_off1 + e];
-        if (c.adj) v *= c.w[(int64_t)q * c.it.w_ld + e];
-        c.dst[t] = v;
+    constexpr int U = 4;
+    const int n1 = c.d_n1;
+    const int rps = nth / n1;            // rows per sweep (n1 <= 256 <= nth)
+    const int r0 = tid / n1, e = tid - r0 * n1;
+    if (r0 >= rps) return;
+    const T* rows = reinterpret_cast<const T*>(buf) + (int64_t)c.d_off0 * (2 * c.it.ld) + c.d_off1 + e;
+    const int64_t rstride = 2 * (int64_t)c.it.ld;
+    const T* w = c.w + e;
+    T* dst = c.dst + e;
+    int q = r0;
+    for (; q + (U - 1) * rps < c.d_n0; q += U * rps) {
+        T v[U], f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = rows[(q + u * rps) * rstride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) f[u] = c.adj ? w[(int64_t)(q + u * rps) * c.it.w_ld] : T(1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[(int64_t)(q + u * rps) * n1] = v[u] * f[u];
+    }
+    for (; q < c.d_n0; q += rps) {
+        T v = rows[q * rstride];
+        if (c.adj) v *= w[(int64_t)q * c.it.w_ld];
+        dst[(int64_t)q * n1] = v;
     }
 }
 

@@ -294,7 +294,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         err = "dtype must be PC_F32 or PC_F64";
         return PC_ERR_ARG;
     }
-    if (a.flags & ~(uint32_t)PC_NO_EXTEND) {
+    if (a.flags & ~(uint32_t)(PC_NO_EXTEND | PC_PLAN_HALF_LDS)) {
         err = "unknown flag bits";
         return PC_ERR_ARG;
     }
@@ -496,6 +496,9 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     // ------------------------------------------------ extension + planning
     const bool extend = !(a.flags & PC_NO_EXTEND);
     const size_t csz = (a.dtype == PC_F64) ? 16 : 8;
+    const bool half = (a.flags & PC_PLAN_HALF_LDS) != 0;
+    const int64_t lds_cap = half ? kLdsBytes / 2 : kLdsBytes;
+    p.conv_threads = (half || a.dtype == PC_F64) ? 512 : 1024;
     std::map<int, int> tw_off;   // length -> complex offset
     auto want_tw = [&](int len) {
         if (tw_off.count(len)) return tw_off[len];
@@ -595,7 +598,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 const int64_t h0 = (m[0] + P0 - 1) / P0;
                 const int n0p = (d == 1) ? 1 : next_fft_size((int)(h0 + K[0] - 1));
                 if (n0p < 0) continue;
-                if ((int64_t)n0p * ld_p * (int64_t)csz > kLdsBytes) continue;
+                if ((int64_t)n0p * ld_p * (int64_t)csz > lds_cap) continue;
                 const double nn = (double)n0p * 2.0 * Mp;
                 const double cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
                 if (cost < best_cost) {

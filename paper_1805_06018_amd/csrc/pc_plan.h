@@ -51,6 +51,7 @@ struct Plan {
     std::vector<int32_t> leaf_box;   // [L][6]: plane, row, col origin and extents (planes x prow x cols view)
     int64_t slot_fwd = 0, slot_adj = 0;   // staging elements per vector
     int max_lds = 0;
+    int conv_threads = 1024;         // workgroup size of the 1-D/2-D convolution kernel
     // statistics
     int64_t sum_fft_points = 0;
     double alg_flops = 0.0;
