@@ -101,6 +101,22 @@ pc_status pc_create(int d, const int64_t* shape,
                     const double* phi, const int64_t* phi_off,
                     pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out);
 
+/* pc_create_patches -- the operator restricted to a subset S of the terms of
+ * the sum (eq. (2.5)):  A~_S u = sum_{k in S} phi_k^E * (w_k . u),  with w_k
+ * and phi_k^E those of the full tiling (arguments as pc_create).  It serves
+ * the incremental update of Y~ = A~* Z during refinement (Sec. 2.8): only the
+ * terms of new points and of points whose cells, weights or neighbours
+ * changed are convolved again.  sel[n_sel]: distinct point indices in [0, r)
+ * (host, any order); n_sel = 0 gives the zero operator; n_sel < 0 or an
+ * index out of range or repeated gives PC_ERR_ARG.  Only the selected
+ * patches' weights, spectra and work items are built and held. */
+pc_status pc_create_patches(int d, const int64_t* shape,
+                            int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                            int64_t r, const int64_t* points, const int64_t* radius,
+                            const double* phi, const int64_t* phi_off,
+                            pc_dtype dtype, uint32_t flags, int64_t n_sel, const int64_t* sel,
+                            hipStream_t s, pc_op** out);
+
 /* pc_apply -- out = A~ u for one vector (eq. (2.5)).  u, out: device, N
  * elements of the operator's dtype; out must not alias u. */
 pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s);
@@ -122,6 +138,18 @@ pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ld
  * order.  Kept as the baseline the fused path is measured against. */
 pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu,
                                void* OUT, int64_t ldo, hipStream_t s);
+
+/* pc_apply_batch_axpy / pc_apply_adjoint_batch_axpy -- OUT[:, j] += alpha *
+ * A~ U[:, j] (eq. (2.5)) or OUT[:, j] += alpha * A~* V[:, j] (eq. (1.6)):
+ * the deterministic patch sum of every output point is formed first, then
+ * scaled by alpha (rounded to the operator's dtype) and added to OUT once.
+ * OUT must not alias the input.  Used to update Y~ in place with the terms
+ * of a pc_create_patches operator (alpha = -1 for the old terms, +1 for the
+ * new ones). */
+pc_status pc_apply_batch_axpy(pc_op* op, int64_t B, const void* U, int64_t ldu, double alpha,
+                              void* OUT, int64_t ldo, hipStream_t s);
+pc_status pc_apply_adjoint_batch_axpy(pc_op* op, int64_t B, const void* V, int64_t ldv, double alpha,
+                                      void* OUT, int64_t ldo, hipStream_t s);
 
 /* Exact adjoint matvec supplied by the caller: out[:, j] = A* in[:, j] for
  * j < B on stream s (device arrays of the operator's dtype).  Return 0 on
@@ -148,6 +176,16 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
                             hipStream_t s);
 
 /* Plan statistics (for measurement and admission). */
+/* pc_estimate_sums -- the estimator of Sec. 2.6 (eq. (2.11)) from a Y~ the
+ * caller already holds (e.g. updated incrementally with the axpy calls):
+ * eta_leaf[c] = sqrt(sum_{x in C} sum_i (Y~ - Y)^2 / q) over the operator's
+ * leaves, eta_abs, eta_rel as pc_error_estimate.  Yt, Y: device [q][ldt],
+ * [q][ldy] of the operator's dtype; host outputs written after the stream
+ * is synchronised. */
+pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt,
+                           const void* Y, int64_t ldy, double* eta_leaf,
+                           double* eta_abs, double* eta_rel, hipStream_t s);
+
 typedef struct {
     int64_t n;              /* N = |Omega|                                          */
     int64_t r;              /* number of sample points                              */

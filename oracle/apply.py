@@ -4,7 +4,8 @@ Forward (eq. (2.5)):  (A~ f)[y] = sum_k sum_{x in U_k} w_k[x] f[x] phi_k^E[y - x
 Adjoint (eq. (1.6)):  (A~* g)[x] = sum_k w_k[x] sum_{y in Omega} phi_k^E[y - x] g[y].
 Matrix entries (Sec. 3.1): A~[y, x] = sum_{k : x in U_k} w_k[x] phi_k^E[y - x].
 
-Everything is FP64 and summed over k in ascending order.  The per-patch
+Everything is FP64 and summed over k in ascending order (optionally over a
+subset of the terms only).  The per-patch
 convolution is a plain double loop (NumPy over the input box for each kernel
 offset, or the C core in ``direct`` for larger grids); no FFT is used.
 """
@@ -92,29 +93,36 @@ class OracleOperator:
             return "c" if self.N > 8192 else "numpy"
         return backend
 
-    def apply(self, f, backend=None):
+    def _terms(self, patches):
+        """Ascending point indices of the terms summed: all, or a subset (the
+        terms Sec. 2.8 recomputes after a refinement)."""
+        if patches is None:
+            return range(self.grid.r)
+        return sorted(int(k) for k in patches)
+
+    def apply(self, f, backend=None, patches=None):
         backend = self._backend(backend)
         f = np.asarray(f, dtype=np.float64).reshape(self.shape)
         out = np.zeros(self.shape)
-        for k in range(self.grid.r):
+        for k in self._terms(patches):
             sl = tuple(slice(int(self.u_lo[k, i]), int(self.u_hi[k, i] + 1)) for i in range(self.d))
             t = self.W[k] * f[sl]
             self._conv_patch(k, t, out, backend)
         return out.ravel()
 
-    def apply_adjoint(self, g, backend=None):
+    def apply_adjoint(self, g, backend=None, patches=None):
         backend = self._backend(backend)
         g = np.asarray(g, dtype=np.float64).reshape(self.shape)
         out = np.zeros(self.shape)
-        for k in range(self.grid.r):
+        for k in self._terms(patches):
             sl = tuple(slice(int(self.u_lo[k, i]), int(self.u_hi[k, i] + 1)) for i in range(self.d))
             out[sl] += self.W[k] * self._corr_patch(k, g, backend)
         return out.ravel()
 
-    def apply_batch(self, F, adjoint=False, backend=None):
+    def apply_batch(self, F, adjoint=False, backend=None, patches=None):
         F = np.asarray(F, dtype=np.float64).reshape(-1, self.N)
         fn = self.apply_adjoint if adjoint else self.apply
-        return np.stack([fn(f, backend) for f in F])
+        return np.stack([fn(f, backend, patches) for f in F])
 
     def entry(self, y, x):
         """A~[y, x] from the matrix-entry formula (Sec. 3.1)."""

@@ -45,11 +45,19 @@ class PcProfile(ctypes.Structure):
 _lib.pc_create.argtypes = [ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, ctypes.c_int,
                            ctypes.c_uint32, _P, ctypes.POINTER(_P)]
 _lib.pc_create.restype = ctypes.c_int
+_lib.pc_create_patches.argtypes = [ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, ctypes.c_int,
+                                   ctypes.c_uint32, _I64, _P, _P, ctypes.POINTER(_P)]
+_lib.pc_create_patches.restype = ctypes.c_int
 _lib.pc_apply.argtypes = [_P, _P, _P, _P]
 _lib.pc_apply.restype = ctypes.c_int
 for _name in ("pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain"):
     getattr(_lib, _name).argtypes = [_P, _I64, _P, _I64, _P, _I64, _P]
     getattr(_lib, _name).restype = ctypes.c_int
+for _name in ("pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy"):
+    getattr(_lib, _name).argtypes = [_P, _I64, _P, _I64, ctypes.c_double, _P, _I64, _P]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.pc_estimate_sums.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P]
+_lib.pc_estimate_sums.restype = ctypes.c_int
 _lib.pc_error_estimate.argtypes = [_P, _I64, _P, _I64, _P, _I64, MATVEC_FN, _P, _P, _P, _P, _P]
 _lib.pc_error_estimate.restype = ctypes.c_int
 _lib.pc_get_stats.argtypes = [_P, ctypes.POINTER(PcStats)]
@@ -70,7 +78,8 @@ _lib.pc_status_string.restype = ctypes.c_char_p
 _lib.pc_last_error.argtypes = []
 _lib.pc_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ["pc_create", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain",
+EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
+            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_estimate_sums",
             "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
 
@@ -118,15 +127,24 @@ class PcOperator:
     copied); the apply methods take torch tensors on the device."""
 
     def __init__(self, d, shape, leaf_lo, leaf_hi, points, radius, phi, phi_off,
-                 dtype=PC_F32, flags=0, stream=None):
+                 dtype=PC_F32, flags=0, stream=None, patches=None):
+        """patches: None for the full operator, else the point indices whose
+        terms the operator keeps (pc_create_patches)."""
         self._keep = [_i64(shape), _i64(leaf_lo), _i64(leaf_hi), _i64(points), _i64(radius),
                       np.ascontiguousarray(phi, dtype=np.float64), _i64(phi_off)]
         k = self._keep
         h = _P()
-        st = _lib.pc_create(int(d), k[0].ctypes.data, int(k[1].size // d), k[1].ctypes.data,
-                            k[2].ctypes.data, int(k[3].size // d), k[3].ctypes.data, k[4].ctypes.data,
-                            k[5].ctypes.data, k[6].ctypes.data, int(dtype), int(flags),
-                            _stream(stream), ctypes.byref(h))
+        if patches is None:
+            st = _lib.pc_create(int(d), k[0].ctypes.data, int(k[1].size // d), k[1].ctypes.data,
+                                k[2].ctypes.data, int(k[3].size // d), k[3].ctypes.data, k[4].ctypes.data,
+                                k[5].ctypes.data, k[6].ctypes.data, int(dtype), int(flags),
+                                _stream(stream), ctypes.byref(h))
+        else:
+            sel = _i64(patches).ravel()
+            st = _lib.pc_create_patches(int(d), k[0].ctypes.data, int(k[1].size // d), k[1].ctypes.data,
+                                        k[2].ctypes.data, int(k[3].size // d), k[3].ctypes.data, k[4].ctypes.data,
+                                        k[5].ctypes.data, k[6].ctypes.data, int(dtype), int(flags), int(sel.size),
+                                        sel.ctypes.data, _stream(stream), ctypes.byref(h))
         _check(st)
         self._h = h
         self.d = int(d)
@@ -162,6 +180,32 @@ class PcOperator:
 
     def apply_batch_plain(self, U, OUT, stream=None):
         return self._batch(_lib.pc_apply_batch_plain, U, OUT, stream)
+
+    def _axpy(self, fn, U, alpha, OUT, stream):
+        B = 1 if U.dim() == 1 else U.shape[0]
+        _check(fn(self._h, B, _dev(U, self.torch_dtype, "U"), _ld(U, "U"), float(alpha),
+                  _dev(OUT, self.torch_dtype, "OUT"), _ld(OUT, "OUT"), _stream(stream)))
+        return OUT
+
+    def apply_batch_axpy(self, U, alpha, OUT, stream=None):
+        """OUT += alpha * A~ U."""
+        return self._axpy(_lib.pc_apply_batch_axpy, U, alpha, OUT, stream)
+
+    def apply_adjoint_batch_axpy(self, V, alpha, OUT, stream=None):
+        """OUT += alpha * A~* V."""
+        return self._axpy(_lib.pc_apply_adjoint_batch_axpy, V, alpha, OUT, stream)
+
+    def estimate_sums(self, Yt, Y, stream=None):
+        """Estimator of Sec. 2.6 from a given Y~ (pc_estimate_sums):
+        (eta_leaf[n_leaves], eta_abs, eta_rel)."""
+        q = 1 if Yt.dim() == 1 else Yt.shape[0]
+        eta = np.zeros(self.n_leaves)
+        ea = ctypes.c_double()
+        er = ctypes.c_double()
+        _check(_lib.pc_estimate_sums(self._h, q, _dev(Yt, self.torch_dtype, "Yt"), _ld(Yt, "Yt"),
+                                     _dev(Y, self.torch_dtype, "Y"), _ld(Y, "Y"), eta.ctypes.data,
+                                     ctypes.byref(ea), ctypes.byref(er), _stream(stream)))
+        return eta, ea.value, er.value
 
     def error_estimate(self, Z, Y=None, exact_adjoint=None, stream=None):
         """Returns (eta_leaf[n_leaves], eta_abs, eta_rel).  exact_adjoint, if
@@ -214,17 +258,24 @@ class PcOperator:
 
 
 def raw_create(d, shape, leaf_lo, leaf_hi, points, radius, phi, phi_off, dtype=PC_F32, flags=0,
-               n_leaves=None, r=None):
-    """pc_create with explicit counts (for argument-validation tests).
-    Returns (status, message)."""
+               n_leaves=None, r=None, patches=None, n_sel=None):
+    """pc_create (or pc_create_patches when patches / n_sel is given) with
+    explicit counts, for argument-validation tests.  Returns (status, message)."""
     k = [_i64(shape), _i64(leaf_lo), _i64(leaf_hi), _i64(points), _i64(radius),
          np.ascontiguousarray(phi, dtype=np.float64), _i64(phi_off)]
     h = _P()
     L = int(k[1].size // max(d, 1)) if n_leaves is None else n_leaves
     R = int(k[3].size // max(d, 1)) if r is None else r
-    st = _lib.pc_create(int(d), k[0].ctypes.data, L, k[1].ctypes.data, k[2].ctypes.data, R,
-                        k[3].ctypes.data, k[4].ctypes.data, k[5].ctypes.data, k[6].ctypes.data,
-                        int(dtype), int(flags), None, ctypes.byref(h))
+    if patches is None and n_sel is None:
+        st = _lib.pc_create(int(d), k[0].ctypes.data, L, k[1].ctypes.data, k[2].ctypes.data, R,
+                            k[3].ctypes.data, k[4].ctypes.data, k[5].ctypes.data, k[6].ctypes.data,
+                            int(dtype), int(flags), None, ctypes.byref(h))
+    else:
+        sel = _i64(patches if patches is not None else []).ravel()
+        ns = int(sel.size) if n_sel is None else int(n_sel)
+        st = _lib.pc_create_patches(int(d), k[0].ctypes.data, L, k[1].ctypes.data, k[2].ctypes.data, R,
+                                    k[3].ctypes.data, k[4].ctypes.data, k[5].ctypes.data, k[6].ctypes.data,
+                                    int(dtype), int(flags), ns, sel.ctypes.data, None, ctypes.byref(h))
     msg = _lib.pc_last_error().decode()
     if st == PC_OK:
         _lib.pc_destroy(h)

@@ -156,6 +156,26 @@ int pc_emu_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* 
     return 0;
 }
 
+// As pc_emu_create, keeping only the terms of the selected points.
+int pc_emu_create_patches(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo,
+                          const int64_t* leaf_hi, int64_t r, const int64_t* points, const int64_t* radius,
+                          const double* phi, const int64_t* phi_off, int dtype, uint32_t flags, int64_t n_sel,
+                          const int64_t* sel, pc_emu** out) {
+    *out = nullptr;
+    pc_emu* e = new pc_emu();
+    pc::CreateArgs a{d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags,
+                     n_sel, sel};
+    std::string err;
+    pc_status st = pc::build_plan(a, e->plan, err);
+    if (st != PC_OK) {
+        g_emu_err = err;
+        delete e;
+        return (int)st;
+    }
+    *out = e;
+    return 0;
+}
+
 int pc_emu_apply(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo) {
     if (e->plan.d == 3) {
         if (e->plan.dtype == PC_F64)

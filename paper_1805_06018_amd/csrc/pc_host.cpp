@@ -176,7 +176,7 @@ pc_status ensure_aux(pc_op* op) {
 // item groups sized by the scratch buffer each run the three kernels of
 // pc_phases3.h; one reduction per chunk.
 pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
-                       hipStream_t s) {
+                       hipStream_t s, bool acc, double alpha) {
     const pc::Plan& P = op->plan;
     const int64_t per = adj ? P.slot_adj : P.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
@@ -244,7 +244,7 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
             prof_end(op, s, ev, 0, g == 0 ? nb : 0);
         }
         prof_begin(op, s, &ev);
-        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s);
+        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s, acc, alpha);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
         prof_end(op, s, ev, 1, nb);
     }
@@ -252,7 +252,7 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
 }
 
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
-                    hipStream_t s) {
+                    hipStream_t s, bool acc = false, double alpha = 1.0) {
     pc_status st = check_op(op);
     if (st != PC_OK) return st;
     const int64_t N = op->plan.N;
@@ -261,7 +261,7 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
     if (ldu < N || ldo < N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
-    if (op->plan.d == 3) return run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s);
+    if (op->plan.d == 3) return run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
     const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     int64_t chunk = 1;
@@ -315,7 +315,7 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
             rs = op->aux;
         }
         prof_begin(op, rs, &ev);
-        e = pc::launch_reduce(op->dev, adj, nb, slots, per, out, ldo, rs);
+        e = pc::launch_reduce(op->dev, adj, nb, slots, per, out, ldo, rs, acc, alpha);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
         prof_end(op, rs, ev, 1, nb);
         if (overlap) {
@@ -330,19 +330,16 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     return PC_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
-                    int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
-                    const int64_t* phi_off, pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out) {
-    (void)s;
+pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                      int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
+                      const int64_t* phi_off, pc_dtype dtype, uint32_t flags, int64_t n_sel, const int64_t* sel,
+                      pc_op** out) {
     if (!out) return fail(PC_ERR_ARG, "null output handle");
     *out = nullptr;
     pc_op* op = new (std::nothrow) pc_op();
     if (!op) return fail(PC_ERR_OOM, "host allocation failed");
-    pc::CreateArgs a{d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, (int)dtype, flags};
+    pc::CreateArgs a{d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, (int)dtype, flags,
+                     n_sel, sel};
     std::string err;
     pc_status st;
     try {
@@ -431,6 +428,60 @@ pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t
     return PC_OK;
 }
 
+// Estimator sums (Sec. 2.6) of Yt - Y over the operator's leaves.
+pc_status est_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy, double* eta_leaf,
+                   double* eta_abs, double* eta_rel, hipStream_t s) {
+    const int L = (int)op->plan.L;
+    const int n_part = 512;
+    void* est = op->est;
+    pc_status st = ensure(&est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 * n_part), "hipMalloc (estimator sums)");
+    op->est = static_cast<double*>(est);
+    if (st != PC_OK) return st;
+    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, ldt, Y, ldy, op->plan.planes,
+                                  op->plan.prow, op->plan.cols, op->est, op->est + L, n_part, s);
+    if (e != hipSuccess) return hip_fail(e, "estimator launch");
+    std::vector<double> h((size_t)L + 2 * n_part);
+    e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (estimator sums)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (estimator)");
+    double dd = 0.0, yy = 0.0;
+    for (int i = 0; i < n_part; ++i) {
+        dd += h[(size_t)L + 2 * i];
+        yy += h[(size_t)L + 2 * i + 1];
+    }
+    if (eta_leaf)
+        for (int c = 0; c < L; ++c) eta_leaf[c] = std::sqrt(h[(size_t)c] / (double)q);
+    *eta_abs = std::sqrt(dd / (double)q);
+    *eta_rel = yy > 0.0 ? std::sqrt(dd) / std::sqrt(yy) : INFINITY;
+    return PC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
+                    int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
+                    const int64_t* phi_off, pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out) {
+    (void)s;
+    return create_impl(d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags, -1,
+                       nullptr, out);
+}
+
+pc_status pc_create_patches(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo,
+                            const int64_t* leaf_hi, int64_t r, const int64_t* points, const int64_t* radius,
+                            const double* phi, const int64_t* phi_off, pc_dtype dtype, uint32_t flags,
+                            int64_t n_sel, const int64_t* sel, hipStream_t s, pc_op** out) {
+    (void)s;
+    if (n_sel < 0) {
+        if (out) *out = nullptr;
+        return fail(PC_ERR_ARG, "negative selection size");
+    }
+    return create_impl(d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags, n_sel,
+                       sel, out);
+}
+
 pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s) {
     if (!op) return fail(PC_ERR_ARG, "null operator");
     return run_batch(op, false, false, 1, u, op->plan.N, out, op->plan.N, s);
@@ -448,6 +499,26 @@ pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ld
 pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
                                hipStream_t s) {
     return run_batch(op, false, true, B, U, ldu, OUT, ldo, s);
+}
+
+pc_status pc_apply_batch_axpy(pc_op* op, int64_t B, const void* U, int64_t ldu, double alpha, void* OUT, int64_t ldo,
+                              hipStream_t s) {
+    return run_batch(op, false, false, B, U, ldu, OUT, ldo, s, true, alpha);
+}
+
+pc_status pc_apply_adjoint_batch_axpy(pc_op* op, int64_t B, const void* V, int64_t ldv, double alpha, void* OUT,
+                                      int64_t ldo, hipStream_t s) {
+    return run_batch(op, true, false, B, V, ldv, OUT, ldo, s, true, alpha);
+}
+
+pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
+                           double* eta_leaf, double* eta_abs, double* eta_rel, hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    const int64_t N = op->plan.N;
+    if (q < 1 || !Yt || !Y || ldt < N || ldy < N) return fail(PC_ERR_ARG, "invalid estimator blocks");
+    if (!eta_abs || !eta_rel) return fail(PC_ERR_ARG, "null output scalar");
+    return est_sums(op, q, Yt, ldt, Y, ldy, eta_leaf, eta_abs, eta_rel, s);
 }
 
 pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, const void* Y_or_null, int64_t ldy,
@@ -476,30 +547,7 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, co
     }
     st = run_batch(op, true, false, q, Z, ldz, Yt, N, s);
     if (st != PC_OK) return st;
-    const int L = (int)op->plan.L;
-    const int n_part = 512;
-    void* est = op->est;
-    st = ensure(&est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 * n_part), "hipMalloc (estimator sums)");
-    op->est = static_cast<double*>(est);
-    if (st != PC_OK) return st;
-    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, N, Y, ldY, op->plan.planes, op->plan.prow,
-                                      op->plan.cols, op->est, op->est + L, n_part, s);
-    if (e != hipSuccess) return hip_fail(e, "estimator launch");
-    std::vector<double> h((size_t)L + 2 * n_part);
-    e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (estimator sums)");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (estimator)");
-    double dd = 0.0, yy = 0.0;
-    for (int i = 0; i < n_part; ++i) {
-        dd += h[(size_t)L + 2 * i];
-        yy += h[(size_t)L + 2 * i + 1];
-    }
-    if (eta_leaf)
-        for (int c = 0; c < L; ++c) eta_leaf[c] = std::sqrt(h[(size_t)c] / (double)q);
-    *eta_abs = std::sqrt(dd / (double)q);
-    *eta_rel = yy > 0.0 ? std::sqrt(dd) / std::sqrt(yy) : INFINITY;
-    return PC_OK;
+    return est_sums(op, q, Yt, N, Y, ldY, eta_leaf, eta_abs, eta_rel, s);
 }
 
 pc_status pc_get_stats(const pc_op* op, pc_stats* st) {

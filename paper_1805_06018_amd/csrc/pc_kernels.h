@@ -53,9 +53,10 @@ hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi,
 // 3-D convolution items -> staging (three kernels, see pc_phases3.h).
 hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s);
 
-// Deterministic reduction of the staging boxes into the outputs.
+// Deterministic reduction of the staging boxes into the outputs (out = sum,
+// or out += alpha * sum with accumulate).
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride,
-                         void* out, int64_t ldo, hipStream_t s);
+                         void* out, int64_t ldo, hipStream_t s, bool accumulate = false, double alpha = 1.0);
 
 // Estimator: per-leaf (leaf_box [L][6]) FP64 sums of squares of (Yt - Y) over q vectors and
 // the totals sum (Yt - Y)^2 and sum Y^2 (per row-block partials).

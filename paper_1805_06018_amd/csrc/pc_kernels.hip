@@ -214,10 +214,12 @@ hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s) {
 
 template <class T>
 __global__ __launch_bounds__(kReduceCols) void reduce_kernel(const Tile* tiles, const Box* cboxes, const T* slots,
-                                                             int64_t slot_stride, T* out, int64_t ldo, int64_t pitch) {
+                                                             int64_t slot_stride, T* out, int64_t ldo, int64_t pitch,
+                                                             int accumulate, T alpha) {
     const Tile t = tiles[blockIdx.x];
     const int rhs = blockIdx.y;
-    reduce_tile<T>(t, threadIdx.x, cboxes, slots + (int64_t)rhs * slot_stride, out + (int64_t)rhs * ldo, pitch);
+    reduce_tile<T>(t, threadIdx.x, cboxes, slots + (int64_t)rhs * slot_stride, out + (int64_t)rhs * ldo, pitch,
+                   accumulate != 0, alpha);
 }
 
 // ---------------------------------------------------------------- estimator
@@ -332,7 +334,7 @@ hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi,
 }
 
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride, void* out,
-                         int64_t ldo, hipStream_t s) {
+                         int64_t ldo, hipStream_t s, bool accumulate, double alpha) {
     const int nt = adjoint ? P.n_tiles_adj : P.n_tiles_fwd;
     if (nt <= 0 || B <= 0) return hipSuccess;
     const Tile* tiles = adjoint ? P.tiles_adj : P.tiles_fwd;
@@ -341,11 +343,11 @@ hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slot
     if (P.dtype == 1)
         hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
                            static_cast<const double*>(slots), slot_stride, static_cast<double*>(out), ldo,
-                           (int64_t)P.cols);
+                           (int64_t)P.cols, accumulate ? 1 : 0, alpha);
     else
         hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
                            static_cast<const float*>(slots), slot_stride, static_cast<float*>(out), ldo,
-                           (int64_t)P.cols);
+                           (int64_t)P.cols, accumulate ? 1 : 0, (float)alpha);
     return hipGetLastError();
 }
 

@@ -492,10 +492,10 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 // ascending item order (ascending patch index k).  cboxes[ci] is the staging
 // box of the tile's ci-th contributor.  Contributors are taken four at a time:
 // their loads are issued together and then added in ascending order, so the
-// sum order is the same as one at a time.
+// sum order is the same as one at a time.  With accumulate, out += alpha * sum.
 template <class T>
 __host__ __device__ inline void reduce_tile(const Tile& t, int col_in_tile, const Box* cboxes, const T* slots,
-                                            T* out, int64_t pitch) {
+                                            T* out, int64_t pitch, bool accumulate = false, T alpha = T(1)) {
     if (col_in_tile >= t.nc) return;
     const int col = t.c0 + col_in_tile;
     constexpr int U = 4;
@@ -532,7 +532,10 @@ __host__ __device__ inline void reduce_tile(const Tile& t, int col_in_tile, cons
     }
 #pragma unroll
     for (int rr = 0; rr < kReduceRows; ++rr)
-        if (rr < t.nr) out[(int64_t)(t.r0 + rr) * pitch + col] = acc[rr];
+        if (rr < t.nr) {
+            T* o = out + (int64_t)(t.r0 + rr) * pitch + col;
+            *o = accumulate ? *o + alpha * acc[rr] : acc[rr];
+        }
 }
 
 }  // namespace pc

@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <set>
 #include <tuple>
 
@@ -58,42 +59,50 @@ int smallest_7smooth(int64_t need) {
 }
 
 // --------------------------------------------------------- FP64 host FFT
-// y[k] = sum_j x[j * stride] w_n^(j k), w_n = exp(-2 pi i / n); recursive
-// mixed radix over the smallest prime factor, twiddles from a table of the
-// top-level length Wn (n divides Wn).
-void fft_rec(const cd* x, int64_t stride, int n, cd* y, const std::vector<cd>& W, int Wn,
-             std::vector<cd>& scratch) {
-    if (n == 1) {
+// Plan of one length: prime factors and the table w_n^e, e < n.
+Dft64::Dft64(int n_) : n(n_), W((size_t)n_) {
+    for (int e = 0; e < n; ++e) {
+        const double ang = 2.0 * kPi * (double)e / (double)n;
+        W[(size_t)e] = cd(std::cos(ang), -std::sin(ang));
+    }
+    int m = n;
+    for (int f = 2; f * f <= m; ++f)
+        while (m % f == 0) {
+            fac.push_back(f);
+            m /= f;
+        }
+    if (m > 1) fac.push_back(m);
+}
+
+// y[k] = sum_j x[j * stride] w_n^(j k) for a sub-length len = n / (product of
+// the first 'level' factors): decimation in time over fac[level], then for
+// every k < len/p an in-place DFT_p of the p twiddled sub-results.
+void Dft64::rec(const cd* x, int64_t stride, int len, int level, cd* y) const {
+    if (len == 1) {
         y[0] = x[0];
         return;
     }
-    int p = n;
-    for (int f = 2; f * f <= n; ++f)
-        if (n % f == 0) {
-            p = f;
-            break;
+    const int p = fac[(size_t)level], m = len / p;
+    for (int q = 0; q < p; ++q) rec(x + q * stride, stride * p, m, level + 1, y + q * m);
+    const int step = n / len, pstep = n / p;
+    cd t[64];
+    for (int k = 0; k < m; ++k) {
+        for (int q = 0; q < p; ++q) t[q] = y[q * m + k] * W[(size_t)(q * k * step)];
+        for (int sft = 0; sft < p; ++sft) {
+            cd acc = t[0];
+            for (int q = 1; q < p; ++q) acc += t[q] * W[(size_t)(((q * sft) % p) * pstep)];
+            y[k + sft * m] = acc;
         }
-    int m = n / p;
-    for (int q = 0; q < p; ++q) fft_rec(x + q * stride, stride * p, m, y + q * m, W, Wn, scratch);
-    std::vector<cd> t(n);
-    const int step = Wn / n;
-    for (int k = 0; k < m; ++k)
-        for (int q = 0; q < p; ++q) {
-            int K = k + q * m;
-            cd s = 0.0;
-            for (int rr = 0; rr < p; ++rr) s += y[rr * m + k] * W[(int64_t)((rr * (int64_t)K) % n) * step];
-            t[K] = s;
-        }
-    std::copy(t.begin(), t.end(), y);
+    }
 }
 
-std::vector<cd> twiddles(int n) {
-    std::vector<cd> W(n);
-    for (int e = 0; e < n; ++e) {
-        double ang = 2.0 * kPi * (double)e / (double)n;
-        W[e] = cd(std::cos(ang), -std::sin(ang));
-    }
-    return W;
+void Dft64::run(const cd* x, int64_t stride, cd* y) const { rec(x, stride, n, 0, y); }
+
+const Dft64& dft64(int n) {
+    thread_local std::map<int, std::unique_ptr<Dft64>> cache;
+    auto& slot = cache[n];
+    if (!slot) slot.reset(new Dft64(n));
+    return *slot;
 }
 
 namespace {
@@ -117,45 +126,64 @@ void edge_hat(const std::vector<int64_t>& cuts, int64_t pos, int64_t c0, int64_t
     }
 }
 
-// Dirichlet problem for the 5-point graph Laplacian on the interior
-// (p x q) of a box: L U = R with L = T_p (x) I + I (x) T_q, solved exactly in
-// the sine eigenbasis of the tridiagonal T_n (T_n = S diag(lambda) S, S
-// symmetric orthogonal).
-void dst_solve(int p, int q, std::vector<double>& R) {
-    auto basis = [](int n, std::vector<double>& S, std::vector<double>& lam) {
-        S.assign((size_t)n * n, 0.0);
-        lam.assign(n, 0.0);
-        double sc = std::sqrt(2.0 / (n + 1));
+// Sine eigenbasis of the tridiagonal T_n = tridiag(-1, 2, -1):
+// T_n = S diag(lambda) S with S symmetric orthogonal.
+struct SineBasis {
+    int n = 0;
+    std::vector<double> S, lam;
+    explicit SineBasis(int n_) : n(n_), S((size_t)n_ * n_), lam((size_t)n_) {
+        const double sc = std::sqrt(2.0 / (n + 1));
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < n; ++a) S[(size_t)i * n + a] = sc * std::sin(kPi * (i + 1) * (a + 1) / (n + 1));
-        for (int a = 0; a < n; ++a) lam[a] = 2.0 - 2.0 * std::cos(kPi * (a + 1) / (n + 1));
-    };
-    std::vector<double> Sp, lp, Sq, lq;
-    basis(p, Sp, lp);
-    basis(q, Sq, lq);
-    std::vector<double> T((size_t)p * q), U((size_t)p * q);
-    auto left = [&](const std::vector<double>& A, std::vector<double>& B) {   // B = Sp A
-        for (int i = 0; i < p; ++i)
-            for (int j = 0; j < q; ++j) {
-                double s = 0.0;
-                for (int k = 0; k < p; ++k) s += Sp[(size_t)i * p + k] * A[(size_t)k * q + j];
-                B[(size_t)i * q + j] = s;
-            }
-    };
-    auto right = [&](const std::vector<double>& A, std::vector<double>& B) {  // B = A Sq
-        for (int i = 0; i < p; ++i)
-            for (int j = 0; j < q; ++j) {
-                double s = 0.0;
-                for (int k = 0; k < q; ++k) s += A[(size_t)i * q + k] * Sq[(size_t)k * q + j];
-                B[(size_t)i * q + j] = s;
-            }
-    };
-    left(R, T);
-    right(T, U);
-    for (int a = 0; a < p; ++a)
-        for (int b = 0; b < q; ++b) U[(size_t)a * q + b] /= (lp[a] + lq[b]);
-    left(U, T);
-    right(T, R);
+        for (int a = 0; a < n; ++a) lam[(size_t)a] = 2.0 - 2.0 * std::cos(kPi * (a + 1) / (n + 1));
+    }
+};
+
+// Dirichlet problem for the 5-point graph Laplacian on the interior (p x q)
+// of a box, L U = R with L = T_p (x) I + I (x) T_q, solved exactly in the
+// sine eigenbasis: U = Sp [(Sp R Sq) / (lambda_a + mu_b)] Sq.  R holds the
+// boundary values next to the border only: R = e_0 t' + e_{p-1} b' + l e_0'
+// + r e_{q-1}' (t, b: top and bottom rows; l, r: left and right columns), so
+// Sp R Sq is a sum of four outer products.  Result in U (p x q, row-major).
+void dst_solve_border(const SineBasis& P, const SineBasis& Q, const double* t, const double* b, const double* l,
+                      const double* r, std::vector<double>& U) {
+    const int p = P.n, q = Q.n;
+    std::vector<double> St(q, 0.0), Sb(q, 0.0), Sl(p, 0.0), Sr(p, 0.0);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            St[i] += Q.S[(size_t)i * q + j] * t[j];
+            Sb[i] += Q.S[(size_t)i * q + j] * b[j];
+        }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+            Sl[i] += P.S[(size_t)i * p + j] * l[j];
+            Sr[i] += P.S[(size_t)i * p + j] * r[j];
+        }
+    std::vector<double> H((size_t)p * q);
+    for (int a = 0; a < p; ++a) {
+        const double pa0 = P.S[(size_t)a * p], pa1 = P.S[(size_t)a * p + p - 1];
+        for (int c = 0; c < q; ++c) {
+            const double v = pa0 * St[c] + pa1 * Sb[c] + Sl[a] * Q.S[(size_t)c * q] + Sr[a] * Q.S[(size_t)c * q + q - 1];
+            H[(size_t)a * q + c] = v / (P.lam[a] + Q.lam[c]);
+        }
+    }
+    // U = Sp H Sq
+    std::vector<double> T((size_t)p * q, 0.0);
+    for (int i = 0; i < p; ++i)
+        for (int k = 0; k < p; ++k) {
+            const double s = P.S[(size_t)i * p + k];
+            const double* h = &H[(size_t)k * q];
+            double* o = &T[(size_t)i * q];
+            for (int j = 0; j < q; ++j) o[j] += s * h[j];
+        }
+    U.assign((size_t)p * q, 0.0);
+    for (int i = 0; i < p; ++i)
+        for (int k = 0; k < q; ++k) {
+            const double s = T[(size_t)i * q + k];
+            const double* qs = &Q.S[(size_t)k * q];
+            double* o = &U[(size_t)i * q];
+            for (int j = 0; j < q; ++j) o[j] += s * qs[j];
+        }
 }
 
 // Weights of every sample point lying on a 2-D leaf over the leaf box.
@@ -190,6 +218,12 @@ void leaf_weights_2d(const int64_t* lo, const int64_t* hi, const std::vector<int
     for (auto* v : {&top, &bot, &lef, &rig}) std::sort(v->begin(), v->end());
     const int p_in = (int)H0 - 1, q_in = (int)H1 - 1;
     std::vector<double> e(std::max(w0, w1));
+    std::unique_ptr<SineBasis> Bp, Bq;
+    if (p_in > 0 && q_in > 0) {
+        Bp.reset(new SineBasis(p_in));
+        Bq.reset(new SineBasis(q_in));
+    }
+    std::vector<double> t, b, l, r, U;
     for (size_t j = 0; j < pts.size(); ++j) {
         const int64_t* p = P + 2 * pts[j];
         std::vector<double>& V = vals[j];
@@ -203,22 +237,24 @@ void leaf_weights_2d(const int64_t* lo, const int64_t* hi, const std::vector<int
         edge_hat(rig, p[1] == hi[1] ? p[0] : INT64_MIN, lo[0], hi[0], e.data());
         for (int64_t y0 = 0; y0 < w0; ++y0) V[(size_t)(y0 * w1 + H1)] = e[y0];
         if (p_in <= 0 || q_in <= 0) continue;
-        std::vector<double> R((size_t)p_in * q_in, 0.0);
+        // boundary values next to the interior: rows 0 and H0, columns 0 and H1
+        t.assign((size_t)q_in, 0.0);
+        b.assign((size_t)q_in, 0.0);
+        l.assign((size_t)p_in, 0.0);
+        r.assign((size_t)p_in, 0.0);
+        for (int jj = 0; jj < q_in; ++jj) {
+            t[(size_t)jj] = V[(size_t)(0 * w1 + jj + 1)];
+            b[(size_t)jj] = V[(size_t)(H0 * w1 + jj + 1)];
+        }
+        for (int i = 0; i < p_in; ++i) {
+            l[(size_t)i] = V[(size_t)((i + 1) * w1)];
+            r[(size_t)i] = V[(size_t)((i + 1) * w1 + H1)];
+        }
+        dst_solve_border(*Bp, *Bq, t.data(), b.data(), l.data(), r.data(), U);
         for (int i = 0; i < p_in; ++i)
-            for (int jj = 0; jj < q_in; ++jj) {
-                double s = 0.0;
-                if (i == 0) s += V[(size_t)(0 * w1 + jj + 1)];
-                if (i == p_in - 1) s += V[(size_t)(H0 * w1 + jj + 1)];
-                if (jj == 0) s += V[(size_t)((i + 1) * w1)];
-                if (jj == q_in - 1) s += V[(size_t)((i + 1) * w1 + H1)];
-                R[(size_t)i * q_in + jj] = s;
-            }
-        dst_solve(p_in, q_in, R);
-        for (int i = 0; i < p_in; ++i)
-            for (int jj = 0; jj < q_in; ++jj) V[(size_t)((i + 1) * w1 + jj + 1)] = R[(size_t)i * q_in + jj];
+            for (int jj = 0; jj < q_in; ++jj) V[(size_t)((i + 1) * w1 + jj + 1)] = U[(size_t)i * q_in + jj];
     }
 }
-
 
 }  // namespace
 
@@ -417,6 +453,22 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             }
         }
     }
+    // ---------------------------------------------------- term selection
+    p.sel.assign((size_t)r, a.n_sel < 0 ? 1 : 0);
+    if (a.n_sel >= 0) {
+        if (a.n_sel > 0 && !a.sel) {
+            err = "null selection array";
+            return PC_ERR_ARG;
+        }
+        for (int64_t i = 0; i < a.n_sel; ++i) {
+            const int64_t k = a.sel[i];
+            if (k < 0 || k >= r || p.sel[(size_t)k]) {
+                err = "selected point indices must be distinct and in [0, r)";
+                return PC_ERR_ARG;
+            }
+            p.sel[(size_t)k] = 1;
+        }
+    }
     if (d == 3) return build_plan_3d(a, p, err);
 
     // ------------------------------------------------------- 2-D view
@@ -464,12 +516,22 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         nbrs[k].assign(s.begin(), s.end());
     }
     // ----------------------------------------------------------- weights
+    // (only the selected points' tables are stored, only their leaves solved)
     std::vector<int64_t> w_base(r + 1, 0);
     for (int64_t k = 0; k < r; ++k)
-        w_base[k + 1] = w_base[k] + (Uhi[2 * k] - Ulo[2 * k] + 1) * (Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1);
+        w_base[k + 1] = w_base[k] + (p.sel[(size_t)k] ? (Uhi[2 * k] - Ulo[2 * k] + 1) *
+                                                            (Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1)
+                                                      : 0);
     std::vector<double> W((size_t)w_base[r], 0.0);
+    // leaves are independent: weights are solved in parallel, then scattered
+    // into the per-point tables in leaf order
+    std::vector<std::vector<std::vector<double>>> leaf_vals((size_t)L);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < L; ++c) {
-        std::vector<std::vector<double>> vals;
+        bool any = false;
+        for (int64_t k : leaf_pts[c]) any = any || p.sel[(size_t)k];
+        if (!any) continue;
+        std::vector<std::vector<double>>& vals = leaf_vals[(size_t)c];
         const int64_t lo[2] = {LO[2 * c], LO[2 * c + 1]}, hi[2] = {HI[2 * c], HI[2 * c + 1]};
         if (d == 1) {
             // two end points; linear hats
@@ -482,15 +544,22 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         } else {
             leaf_weights_2d(lo, hi, leaf_pts[c], P2.data(), vals);
         }
+    }
+    for (int64_t c = 0; c < L; ++c) {
+        const std::vector<std::vector<double>>& vals = leaf_vals[(size_t)c];
+        if (vals.empty()) continue;
+        const int64_t lo[2] = {LO[2 * c], LO[2 * c + 1]}, hi[2] = {HI[2 * c], HI[2 * c + 1]};
         const int64_t w1 = hi[1] - lo[1] + 1;
         for (size_t j = 0; j < leaf_pts[c].size(); ++j) {
             int64_t k = leaf_pts[c][j];
+            if (!p.sel[(size_t)k]) continue;
             int64_t um1 = Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1;
             for (int64_t y0 = lo[0]; y0 <= hi[0]; ++y0)
                 for (int64_t y1 = lo[1]; y1 <= hi[1]; ++y1)
                     W[(size_t)(w_base[k] + (y0 - Ulo[2 * k]) * um1 + (y1 - Ulo[2 * k + 1]))] =
                         vals[j][(size_t)((y0 - lo[0]) * w1 + (y1 - lo[1]))];
         }
+        std::vector<std::vector<double>>().swap(leaf_vals[(size_t)c]);
     }
     p.wts = std::move(W);
     // ------------------------------------------------ extension + planning
@@ -516,9 +585,11 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     struct PatchOut {
         pc_status st = PC_OK;
         std::string err;
-        std::vector<double> spec;
+        std::vector<double> E;       // phi_k^E on [zlo, zhi] (until its spectrum is formed)
+        int64_t zlo[2] = {0, 0}, zhi[2] = {0, 0};
         std::vector<Item> items;
-        int n0 = 0, M = 0;
+        int n0 = 0, M = 0, a0 = 1, b0 = 1, am = 1, bm = 1;
+        int64_t spec_off = 0;
         double flops = 0.0;
         int64_t kel = 0;
     };
@@ -528,6 +599,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < r; ++k) {
         PatchOut& po = outs[(size_t)k];
+        if (!p.sel[(size_t)k]) continue;
         const int64_t I_lo[2] = {Ulo[2 * k], Ulo[2 * k + 1]}, I_hi[2] = {Uhi[2 * k], Uhi[2 * k + 1]};
         const int64_t m[2] = {I_hi[0] - I_lo[0] + 1, I_hi[1] - I_lo[1] + 1};
         int64_t Rm[2] = {R2[2 * k], R2[2 * k + 1]};
@@ -631,35 +703,15 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         po.n0 = n0;
         po.M = M;
         const int n1 = 2 * M;
-        // spectrum of phi_k^E placed circularly, FP64, half spectrum along axis 1
-        {
-            std::vector<cd> G((size_t)n0 * n1, cd(0.0));
-            for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0)
-                for (int64_t z1 = zlo[1]; z1 <= zhi[1]; ++z1) {
-                    int64_t i0 = ((z0 % n0) + n0) % n0, i1 = ((z1 % n1) + n1) % n1;
-                    G[(size_t)(i0 * n1 + i1)] += E[(size_t)((z0 - zlo[0]) * K[1] + (z1 - zlo[1]))];
-                }
-            std::vector<cd> rowout((size_t)n1), colin((size_t)n0), colout((size_t)n0), scratch;
-            std::vector<cd> W1 = twiddles(n1), W0 = twiddles(n0);
-            std::vector<cd> H((size_t)n0 * (M + 1));
-            for (int i0 = 0; i0 < n0; ++i0) {
-                fft_rec(&G[(size_t)i0 * n1], 1, n1, rowout.data(), W1, n1, scratch);
-                for (int kk = 0; kk <= M; ++kk) H[(size_t)i0 * (M + 1) + kk] = rowout[kk];
-            }
-            const double sc = 1.0 / ((double)n0 * (double)M);
-            std::vector<double> out((size_t)n0 * (M + 1) * 2);
-            for (int kk = 0; kk <= M; ++kk) {
-                for (int i0 = 0; i0 < n0; ++i0) colin[i0] = H[(size_t)i0 * (M + 1) + kk];
-                fft_rec(colin.data(), 1, n0, colout.data(), W0, n0, scratch);
-                int s1 = (kk < M) ? perm_slot(kk, am, bm) : M;
-                for (int k0 = 0; k0 < n0; ++k0) {
-                    int s0 = perm_slot(k0, a0, b0);
-                    out[2 * ((size_t)s0 * (M + 1) + s1)] = colout[k0].real() * sc;
-                    out[2 * ((size_t)s0 * (M + 1) + s1) + 1] = colout[k0].imag() * sc;
-                }
-            }
-            po.spec = std::move(out);
+        po.a0 = a0;
+        po.b0 = b0;
+        po.am = am;
+        po.bm = bm;
+        for (int i = 0; i < 2; ++i) {
+            po.zlo[i] = zlo[i];
+            po.zhi[i] = zhi[i];
         }
+        po.E = std::move(E);
         // pieces: P0 row ranges x P1 column ranges of the patch box
         for (int i0 = 0; i0 < best_P0; ++i0)
             for (int i1 = 0; i1 < best_P1; ++i1) {
@@ -700,20 +752,23 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 po.items.push_back(it);
             }
     }
-    // assembly in patch order: spectra, twiddle tables, staging offsets
+    // assembly in patch order: spectrum offsets, twiddle tables, staging offsets
     int64_t kernel_elems = 0;
     double alg_flops = 0.0;
+    int64_t spec_total = 0;
+
     for (int64_t k = 0; k < r; ++k) {
         PatchOut& po = outs[(size_t)k];
         if (po.st != PC_OK) {
             err = po.err;
             return po.st;
         }
+        if (!p.sel[(size_t)k]) continue;
         kernel_elems += po.kel;
         alg_flops += po.flops;
-        const int64_t spec_off = (int64_t)(p.spec.size() / 2);
-        p.spec.insert(p.spec.end(), po.spec.begin(), po.spec.end());
-        std::vector<double>().swap(po.spec);
+        const int64_t spec_off = spec_total;
+        po.spec_off = spec_off;
+        spec_total += (int64_t)po.n0 * (po.M + 1);
         const int t0 = want_tw(po.n0), tm = want_tw(po.M), t2m = want_tw(2 * po.M);
         int ldr = po.M + 1;
         if (ldr % 2 == 0) ++ldr;
@@ -733,6 +788,48 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     }
     p.kernel_elems = kernel_elems;
     p.alg_flops = alg_flops;
+    // spectra of phi_k^E placed circularly, FP64, half spectrum along axis 1,
+    // written in place (patches in parallel)
+    p.spec.assign((size_t)(2 * spec_total), 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < r; ++k) {
+        PatchOut& po = outs[(size_t)k];
+        if (!p.sel[(size_t)k]) continue;
+        const int n0 = po.n0, M = po.M, n1 = 2 * M;
+        const int64_t* zlo = po.zlo;
+        const int64_t* zhi = po.zhi;
+        const int64_t K1 = zhi[1] - zlo[1] + 1;
+        std::vector<cd> G((size_t)n0 * n1, cd(0.0));
+        for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0)
+            for (int64_t z1 = zlo[1]; z1 <= zhi[1]; ++z1) {
+                int64_t i0 = ((z0 % n0) + n0) % n0, i1 = ((z1 % n1) + n1) % n1;
+                G[(size_t)(i0 * n1 + i1)] += po.E[(size_t)((z0 - zlo[0]) * K1 + (z1 - zlo[1]))];
+            }
+        std::vector<double>().swap(po.E);
+        std::vector<cd> rowout((size_t)n1), colin((size_t)n0), colout((size_t)n0);
+        const Dft64& F1 = dft64(n1);
+        const Dft64& F0 = dft64(n0);
+        std::vector<cd> H((size_t)n0 * (M + 1), cd(0.0));
+        std::vector<char> live((size_t)n0, 0);
+        for (int64_t z0 = zlo[0]; z0 <= zhi[0]; ++z0) live[(size_t)(((z0 % n0) + n0) % n0)] = 1;
+        for (int i0 = 0; i0 < n0; ++i0) {
+            if (!live[(size_t)i0]) continue;      // rows outside the kernel box stay zero
+            F1.run(&G[(size_t)i0 * n1], 1, rowout.data());
+            for (int kk = 0; kk <= M; ++kk) H[(size_t)i0 * (M + 1) + kk] = rowout[kk];
+        }
+        const double sc = 1.0 / ((double)n0 * (double)M);
+        double* out = &p.spec[(size_t)(2 * po.spec_off)];
+        for (int kk = 0; kk <= M; ++kk) {
+            for (int i0 = 0; i0 < n0; ++i0) colin[i0] = H[(size_t)i0 * (M + 1) + kk];
+            F0.run(colin.data(), 1, colout.data());
+            int s1 = (kk < M) ? perm_slot(kk, po.am, po.bm) : M;
+            for (int k0 = 0; k0 < n0; ++k0) {
+                int s0 = perm_slot(k0, po.a0, po.b0);
+                out[2 * ((size_t)s0 * (M + 1) + s1)] = colout[k0].real() * sc;
+                out[2 * ((size_t)s0 * (M + 1) + s1) + 1] = colout[k0].imag() * sc;
+            }
+        }
+    }
     // --------------------------------------------------- reduction tiles
     std::vector<Box> bf(p.items.size()), ba(p.items.size());
     for (size_t i = 0; i < p.items.size(); ++i) {

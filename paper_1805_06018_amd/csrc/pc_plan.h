@@ -26,6 +26,8 @@ struct CreateArgs {
     const int64_t* phi_off;
     int dtype;
     uint32_t flags;
+    int64_t n_sel = -1;              // >= 0: keep only the terms of these points
+    const int64_t* sel = nullptr;
 };
 
 struct Plan {
@@ -37,6 +39,7 @@ struct Plan {
     int dtype = 0;
     uint32_t flags = 0;
     int64_t r = 0, L = 0;
+    std::vector<char> sel;           // [r]: 1 if point k's term is part of the operator
     std::vector<Item> items;         // d = 1, 2
     std::vector<Item3> items3;       // d = 3
     int64_t scratch_per_vec = 0;     // d = 3: complex scratch elements per vector over all items
@@ -71,9 +74,20 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // slot of frequency k in the two-pass order of a length a * b transform
 int perm_slot(int k, int a, int b);
 int smallest_7smooth(int64_t need);
-// y[k] = sum_j x[j stride] w_n^(j k) (FP64, any length; W = twiddles(Wn), n | Wn)
-void fft_rec(const cd* x, int64_t stride, int n, cd* y, const std::vector<cd>& W, int Wn, std::vector<cd>& scratch);
-std::vector<cd> twiddles(int n);
+// FP64 DFT of one length with prime factors <= 64:
+// y[k] = sum_j x[j stride] w_n^(j k), w_n = exp(-2 pi i / n).
+struct Dft64 {
+    int n;
+    std::vector<int> fac;          // prime factors
+    std::vector<cd> W;             // w_n^e, e < n
+    explicit Dft64(int n_);
+    void run(const cd* x, int64_t stride, cd* y) const;
+
+  private:
+    void rec(const cd* x, int64_t stride, int len, int level, cd* y) const;
+};
+// cached plan of length n (per thread)
+const Dft64& dft64(int n);
 // reduction tiles and contributor boxes of both directions from the
 // per-item staging boxes (ascending item order)
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);

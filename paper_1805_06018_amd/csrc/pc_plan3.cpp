@@ -128,6 +128,7 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < r; ++k) {
         Geo3& g = geo[(size_t)k];
+        if (!p.sel[(size_t)k]) continue;
         int64_t K[3], Rm[3], olo[3], ohi[3];
         for (int i = 0; i < 3; ++i) {
             g.I_lo[i] = Ulo[3 * k + i];
@@ -225,6 +226,7 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
             err = g.err;
             return g.st;
         }
+        if (!p.sel[(size_t)k]) continue;
         Item3& it = g.it;
         Item& q = it.p;
         q.tw0 = want_tw(q.n0);
@@ -250,9 +252,10 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
     // ------------------------------------------- FP64 spectra, in place
     p.spec.assign((size_t)(2 * spec_total), 0.0);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t k = 0; k < r; ++k) {
+    for (int64_t ii = 0; ii < (int64_t)p.items3.size(); ++ii) {
+        const Item3& it = p.items3[(size_t)ii];
+        const int64_t k = it.p.patch;
         const Geo3& g = geo[(size_t)k];
-        const Item3& it = p.items3[(size_t)k];
         const int nz = it.nz, n1 = it.p.n0, M = it.p.m, n2 = 2 * M;
         // extended kernel phi_k^E (Sec. 2.5) on [zlo, zhi], placed circularly
         auto defined = [&](int64_t j, const int64_t* z) {
@@ -294,19 +297,21 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         // axis 2 (real length 2M, keep 0..M), axis 1, axis 0
         const int NC = M + 1;
         std::vector<cd> H((size_t)nz * n1 * NC, cd(0.0)), buf_in(std::max({n1, nz, n2})),
-            buf_out(std::max({n1, nz, n2})), scratch;
-        std::vector<cd> W2 = twiddles(n2), W1 = twiddles(n1), W0 = twiddles(nz);
+            buf_out(std::max({n1, nz, n2}));
+        const Dft64& F2 = dft64(n2);
+        const Dft64& F1 = dft64(n1);
+        const Dft64& F0 = dft64(nz);
         for (int i0 = 0; i0 < nz; ++i0)
             for (int i1 = 0; i1 < n1; ++i1) {
                 if (!live[(size_t)(i0 * n1 + i1)]) continue;
-                fft_rec(&G[(size_t)((i0 * n1 + i1) * n2)], 1, n2, buf_out.data(), W2, n2, scratch);
+                F2.run(&G[(size_t)((i0 * n1 + i1) * n2)], 1, buf_out.data());
                 for (int kk = 0; kk < NC; ++kk) H[(size_t)((i0 * n1 + i1) * NC + kk)] = buf_out[kk];
             }
         std::vector<cd>().swap(G);
         for (int i0 = 0; i0 < nz; ++i0)
             for (int kk = 0; kk < NC; ++kk) {
                 for (int i1 = 0; i1 < n1; ++i1) buf_in[i1] = H[(size_t)((i0 * n1 + i1) * NC + kk)];
-                fft_rec(buf_in.data(), 1, n1, buf_out.data(), W1, n1, scratch);
+                F1.run(buf_in.data(), 1, buf_out.data());
                 for (int k1 = 0; k1 < n1; ++k1) H[(size_t)((i0 * n1 + k1) * NC + kk)] = buf_out[k1];
             }
         const double sc = 1.0 / ((double)nz * (double)n1 * (double)M);
@@ -314,7 +319,7 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         for (int k1 = 0; k1 < n1; ++k1)
             for (int kk = 0; kk < NC; ++kk) {
                 for (int i0 = 0; i0 < nz; ++i0) buf_in[i0] = H[(size_t)((i0 * n1 + k1) * NC + kk)];
-                fft_rec(buf_in.data(), 1, nz, buf_out.data(), W0, nz, scratch);
+                F0.run(buf_in.data(), 1, buf_out.data());
                 const int s1 = perm_slot(k1, it.p.a0, it.p.b0);
                 const int s2 = (kk < M) ? perm_slot(kk, it.p.am, it.p.bm) : M;
                 for (int kz = 0; kz < nz; ++kz) {

@@ -79,3 +79,93 @@ def test_refinement_loop_converges_and_matches_oracle(mods):
     eta_o, eabs_o, erel_o, _ = estimate(ora, Zh, Y.cpu().numpy().astype(np.float64))
     assert abs(erel - erel_o) <= 1e-3 * erel_o, (erel, erel_o)
     assert np.abs(eta - eta_o).max() <= 1e-3 * eta_o.max()
+
+
+def test_term_subset_operators_and_axpy(mods):
+    """pc_create_patches against the oracle's sum over the same terms;
+    axpy against apply + add (bitwise for alpha = +-1 and 0.5); a complementary
+    pair of subsets adds up to the full operator."""
+    _lib = mods[0]
+    from tests.libhelpers import small_cases
+    for name, w in small_cases()[:2]:
+        ora = OracleOperator.from_workload(w)
+        rng = np.random.default_rng(3)
+        S = rng.permutation(w.r)[: w.r // 2]
+        Sc = np.setdiff1d(np.arange(w.r), S)
+        U = rng.standard_normal((3, w.N))
+        Ud = torch.from_numpy(U).cuda()
+        full = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F64)
+        part = _lib.PcOperator(w.d, w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius, w.phi, w.phi_off,
+                               dtype=_lib.PC_F64, patches=S)
+        rest = _lib.PcOperator(w.d, w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius, w.phi, w.phi_off,
+                               dtype=_lib.PC_F64, patches=Sc)
+        for adj in (False, True):
+            fn = (lambda op: op.apply_adjoint_batch) if adj else (lambda op: op.apply_batch)
+            ax = (lambda op: op.apply_adjoint_batch_axpy) if adj else (lambda op: op.apply_batch_axpy)
+            got = torch.zeros_like(Ud)
+            fn(part)(Ud, got)
+            torch.cuda.synchronize()
+            ref = ora.apply_batch(U, adjoint=adj, patches=S)
+            assert np.abs(got.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max(), (name, adj)
+            base = torch.from_numpy(rng.standard_normal((3, w.N))).cuda()
+            for alpha in (1.0, -1.0, 0.5):
+                acc = base.clone()
+                ax(part)(Ud, alpha, acc)
+                torch.cuda.synchronize()
+                assert torch.equal(acc, base + alpha * got), (name, adj, alpha)
+            tot = torch.zeros_like(Ud)
+            ax(part)(Ud, 1.0, tot)
+            ax(rest)(Ud, 1.0, tot)
+            whole = torch.zeros_like(Ud)
+            fn(full)(Ud, whole)
+            torch.cuda.synchronize()
+            assert (tot - whole).abs().max().item() <= 1e-12 * whole.abs().max().item()
+
+
+def test_incremental_refinement_tracks_full_recompute(mods):
+    """Sec. 2.8: Y~ updated with the changed terms only stays equal (to FP32
+    rounding) to a full recomputation on the final tiling, and so does the
+    estimate; far fewer terms are convolved than by rebuilding every round.
+    Then three rounds of one leaf each (Algorithm 1)."""
+    _lib, refine, GpuBlurAdjoint = mods
+    from workloads import cosine_field, uniform_nodes, tensor_leaves
+    n = 256
+    s, _ = cosine_field((n, n), 1.0, 4.0, 2, 3, seed=3)
+    nodes = uniform_nodes(n, 4)
+    lo0, hi0 = tensor_leaves([nodes, nodes])
+    w = workload_from(np.stack([s, s]), lo0, hi0)
+    Z = torch.from_numpy(w.rademacher(8, 7).astype(np.float32)).cuda()
+    Y = GpuBlurAdjoint(w.op)(Z)
+    torch.cuda.synchronize()
+    yts = []
+    lo, hi, rounds = refine.refine(w.shape, w.leaf_lo, w.leaf_hi, w.op.impulse_responses, w.op.patch, Z, Y,
+                                   tol=1e-9, max_points=500, frac=0.15, incremental=True, yt_out=yts)
+    print("points", [r["points"] for r in rounds], "terms", [r["terms_convolved"] for r in rounds], flush=True)
+    assert len(rounds) >= 4
+    pts = corner_points(lo, hi)
+    radius, phi, off = w.op.impulse_responses(pts)
+    op = _lib.PcOperator(2, w.shape, lo, hi, pts, radius, phi, off, dtype=_lib.PC_F32)
+    full = torch.zeros_like(Y)
+    op.apply_adjoint_batch(Z, full)
+    torch.cuda.synchronize()
+    drift = ((yts[0] - full).double().norm() / full.double().norm()).item()
+    assert drift <= 2e-6, drift
+    eta_f, _, erel_f = op.estimate_sums(full, Y)
+    eta_e, _, erel_e = op.error_estimate(Z, Y)
+    assert np.array_equal(eta_f, eta_e) and erel_f == erel_e     # same Y~ bits, same sums
+    assert abs(rounds[-1]["eta_rel"] - erel_f) <= 1e-4 * erel_f
+    assert sum(r["terms_convolved"] for r in rounds) <= sum(r["points"] for r in rounds)
+    # Algorithm 1: one leaf per round; each round convolves a few terms only
+    yts1 = []
+    lo1, hi1, r1 = refine.refine(w.shape, lo, hi, w.op.impulse_responses, w.op.patch, Z, Y, tol=1e-9,
+                                 max_points=10**6, frac=0.0, max_rounds=6, incremental=True, yt_out=yts1)
+    print("one-leaf terms", [r["terms_convolved"] for r in r1], flush=True)
+    assert [r["leaves"] for r in r1] == [len(lo) + i for i in range(6)]
+    assert all(r["terms_convolved"] <= 40 for r in r1[1:])
+    pts1 = corner_points(lo1, hi1)
+    radius1, phi1, off1 = w.op.impulse_responses(pts1)
+    op1 = _lib.PcOperator(2, w.shape, lo1, hi1, pts1, radius1, phi1, off1, dtype=_lib.PC_F32)
+    full1 = torch.zeros_like(Y)
+    op1.apply_adjoint_batch(Z, full1)
+    torch.cuda.synchronize()
+    assert ((yts1[0] - full1).double().norm() / full1.double().norm()).item() <= 2e-6

@@ -86,20 +86,28 @@ def _emu_lib(path=os.path.join(PKG, "libpc_emu.so")):
     P = ctypes.c_void_p
     lib.pc_emu_create.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P, P, P,
                                   ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(P)]
+    lib.pc_emu_create_patches.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P, P, P,
+                                          ctypes.c_int, ctypes.c_uint32, ctypes.c_int64, P, ctypes.POINTER(P)]
     lib.pc_emu_apply.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64]
     lib.pc_emu_destroy.argtypes = [P]
     lib.pc_emu_last_error.restype = ctypes.c_char_p
     return lib
 
 
-def emu_apply(lib, w, U, dtype, flags=0, adj=False):
+def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None):
     k = [np.ascontiguousarray(v, dtype=np.int64) for v in (w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius)]
     phi = np.ascontiguousarray(w.phi, dtype=np.float64)
     off = np.ascontiguousarray(w.phi_off, dtype=np.int64)
     h = ctypes.c_void_p()
-    rc = lib.pc_emu_create(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
-                           len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data, off.ctypes.data,
-                           dtype, flags, ctypes.byref(h))
+    if patches is None:
+        rc = lib.pc_emu_create(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
+                               len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data, off.ctypes.data,
+                               dtype, flags, ctypes.byref(h))
+    else:
+        sel = np.ascontiguousarray(patches, dtype=np.int64)
+        rc = lib.pc_emu_create_patches(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
+                                       len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data,
+                                       off.ctypes.data, dtype, flags, sel.size, sel.ctypes.data, ctypes.byref(h))
     assert rc == 0, lib.pc_emu_last_error()
     dt = np.float64 if dtype == 1 else np.float32
     U = np.ascontiguousarray(U, dtype=dt)
@@ -124,6 +132,35 @@ def test_emulated_kernels_match_oracle(idx):
                 ref = op.apply_batch(Ur, adjoint=adj)
                 e = relerr(got, ref)
                 assert e.max() <= TOL[dtype], (name, flags, dtype, adj, e)
+
+
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24"])
+def test_emulated_term_subsets_match_oracle(name):
+    """Operators restricted to a subset of the terms (pc_create_patches) against
+    the oracle's sum over the same terms; the empty subset gives zero."""
+    w = dict(small_cases() + small_cases_3d())[name]
+    lib = _emu_lib()
+    rng = np.random.default_rng(7)
+    U = rng.standard_normal((2, w.N))
+    ora = OracleOperator.from_workload(w)
+    for sel in (rng.permutation(w.r)[: max(1, w.r // 3)], np.array([w.r - 1]), np.zeros(0, dtype=np.int64)):
+        for adj in (False, True):
+            got = emu_apply(lib, w, U, 1, 0, adj, patches=sel)
+            ref = ora.apply_batch(U, adjoint=adj, patches=sel)
+            if sel.size == 0:
+                assert np.all(got == 0.0)
+            else:
+                assert relerr(got, ref).max() <= TOL[1], (name, sel.size, adj)
+
+
+def test_create_patches_rejects_bad_selection():
+    from paper_1805_06018_amd._lib import raw_create, PC_ERR_ARG
+    w = make_config(0)
+    for bad in ([0, 0], [w.r], [-1]):
+        st, msg = raw_create(**_args(w), patches=bad)
+        assert st == PC_ERR_ARG and "distinct" in msg, (bad, msg)
+    st, msg = raw_create(**_args(w), n_sel=-1)
+    assert st == PC_ERR_ARG, msg
 
 
 def test_emulated_kernels_under_address_sanitizer():

@@ -421,3 +421,21 @@ def test_sampled_adjoint_matches_full_adjoint():
     full = op.apply_adjoint(v).reshape(op.shape)
     xs = np.array([[0, 0], [12, 12], [3, 7], [12, 0], [6, 6]])
     assert np.abs(op.apply_adjoint_at(v, xs) - full[xs[:, 0], xs[:, 1]]).max() < 1e-13
+
+
+def test_term_subsets_partition_the_sum():
+    """Sums over complementary subsets of the terms add up to the full apply
+    (each term counted once), forward and adjoint (Sec. 2.8 recomputes only a
+    subset of the terms after a refinement)."""
+    w = make_config(0)
+    op = OracleOperator.from_workload(w)
+    rng = np.random.default_rng(12)
+    S = rng.permutation(w.r)[:11]
+    Sc = np.setdiff1d(np.arange(w.r), S)
+    u = rng.standard_normal(w.N)
+    for adj in (False, True):
+        fn = op.apply_adjoint if adj else op.apply
+        full = fn(u)
+        part = fn(u, patches=S) + fn(u, patches=Sc)
+        assert np.abs(part - full).max() <= 1e-13 * np.abs(full).max()
+        assert np.all(fn(u, patches=[]) == 0.0)
