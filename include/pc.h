@@ -176,6 +176,19 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
                             hipStream_t s);
 
 /* Plan statistics (for measurement and admission). */
+/* pc_entries -- matrix entries out[i] = A~[ys[i], xs[i]] for i < n (Sec. 3.1,
+ * eq. (3.1)): sum over the points k of a leaf containing x of
+ * w_k[x] phi_k^E[y - x], accumulated in FP64 in ascending k and rounded to
+ * the operator's dtype (weights and kernels are held in that dtype).
+ * ys, xs: device int64 [n][d] Omega coordinates; out: device [n] of the
+ * operator's dtype.  A pair with y or x outside Omega gives NaN.  For an
+ * operator from pc_create_patches only the kept terms are summed.  The
+ * first call uploads the entry tables (a leaf index per grid point and the
+ * extended kernels, about N * 4 bytes plus the kernels in dtype), kept until
+ * pc_destroy. */
+pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs,
+                     void* out, hipStream_t s);
+
 /* pc_estimate_sums -- the estimator of Sec. 2.6 (eq. (2.11)) from a Y~ the
  * caller already holds (e.g. updated incrementally with the axpy calls):
  * eta_leaf[c] = sqrt(sum_{x in C} sum_i (Y~ - Y)^2 / q) over the operator's

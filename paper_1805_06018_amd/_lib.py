@@ -56,6 +56,8 @@ for _name in ("pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain"
 for _name in ("pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy"):
     getattr(_lib, _name).argtypes = [_P, _I64, _P, _I64, ctypes.c_double, _P, _I64, _P]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.pc_entries.argtypes = [_P, _I64, _P, _P, _P, _P]
+_lib.pc_entries.restype = ctypes.c_int
 _lib.pc_estimate_sums.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P]
 _lib.pc_estimate_sums.restype = ctypes.c_int
 _lib.pc_error_estimate.argtypes = [_P, _I64, _P, _I64, _P, _I64, MATVEC_FN, _P, _P, _P, _P, _P]
@@ -79,7 +81,8 @@ _lib.pc_last_error.argtypes = []
 _lib.pc_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
-            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_estimate_sums",
+            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_entries",
+            "pc_estimate_sums",
             "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
 
@@ -194,6 +197,20 @@ class PcOperator:
     def apply_adjoint_batch_axpy(self, V, alpha, OUT, stream=None):
         """OUT += alpha * A~* V."""
         return self._axpy(_lib.pc_apply_adjoint_batch_axpy, V, alpha, OUT, stream)
+
+    def entries(self, ys, xs, out=None, stream=None):
+        """Matrix entries A~[ys[i], xs[i]] (pc_entries); ys, xs: (n, d) int64
+        device tensors.  Returns a device tensor of the operator's dtype."""
+        if ys.dtype != torch.int64 or xs.dtype != torch.int64 or ys.shape != xs.shape:
+            raise TypeError("ys and xs must be int64 tensors of the same shape (n, d)")
+        ys = ys.reshape(-1, self.d).contiguous()
+        xs = xs.reshape(-1, self.d).contiguous()
+        n = ys.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=self.torch_dtype, device=ys.device)
+        _check(_lib.pc_entries(self._h, n, _dev(ys, torch.int64, "ys"), _dev(xs, torch.int64, "xs"),
+                               _dev(out, self.torch_dtype, "out"), _stream(stream)))
+        return out
 
     def estimate_sums(self, Yt, Y, stream=None):
         """Estimator of Sec. 2.6 from a given Y~ (pc_estimate_sums):

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "pc_entries.h"
 #include "pc_phases3.h"
 #include "pc_plan.h"
 
@@ -203,6 +204,27 @@ int pc_emu_stats(pc_emu* e, int64_t* out8) {
     out8[5] = (int64_t)P.tiles_fwd.size();
     out8[6] = (int64_t)P.contrib_fwd.size();
     out8[7] = P.kernel_elems;
+    return 0;
+}
+
+// Matrix entries on the host with the same entry function as the kernel
+// (FP64 tables): out[i] = A~[ys[i], xs[i]], host int64 [n][d] coordinates.
+int pc_emu_entries(pc_emu* e, int64_t n, const int64_t* ys, const int64_t* xs, double* out) {
+    const pc::Plan& P = e->plan;
+    std::vector<int32_t> leaf_of((size_t)P.N, -1);
+    for (int64_t c = 0; c < P.L; ++c) {
+        const int32_t* b = &P.leaf_box[(size_t)c * 6];
+        for (int32_t z = 0; z < b[3]; ++z)
+            for (int32_t y = 0; y < b[4]; ++y)
+                for (int32_t x = 0; x < b[5]; ++x) {
+                    int32_t& v = leaf_of[(size_t)(((int64_t)(b[0] + z) * P.prow + b[1] + y) * P.cols + b[2] + x)];
+                    if (v < 0) v = (int32_t)c;
+                }
+    }
+    pc::EntryTables E{P.d, P.planes, P.prow, P.cols, leaf_of.data(), P.leaf_pts_off.data(), P.leaf_pts.data(),
+                      P.pt_wbase.data(), P.pt_ubox.data(), P.pt_eoff.data(), P.pt_ebox.data()};
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = pc::entry_value<double>(E, P.wts.data(), P.phiE.data(), ys + i * P.d, xs + i * P.d);
     return 0;
 }
 

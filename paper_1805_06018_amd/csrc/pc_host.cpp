@@ -60,6 +60,11 @@ struct pc_op {
     double* est = nullptr;    // estimator sums
     size_t est_bytes = 0;
     int32_t* leaf_box = nullptr;   // [L][6] leaf boxes, device
+    void* d_wts = nullptr;         // weight tables (dtype), device
+    // matrix entries: tables uploaded on the first pc_entries call
+    bool ent_ready = false;
+    pc::EntryTables ent{};
+    void* ent_phiE = nullptr;
     // profiling: event pairs of launches not yet read
     bool profiling = false;
     struct Timed {
@@ -417,6 +422,7 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     D.max_lds_axis = P.max_lds_axis;
     D.dtype = (int)dtype;
     op->leaf_box = static_cast<int32_t*>(d_leaf);
+    op->d_wts = d_wts;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         delete op;
@@ -425,6 +431,44 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     // spectra are only needed on the device from now on
     std::vector<double>().swap(P.spec);
     *out = op;
+    return PC_OK;
+}
+
+// Uploads the matrix-entry tables (once per operator).
+pc_status ensure_entries(pc_op* op) {
+    if (op->ent_ready) return PC_OK;
+    const pc::Plan& P = op->plan;
+    std::vector<int32_t> leaf_of((size_t)P.N, -1);
+    for (int64_t c = 0; c < P.L; ++c) {
+        const int32_t* b = &P.leaf_box[(size_t)c * 6];
+        for (int32_t z = 0; z < b[3]; ++z)
+            for (int32_t y = 0; y < b[4]; ++y) {
+                int32_t* row = &leaf_of[(size_t)(((int64_t)(b[0] + z) * P.prow + b[1] + y) * P.cols + b[2])];
+                for (int32_t x = 0; x < b[5]; ++x)
+                    if (row[x] < 0) row[x] = (int32_t)c;
+            }
+    }
+    void *d_leaf, *d_off, *d_lp, *d_wb, *d_ub, *d_eo, *d_eb, *d_phi;
+    pc_status st;
+    if ((st = upload(op, leaf_of, &d_leaf)) != PC_OK || (st = upload(op, P.leaf_pts_off, &d_off)) != PC_OK ||
+        (st = upload(op, P.leaf_pts, &d_lp)) != PC_OK || (st = upload(op, P.pt_wbase, &d_wb)) != PC_OK ||
+        (st = upload(op, P.pt_ubox, &d_ub)) != PC_OK || (st = upload(op, P.pt_eoff, &d_eo)) != PC_OK ||
+        (st = upload(op, P.pt_ebox, &d_eb)) != PC_OK || (st = upload_real(op, P.phiE, &d_phi)) != PC_OK)
+        return st;
+    pc::EntryTables& E = op->ent;
+    E.d = P.d;
+    E.planes = P.planes;
+    E.prow = P.prow;
+    E.cols = P.cols;
+    E.leaf_of = static_cast<const int32_t*>(d_leaf);
+    E.lp_off = static_cast<const int32_t*>(d_off);
+    E.lp = static_cast<const int32_t*>(d_lp);
+    E.wbase = static_cast<const int64_t*>(d_wb);
+    E.ubox = static_cast<const int32_t*>(d_ub);
+    E.eoff = static_cast<const int64_t*>(d_eo);
+    E.ebox = static_cast<const int32_t*>(d_eb);
+    op->ent_phiE = d_phi;
+    op->ent_ready = true;
     return PC_OK;
 }
 
@@ -509,6 +553,18 @@ pc_status pc_apply_batch_axpy(pc_op* op, int64_t B, const void* U, int64_t ldu, 
 pc_status pc_apply_adjoint_batch_axpy(pc_op* op, int64_t B, const void* V, int64_t ldv, double alpha, void* OUT,
                                       int64_t ldo, hipStream_t s) {
     return run_batch(op, true, false, B, V, ldv, OUT, ldo, s, true, alpha);
+}
+
+pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs, void* out, hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    if (n < 0) return fail(PC_ERR_ARG, "negative entry count");
+    if (n == 0) return PC_OK;
+    if (!ys || !xs || !out) return fail(PC_ERR_ARG, "null coordinate or output pointer");
+    if ((st = ensure_entries(op)) != PC_OK) return st;
+    hipError_t e = pc::launch_entries(op->ent, op->plan.dtype, op->d_wts, op->ent_phiE, n, ys, xs, out, s);
+    if (e != hipSuccess) return hip_fail(e, "entries launch");
+    return PC_OK;
 }
 
 pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy,

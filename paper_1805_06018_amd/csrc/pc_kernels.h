@@ -2,6 +2,7 @@
 #pragma once
 #include <stdint.h>
 #include <hip/hip_runtime.h>
+#include "pc_entries.h"
 #include "pc_internal.h"
 
 namespace pc {
@@ -64,6 +65,10 @@ hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q,
                       const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
                       int planes, int prow, int cols, double* leaf_sq, double* partials, int n_part,
                       hipStream_t s);
+
+// Matrix entries out[i] = A~[ys[i], xs[i]] (device int64 [n][d] coordinates).
+hipError_t launch_entries(const EntryTables& E, int dtype, const void* wts, const void* phiE, int64_t n,
+                          const int64_t* ys, const int64_t* xs, void* out, hipStream_t s);
 
 hipError_t set_kernel_attributes();
 

@@ -1,5 +1,6 @@
 // HIP kernels of the product-convolution apply for gfx950.
 #include "pc_kernels.h"
+#include "pc_entries.h"
 #include "pc_phases3.h"
 
 namespace pc {
@@ -220,6 +221,31 @@ __global__ __launch_bounds__(kReduceCols) void reduce_kernel(const Tile* tiles, 
     const int rhs = blockIdx.y;
     reduce_tile<T>(t, threadIdx.x, cboxes, slots + (int64_t)rhs * slot_stride, out + (int64_t)rhs * ldo, pitch,
                    accumulate != 0, alpha);
+}
+
+// ------------------------------------------------------------ matrix entries
+template <class T>
+__global__ __launch_bounds__(256) void entries_kernel(EntryTables E, const T* wts, const T* phiE, int64_t n,
+                                                      const int64_t* ys, const int64_t* xs, T* out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (T)entry_value<T>(E, wts, phiE, ys + i * E.d, xs + i * E.d);
+}
+
+hipError_t launch_entries(const EntryTables& E, int dtype, const void* wts, const void* phiE, int64_t n,
+                          const int64_t* ys, const int64_t* xs, void* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (dtype == 1)
+        hipLaunchKernelGGL(entries_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, E,
+                           static_cast<const double*>(wts), static_cast<const double*>(phiE), n, ys, xs,
+                           static_cast<double*>(out));
+    else
+        hipLaunchKernelGGL(entries_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, E,
+                           static_cast<const float*>(wts), static_cast<const float*>(phiE), n, ys, xs,
+                           static_cast<float*>(out));
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- estimator

@@ -515,6 +515,11 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         }
         nbrs[k].assign(s.begin(), s.end());
     }
+    p.leaf_pts_off.assign((size_t)L + 1, 0);
+    for (int64_t c = 0; c < L; ++c) {
+        p.leaf_pts_off[(size_t)c + 1] = p.leaf_pts_off[(size_t)c] + (int32_t)leaf_pts[c].size();
+        for (int64_t k : leaf_pts[c]) p.leaf_pts.push_back((int32_t)k);
+    }
     // ----------------------------------------------------------- weights
     // (only the selected points' tables are stored, only their leaves solved)
     std::vector<int64_t> w_base(r + 1, 0);
@@ -522,6 +527,18 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         w_base[k + 1] = w_base[k] + (p.sel[(size_t)k] ? (Uhi[2 * k] - Ulo[2 * k] + 1) *
                                                             (Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1)
                                                       : 0);
+    p.pt_wbase.assign((size_t)r, -1);
+    p.pt_ubox.assign((size_t)r * 6, 0);
+    for (int64_t k = 0; k < r; ++k) {
+        if (p.sel[(size_t)k]) p.pt_wbase[(size_t)k] = w_base[k];
+        int32_t* u = &p.pt_ubox[(size_t)k * 6];
+        u[0] = 0;
+        u[1] = (int32_t)Ulo[2 * k];
+        u[2] = (int32_t)Ulo[2 * k + 1];
+        u[3] = 1;
+        u[4] = (int32_t)(Uhi[2 * k] - Ulo[2 * k] + 1);
+        u[5] = (int32_t)(Uhi[2 * k + 1] - Ulo[2 * k + 1] + 1);
+    }
     std::vector<double> W((size_t)w_base[r], 0.0);
     // leaves are independent: weights are solved in parallel, then scattered
     // into the per-point tables in leaf order
@@ -788,6 +805,24 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     }
     p.kernel_elems = kernel_elems;
     p.alg_flops = alg_flops;
+    // extended kernels kept for matrix entries
+    p.pt_eoff.assign((size_t)r, -1);
+    p.pt_ebox.assign((size_t)r * 6, 0);
+    int64_t e_total = 0;
+    for (int64_t k = 0; k < r; ++k) {
+        if (!p.sel[(size_t)k]) continue;
+        const PatchOut& po = outs[(size_t)k];
+        int32_t* e = &p.pt_ebox[(size_t)k * 6];
+        e[0] = 0;
+        e[1] = (int32_t)po.zlo[0];
+        e[2] = (int32_t)po.zlo[1];
+        e[3] = 1;
+        e[4] = (int32_t)(po.zhi[0] - po.zlo[0] + 1);
+        e[5] = (int32_t)(po.zhi[1] - po.zlo[1] + 1);
+        p.pt_eoff[(size_t)k] = e_total;
+        e_total += (int64_t)e[4] * e[5];
+    }
+    p.phiE.assign((size_t)e_total, 0.0);
     // spectra of phi_k^E placed circularly, FP64, half spectrum along axis 1,
     // written in place (patches in parallel)
     p.spec.assign((size_t)(2 * spec_total), 0.0);
@@ -805,6 +840,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 int64_t i0 = ((z0 % n0) + n0) % n0, i1 = ((z1 % n1) + n1) % n1;
                 G[(size_t)(i0 * n1 + i1)] += po.E[(size_t)((z0 - zlo[0]) * K1 + (z1 - zlo[1]))];
             }
+        std::copy(po.E.begin(), po.E.end(), p.phiE.begin() + p.pt_eoff[(size_t)k]);
         std::vector<double>().swap(po.E);
         std::vector<cd> rowout((size_t)n1), colin((size_t)n0), colout((size_t)n0);
         const Dft64& F1 = dft64(n1);

@@ -52,6 +52,13 @@ struct Plan {
     std::vector<Box> boxes_fwd, boxes_adj;     // staging box of every item
     std::vector<Box> cboxes_fwd, cboxes_adj;   // staging box of every tile contributor
     std::vector<int32_t> leaf_box;   // [L][6]: plane, row, col origin and extents (planes x prow x cols view)
+    // matrix entries (Sec. 3.1), in the planes x prow x cols view
+    std::vector<int32_t> leaf_pts_off, leaf_pts;   // CSR: points on each closed leaf, ascending
+    std::vector<int64_t> pt_wbase;   // [r] weight table offset of point k, -1 if its term is not kept
+    std::vector<int32_t> pt_ubox;    // [r][6] bbox(U_k): origin, extents
+    std::vector<int64_t> pt_eoff;    // [r] offset of phi_k^E in phiE, -1 if not kept
+    std::vector<int32_t> pt_ebox;    // [r][6] box of phi_k^E: offset origin zlo, extents
+    std::vector<double> phiE;        // extended kernels phi_k^E, FP64
     int64_t slot_fwd = 0, slot_adj = 0;   // staging elements per vector
     int max_lds = 0;
     int conv_threads = 1024;         // workgroup size of the 1-D/2-D convolution kernel

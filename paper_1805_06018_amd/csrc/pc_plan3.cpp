@@ -91,12 +91,26 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         }
         nbrs[k].assign(s.begin(), s.end());
     }
+    p.leaf_pts_off.assign((size_t)L + 1, 0);
+    for (int64_t c = 0; c < L; ++c) {
+        p.leaf_pts_off[(size_t)c + 1] = p.leaf_pts_off[(size_t)c] + (int32_t)leaf_pts[c].size();
+        for (int64_t k : leaf_pts[c]) p.leaf_pts.push_back((int32_t)k);
+    }
     // ----------------------------------------- weights: trilinear hats
     std::vector<int64_t> w_base(r + 1, 0);
     for (int64_t k = 0; k < r; ++k) {
         int64_t v = 1;
         for (int i = 0; i < 3; ++i) v *= Uhi[3 * k + i] - Ulo[3 * k + i] + 1;
         w_base[k + 1] = w_base[k] + v;
+    }
+    p.pt_wbase.assign((size_t)r, -1);
+    p.pt_ubox.assign((size_t)r * 6, 0);
+    for (int64_t k = 0; k < r; ++k) {
+        if (p.sel[(size_t)k]) p.pt_wbase[(size_t)k] = w_base[k];
+        for (int i = 0; i < 3; ++i) {
+            p.pt_ubox[(size_t)k * 6 + i] = (int32_t)Ulo[3 * k + i];
+            p.pt_ubox[(size_t)k * 6 + 3 + i] = (int32_t)(Uhi[3 * k + i] - Ulo[3 * k + i] + 1);
+        }
     }
     std::vector<double> W((size_t)w_base[r], 0.0);
     for (int64_t c = 0; c < L; ++c) {
@@ -249,6 +263,23 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         p.max_lds_axis = std::max(p.max_lds_axis, g.lds_axis);
         p.items3.push_back(it);
     }
+    // extended kernels kept for matrix entries
+    p.pt_eoff.assign((size_t)r, -1);
+    p.pt_ebox.assign((size_t)r * 6, 0);
+    int64_t e_total = 0;
+    for (const Item3& it : p.items3) {
+        const int64_t k = it.p.patch;
+        const Geo3& g = geo[(size_t)k];
+        int64_t vol = 1;
+        for (int i = 0; i < 3; ++i) {
+            p.pt_ebox[(size_t)k * 6 + i] = (int32_t)g.zlo[i];
+            p.pt_ebox[(size_t)k * 6 + 3 + i] = (int32_t)(g.zhi[i] - g.zlo[i] + 1);
+            vol *= g.zhi[i] - g.zlo[i] + 1;
+        }
+        p.pt_eoff[(size_t)k] = e_total;
+        e_total += vol;
+    }
+    p.phiE.assign((size_t)e_total, 0.0);
     // ------------------------------------------- FP64 spectra, in place
     p.spec.assign((size_t)(2 * spec_total), 0.0);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -292,6 +323,10 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
                     const int64_t i0 = ((z[0] % nz) + nz) % nz, i1 = ((z[1] % n1) + n1) % n1,
                                   i2 = ((z[2] % n2) + n2) % n2;
                     G[(size_t)((i0 * n1 + i1) * n2 + i2)] += v;
+                    p.phiE[(size_t)(p.pt_eoff[(size_t)k] +
+                                    ((z[0] - g.zlo[0]) * (g.zhi[1] - g.zlo[1] + 1) + (z[1] - g.zlo[1])) *
+                                        (g.zhi[2] - g.zlo[2] + 1) +
+                                    (z[2] - g.zlo[2]))] = v;
                     live[(size_t)(i0 * n1 + i1)] = 1;
                 }
         // axis 2 (real length 2M, keep 0..M), axis 1, axis 0

@@ -337,3 +337,41 @@ def test_full_size_blur3d_128(lib, dtype):
             ra = ora.apply_adjoint_at(u, ys)
             sa = np.abs(adj[j]).max()
             assert np.abs(adj[j, flat] - ra).max() <= tol * sa, (j, np.abs(adj[j, flat] - ra).max() / sa)
+
+
+# ------------------------------------------------------------ matrix entries
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24"])
+def test_entries_match_oracle(lib, name):
+    """pc_entries (Sec. 3.1) against the oracle's entry formula, FP64 and
+    FP32; out-of-range pairs give NaN; entries agree with applies to unit
+    vectors (columns of A~)."""
+    from tests.libhelpers import small_cases_3d
+    w = dict(small_cases() + small_cases_3d())[name]
+    ora = OracleOperator.from_workload(w)
+    rng = np.random.default_rng(21)
+    n = np.array(w.shape)
+    xs = rng.integers(0, n, (500, w.d))
+    xs[:30] = w.points[rng.integers(0, w.r, 30)]
+    ys = np.clip(xs + rng.integers(-8, 9, (500, w.d)), 0, n - 1)
+    ref = np.array([ora.entry(y, x) for y, x in zip(ys, xs)])
+    scale = np.abs(ref).max()
+    for dtype, tol in ((lib.PC_F64, 1e-13), (lib.PC_F32, 2e-6)):
+        op = lib.PcOperator.from_workload(w, dtype=dtype)
+        got = op.entries(torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()).cpu().numpy()
+        assert np.abs(got - ref).max() <= tol * scale, (name, dtype)
+        bad = op.entries(torch.tensor([list(n)], dtype=torch.int64).cuda(),
+                         torch.zeros((1, w.d), dtype=torch.int64).cuda()).cpu().numpy()
+        assert np.isnan(bad[0])
+        if dtype == lib.PC_F64:
+            # column x of A~ from an apply to the unit vector at x
+            x = xs[5]
+            e = torch.zeros(w.N, dtype=torch.float64, device="cuda")
+            e[int(np.ravel_multi_index(tuple(x), w.shape))] = 1.0
+            col = torch.zeros_like(e)
+            op.apply(e, col)
+            allys = np.stack(np.unravel_index(np.arange(w.N), w.shape), axis=1)
+            ent = op.entries(torch.from_numpy(allys).cuda(),
+                             torch.from_numpy(np.repeat(x[None, :], w.N, axis=0)).cuda())
+            torch.cuda.synchronize()
+            assert (ent - col).abs().max().item() <= 1e-13 * col.abs().max().item()
+        op.close()

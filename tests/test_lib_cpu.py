@@ -163,6 +163,76 @@ def test_create_patches_rejects_bad_selection():
     assert st == PC_ERR_ARG, msg
 
 
+def _emu_handle(lib, w, dtype=1, patches=None):
+    k = [np.ascontiguousarray(v, dtype=np.int64) for v in (w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius)]
+    phi = np.ascontiguousarray(w.phi, dtype=np.float64)
+    off = np.ascontiguousarray(w.phi_off, dtype=np.int64)
+    h = ctypes.c_void_p()
+    if patches is None:
+        rc = lib.pc_emu_create(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
+                               len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data, off.ctypes.data,
+                               dtype, 0, ctypes.byref(h))
+    else:
+        sel = np.ascontiguousarray(patches, dtype=np.int64)
+        rc = lib.pc_emu_create_patches(w.d, k[0].ctypes.data, len(w.leaf_lo), k[1].ctypes.data, k[2].ctypes.data,
+                                       len(w.points), k[3].ctypes.data, k[4].ctypes.data, phi.ctypes.data,
+                                       off.ctypes.data, dtype, 0, sel.size, sel.ctypes.data, ctypes.byref(h))
+    assert rc == 0, lib.pc_emu_last_error()
+    return h
+
+
+def _emu_entries(lib, h, ys, xs):
+    lib.pc_emu_entries.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    ys = np.ascontiguousarray(ys, dtype=np.int64)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    out = np.zeros(len(ys))
+    lib.pc_emu_entries(h, len(ys), ys.ctypes.data, xs.ctypes.data, out.ctypes.data)
+    return out
+
+
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect3d"])
+def test_emulated_entries_match_oracle(name):
+    """Matrix entries (Sec. 3.1) from the library's entry function against
+    the oracle's entry formula: random pairs with y near x (inside the kernel
+    boxes), pairs on leaf edges and corners, and pairs outside Omega (NaN)."""
+    w = dict(small_cases() + small_cases_3d())[name]
+    lib = _emu_lib()
+    h = _emu_handle(lib, w)
+    ora = OracleOperator.from_workload(w)
+    rng = np.random.default_rng(9)
+    n = np.array(w.shape)
+    xs = rng.integers(0, n, (300, w.d))
+    xs[:20] = w.points[rng.integers(0, w.r, 20)]             # on sample points / leaf corners
+    ys = np.clip(xs + rng.integers(-6, 7, (300, w.d)), 0, n - 1)
+    got = _emu_entries(lib, h, ys, xs)
+    ref = np.array([ora.entry(y, x) for y, x in zip(ys, xs)])
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), name
+    bad = _emu_entries(lib, h, np.vstack([n, n - 1]), np.vstack([n - 1, -np.ones(w.d, dtype=np.int64)]))
+    assert np.all(np.isnan(bad))
+    # entries of a term subset + its complement = the full entries
+    S = rng.permutation(w.r)[: w.r // 2]
+    Sc = np.setdiff1d(np.arange(w.r), S)
+    hs, hc = _emu_handle(lib, w, patches=S), _emu_handle(lib, w, patches=Sc)
+    part = _emu_entries(lib, hs, ys, xs) + _emu_entries(lib, hc, ys, xs)
+    assert np.abs(part - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    for x in (h, hs, hc):
+        lib.pc_emu_destroy(x)
+
+
+def test_emulated_entries_form_the_dense_matrix():
+    """On the 1-D case every entry (N^2 pairs) equals the oracle's dense A~."""
+    w = dict(small_cases())["1d"]
+    lib = _emu_lib()
+    h = _emu_handle(lib, w)
+    N = w.N
+    yy, xx = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    got = _emu_entries(lib, h, yy.reshape(-1, 1), xx.reshape(-1, 1)).reshape(N, N)
+    ref = OracleOperator.from_workload(w).dense()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    lib.pc_emu_destroy(h)
+
+
 def test_emulated_kernels_under_address_sanitizer():
     """Same emulation built with AddressSanitizer, run in a child process with
     the sanitizer runtime preloaded: any out-of-range index aborts it."""
@@ -175,8 +245,13 @@ def test_emulated_kernels_under_address_sanitizer():
         "from tests.test_lib_cpu import _emu_lib, emu_apply\n"
         "from tests.libhelpers import small_cases, small_cases_3d\n"
         "lib = _emu_lib(%r)\n"
+        "from tests.test_lib_cpu import _emu_handle, _emu_entries\n"
         "for name, w in small_cases() + small_cases_3d():\n"
         "    U = np.random.default_rng(1).standard_normal((2, w.N))\n"
+        "    h = _emu_handle(lib, w)\n"
+        "    xs = np.random.default_rng(2).integers(0, np.array(w.shape), (50, w.d))\n"
+        "    _emu_entries(lib, h, np.clip(xs + 3, 0, np.array(w.shape) - 1), xs)\n"
+        "    lib.pc_emu_destroy(h)\n"
         "    for dt in (0, 1):\n"
         "        for fl in (0, 1):\n"
         "            for adj in (0, 1): emu_apply(lib, w, U, dt, fl, adj)\n"
