@@ -176,6 +176,22 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
                             hipStream_t s);
 
 /* Plan statistics (for measurement and admission). */
+/* pc_apply_block -- apply a block of the operator (Sec. 3.3):
+ *   adjoint = 0:  OUT_T[:, j] = A~[T, S] U_S[:, j]
+ *   adjoint = 1:  OUT_T[:, j] = A~*[T, S] U_S[:, j]  ((A~*)[T, S] = A~[S, T]*)
+ * tlo/thi, slo/shi: host int64 [d] inclusive boxes inside Omega (else
+ * PC_ERR_ARG).  U_S: device [B][ldu], each vector row-major over the box S
+ * (ldu >= |S|); OUT_T: device [B][ldo] over T (ldo >= |T|), fully written.
+ * Only the work items whose gather box meets S (adjoint: whose output box
+ * meets S) and whose written box meets T run, both boxes clipped, so the
+ * cost follows the paper's O(r_S sigma log sigma) (adjoint: r_T).  Results
+ * equal the restriction to T of the full apply to U_S extended by zero, to
+ * rounding.  d = 3 gives PC_ERR_UNSUPPORTED.  Each call copies its small
+ * tables to the device synchronously. */
+pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64_t* thi,
+                         const int64_t* slo, const int64_t* shi, int64_t B,
+                         const void* U, int64_t ldu, void* OUT, int64_t ldo, hipStream_t s);
+
 /* pc_entries -- matrix entries out[i] = A~[ys[i], xs[i]] for i < n (Sec. 3.1,
  * eq. (3.1)): sum over the points k of a leaf containing x of
  * w_k[x] phi_k^E[y - x], accumulated in FP64 in ascending k and rounded to

@@ -56,6 +56,8 @@ for _name in ("pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain"
 for _name in ("pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy"):
     getattr(_lib, _name).argtypes = [_P, _I64, _P, _I64, ctypes.c_double, _P, _I64, _P]
     getattr(_lib, _name).restype = ctypes.c_int
+_lib.pc_apply_block.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P]
+_lib.pc_apply_block.restype = ctypes.c_int
 _lib.pc_entries.argtypes = [_P, _I64, _P, _P, _P, _P]
 _lib.pc_entries.restype = ctypes.c_int
 _lib.pc_estimate_sums.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P]
@@ -81,7 +83,7 @@ _lib.pc_last_error.argtypes = []
 _lib.pc_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
-            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_entries",
+            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_apply_block", "pc_entries",
             "pc_estimate_sums",
             "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
@@ -197,6 +199,18 @@ class PcOperator:
     def apply_adjoint_batch_axpy(self, V, alpha, OUT, stream=None):
         """OUT += alpha * A~* V."""
         return self._axpy(_lib.pc_apply_adjoint_batch_axpy, V, alpha, OUT, stream)
+
+    def apply_block(self, t_box, s_box, U, OUT, adjoint=False, stream=None):
+        """OUT_T = A~[T, S] U_S (adjoint: A~*[T, S] U_S), pc_apply_block.
+        t_box, s_box: (lo, hi) pairs of d inclusive coordinates; U: (B, |S|)
+        and OUT: (B, |T|) device tensors, row-major over the boxes."""
+        tlo, thi = _i64(t_box[0]).ravel(), _i64(t_box[1]).ravel()
+        slo, shi = _i64(s_box[0]).ravel(), _i64(s_box[1]).ravel()
+        B = 1 if U.dim() == 1 else U.shape[0]
+        _check(_lib.pc_apply_block(self._h, int(bool(adjoint)), tlo.ctypes.data, thi.ctypes.data, slo.ctypes.data,
+                                   shi.ctypes.data, B, _dev(U, self.torch_dtype, "U"), _ld(U, "U"),
+                                   _dev(OUT, self.torch_dtype, "OUT"), _ld(OUT, "OUT"), _stream(stream)))
+        return OUT
 
     def entries(self, ys, xs, out=None, stream=None):
         """Matrix entries A~[ys[i], xs[i]] (pc_entries); ys, xs: (n, d) int64

@@ -207,6 +207,50 @@ int pc_emu_stats(pc_emu* e, int64_t* out8) {
     return 0;
 }
 
+// Block apply (same per-call plan and phases as the library): OUT_T over T
+// from U_S over S, host arrays.
+int pc_emu_apply_block(pc_emu* e, int adj, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                       const int64_t* shi, int64_t B, const double* U, int64_t ldu, double* OUT, int64_t ldo) {
+    const pc::Plan& P = e->plan;
+    if (P.dtype != PC_F64) return -1;
+    pc::BlockPlan bp;
+    std::string err;
+    pc_status st = pc::build_block(P, adj != 0, tlo, thi, slo, shi, bp, err);
+    if (st != PC_OK) {
+        g_emu_err = err;
+        return (int)st;
+    }
+    using C = pc::cx<double>;
+    const C* spec = reinterpret_cast<const C*>(P.spec.data());
+    const C* tw = reinterpret_cast<const C*>(P.tw.data());
+    const int64_t nS = (int64_t)bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
+    for (int64_t b = 0; b < B; ++b) {
+        std::vector<double> in(U + b * ldu, U + b * ldu + nS);
+        std::vector<double> slots((size_t)std::max<int64_t>(bp.per, 1), 0.0);
+        for (const pc::Item& it : bp.items) {
+            std::vector<C> buf((size_t)it.n0 * it.ld, C{1e30, 1e30});
+            pc::Ctx<double> c = pc::make_ctx<double>(it, adj != 0, in.data(), slots.data(), P.wts.data(), spec, tw,
+                                                     bp.s_cols);
+            const int nth = P.conv_threads;
+            for (int t = 0; t < nth; ++t) pc::phA0(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phA(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phB(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phC(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phD(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phE(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phF(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phG(c, buf.data(), t, nth);
+            for (int t = 0; t < nth; ++t) pc::phH(c, buf.data(), t, nth);
+        }
+        std::vector<double> out((size_t)nT, 0.0);
+        for (const pc::Tile& t : bp.tiles)
+            for (int col = 0; col < pc::kReduceCols; ++col)
+                pc::reduce_tile<double>(t, col, bp.cboxes.data(), slots.data(), out.data(), bp.t_cols);
+        std::memcpy(OUT + b * ldo, out.data(), sizeof(double) * (size_t)nT);
+    }
+    return 0;
+}
+
 // Matrix entries on the host with the same entry function as the kernel
 // (FP64 tables): out[i] = A~[ys[i], xs[i]], host int64 [n][d] coordinates.
 int pc_emu_entries(pc_emu* e, int64_t n, const int64_t* ys, const int64_t* xs, double* out) {

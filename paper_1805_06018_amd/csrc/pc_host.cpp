@@ -61,6 +61,10 @@ struct pc_op {
     size_t est_bytes = 0;
     int32_t* leaf_box = nullptr;   // [L][6] leaf boxes, device
     void* d_wts = nullptr;         // weight tables (dtype), device
+    // block applies: per-call tables and the event of the last call using them
+    void* blk = nullptr;
+    size_t blk_bytes = 0;
+    hipEvent_t blk_done = nullptr;
     // matrix entries: tables uploaded on the first pc_entries call
     bool ent_ready = false;
     pc::EntryTables ent{};
@@ -89,6 +93,8 @@ struct pc_op {
         for (void* p : allocs) hipFree(p);
         if (slots) hipFree(slots);
         if (scratch) hipFree(scratch);
+        if (blk) hipFree(blk);
+        if (blk_done) hipEventDestroy(blk_done);
         if (work) hipFree(work);
         if (est) hipFree(est);
     }
@@ -553,6 +559,71 @@ pc_status pc_apply_batch_axpy(pc_op* op, int64_t B, const void* U, int64_t ldu, 
 pc_status pc_apply_adjoint_batch_axpy(pc_op* op, int64_t B, const void* V, int64_t ldv, double alpha, void* OUT,
                                       int64_t ldo, hipStream_t s) {
     return run_batch(op, true, false, B, V, ldv, OUT, ldo, s, true, alpha);
+}
+
+pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                         const int64_t* shi, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                         hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    if (B < 0) return fail(PC_ERR_ARG, "negative batch size");
+    pc::BlockPlan bp;
+    std::string err;
+    st = pc::build_block(op->plan, adjoint != 0, tlo, thi, slo, shi, bp, err);
+    if (st != PC_OK) return fail(st, err);
+    const int64_t nS = (int64_t)bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
+    if (B == 0) return PC_OK;
+    if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
+    if (ldu < nS || ldo < nT) return fail(PC_ERR_ARG, "leading dimension smaller than the block box");
+    if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
+    // per-call tables: items | tiles | contributor boxes
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t bi = al(bp.items.size() * sizeof(pc::Item)), bt = al(bp.tiles.size() * sizeof(pc::Tile)),
+                 bc = al(bp.cboxes.size() * sizeof(pc::Box));
+    hipError_t e;
+    if (op->blk_done) {
+        e = hipEventSynchronize(op->blk_done);   // the previous block call may still read the tables
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    } else {
+        e = hipEventCreateWithFlags(&op->blk_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    st = ensure(&op->blk, &op->blk_bytes, std::max<size_t>(bi + bt + bc, 256), "hipMalloc (block tables)");
+    if (st != PC_OK) return st;
+    char* base = static_cast<char*>(op->blk);
+    if (!bp.items.empty()) e = hipMemcpy(base, bp.items.data(), bp.items.size() * sizeof(pc::Item), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !bp.tiles.empty())
+        e = hipMemcpy(base + bi, bp.tiles.data(), bp.tiles.size() * sizeof(pc::Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !bp.cboxes.empty())
+        e = hipMemcpy(base + bi + bt, bp.cboxes.data(), bp.cboxes.size() * sizeof(pc::Box), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (block tables)");
+    pc::DevPlan Dc = op->dev;          // convolution: gather pitch of S
+    Dc.items = reinterpret_cast<const pc::Item*>(base);
+    Dc.n_items = (int)bp.items.size();
+    Dc.cols = bp.s_cols;
+    pc::DevPlan Dr = op->dev;          // reduction over T
+    Dr.tiles_fwd = Dr.tiles_adj = reinterpret_cast<const pc::Tile*>(base + bi);
+    Dr.n_tiles_fwd = Dr.n_tiles_adj = (int)bp.tiles.size();
+    Dr.cboxes_fwd = Dr.cboxes_adj = reinterpret_cast<const pc::Box*>(base + bi + bt);
+    Dr.rows = bp.t_rows;
+    Dr.cols = bp.t_cols;
+    const size_t per_bytes = (size_t)std::max<int64_t>(bp.per, 1) * op->esz;
+    const int64_t chunk = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t)(kSlotCapBytes / per_bytes)));
+    st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    if (st != PC_OK) return st;
+    const char* u = static_cast<const char*>(U);
+    char* o = static_cast<char*>(OUT);
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        e = pc::launch_conv(Dc, adjoint != 0, 0, Dc.n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu, op->slots,
+                            bp.per, s);
+        if (e != hipSuccess) return hip_fail(e, "block conv launch");
+        e = pc::launch_reduce(Dr, adjoint != 0, nb, op->slots, bp.per, o + (size_t)b0 * ldo * op->esz, ldo, s);
+        if (e != hipSuccess) return hip_fail(e, "block reduce launch");
+    }
+    e = hipEventRecord(op->blk_done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return PC_OK;
 }
 
 pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs, void* out, hipStream_t s) {

@@ -24,7 +24,9 @@ constexpr int axis_cols(int dtype) { return dtype == 1 ? 32 : 64; }
 // (g0 + i0, g1 + i1).  The input box of the forward sum (the patch's
 // weighted gather box I) sits at FFT offset (in_off0, in_off1) with extent
 // (in_n0, in_n1); the output box O = (I + kernel box) n Omega sits at FFT
-// offset (0, 0) with extent (out_n0, out_n1).  The adjoint swaps the roles.
+// offset (out_off0, out_off1) with extent (out_n0, out_n1) (offset 0 for the
+// whole operator; block applies clip both boxes).  The adjoint swaps the
+// roles.
 struct Item {
     int32_t n0;          // column FFT length (axis 0); 1 for 1-D problems
     int32_t a0, b0;      // n0 = a0 * b0
@@ -35,6 +37,7 @@ struct Item {
     int32_t g0, g1;      // Omega coordinates of FFT index (0, 0)
     int32_t in_off0, in_off1, in_n0, in_n1;
     int32_t out_n0, out_n1;
+    int32_t out_off0, out_off1;  // FFT offset of the output box (0 except in block applies)
     int32_t patch;       // k
     int32_t w_ld;        // row stride of the weight table (the patch's box width)
     int64_t w_off;       // weight table (in_n0 x in_n1 block, row stride w_ld)

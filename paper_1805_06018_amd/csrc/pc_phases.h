@@ -64,10 +64,10 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
     c.adj = adj;
     if (!adj) {
         c.s_off0 = it.in_off0; c.s_n0 = it.in_n0; c.s_off1 = it.in_off1; c.s_n1 = it.in_n1;
-        c.d_off0 = 0; c.d_n0 = it.out_n0; c.d_off1 = 0; c.d_n1 = it.out_n1;
+        c.d_off0 = it.out_off0; c.d_n0 = it.out_n0; c.d_off1 = it.out_off1; c.d_n1 = it.out_n1;
         c.dst = slot_vec + it.slot_fwd;
     } else {
-        c.s_off0 = 0; c.s_n0 = it.out_n0; c.s_off1 = 0; c.s_n1 = it.out_n1;
+        c.s_off0 = it.out_off0; c.s_n0 = it.out_n0; c.s_off1 = it.out_off1; c.s_n1 = it.out_n1;
         c.d_off0 = it.in_off0; c.d_n0 = it.in_n0; c.d_off1 = it.in_off1; c.d_n1 = it.in_n1;
         c.dst = slot_vec + it.slot_adj;
     }

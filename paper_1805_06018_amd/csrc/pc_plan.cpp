@@ -311,6 +311,88 @@ bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::stri
     return true;
 }
 
+pc_status build_block(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                      const int64_t* shi, BlockPlan& B, std::string& err) {
+    if (P.d == 3) {
+        err = "block applies of 3-D operators are not implemented";
+        return PC_ERR_UNSUPPORTED;
+    }
+    if (!tlo || !thi || !slo || !shi) {
+        err = "null box pointer";
+        return PC_ERR_ARG;
+    }
+    const int d = P.d;
+    for (int i = 0; i < d; ++i)
+        if (tlo[i] < 0 || thi[i] >= P.shape[i] || tlo[i] > thi[i] || slo[i] < 0 || shi[i] >= P.shape[i] ||
+            slo[i] > shi[i]) {
+            err = "block boxes must be non-empty and inside Omega";
+            return PC_ERR_ARG;
+        }
+    // boxes in the 2-D view (d = 1: one row)
+    const int64_t T0 = d == 1 ? 0 : tlo[0], T1 = tlo[d - 1], Tn0 = d == 1 ? 1 : thi[0] - tlo[0] + 1,
+                  Tn1 = thi[d - 1] - tlo[d - 1] + 1;
+    const int64_t S0 = d == 1 ? 0 : slo[0], S1 = slo[d - 1], Sn0 = d == 1 ? 1 : shi[0] - slo[0] + 1,
+                  Sn1 = shi[d - 1] - slo[d - 1] + 1;
+    B = BlockPlan();
+    B.t_rows = (int)Tn0;
+    B.t_cols = (int)Tn1;
+    B.s_rows = (int)Sn0;
+    B.s_cols = (int)Sn1;
+    auto clip = [](int64_t alo, int64_t an, int64_t blo, int64_t bn, int64_t& lo, int64_t& n) {
+        lo = std::max(alo, blo);
+        n = std::min(alo + an, blo + bn) - lo;
+        return n > 0;
+    };
+    std::vector<Box> boxes;
+    for (const Item& it : P.items) {
+        // input box I and output box O in Omega coordinates
+        const int64_t I0 = it.g0 + it.in_off0, I1 = it.g1 + it.in_off1;
+        const int64_t O0 = it.g0, O1 = it.g1;
+        int64_t g0l, g0n, g1l, g1n, w0l, w0n, w1l, w1n;   // gathered and written boxes
+        bool ok;
+        if (!adjoint)
+            ok = clip(I0, it.in_n0, S0, Sn0, g0l, g0n) && clip(I1, it.in_n1, S1, Sn1, g1l, g1n) &&
+                 clip(O0, it.out_n0, T0, Tn0, w0l, w0n) && clip(O1, it.out_n1, T1, Tn1, w1l, w1n);
+        else
+            ok = clip(O0, it.out_n0, S0, Sn0, g0l, g0n) && clip(O1, it.out_n1, S1, Sn1, g1l, g1n) &&
+                 clip(I0, it.in_n0, T0, Tn0, w0l, w0n) && clip(I1, it.in_n1, T1, Tn1, w1l, w1n);
+        if (!ok) continue;
+        Item c = it;
+        if (!adjoint) {
+            c.in_off0 = (int32_t)(g0l - it.g0);
+            c.in_off1 = (int32_t)(g1l - it.g1);
+            c.in_n0 = (int32_t)g0n;
+            c.in_n1 = (int32_t)g1n;
+            c.w_off = it.w_off + (g0l - I0) * it.w_ld + (g1l - I1);
+            c.out_off0 = (int32_t)(w0l - it.g0);
+            c.out_off1 = (int32_t)(w1l - it.g1);
+            c.out_n0 = (int32_t)w0n;
+            c.out_n1 = (int32_t)w1n;
+        } else {
+            c.out_off0 = (int32_t)(g0l - it.g0);
+            c.out_off1 = (int32_t)(g1l - it.g1);
+            c.out_n0 = (int32_t)g0n;
+            c.out_n1 = (int32_t)g1n;
+            c.in_off0 = (int32_t)(w0l - it.g0);
+            c.in_off1 = (int32_t)(w1l - it.g1);
+            c.in_n0 = (int32_t)w0n;
+            c.in_n1 = (int32_t)w1n;
+            c.w_off = it.w_off + (w0l - I0) * it.w_ld + (w1l - I1);
+        }
+        c.g0 = (int32_t)(it.g0 - S0);     // gather in S-local coordinates
+        c.g1 = (int32_t)(it.g1 - S1);
+        c.slot_fwd = c.slot_adj = B.per;
+        boxes.push_back(Box{(int32_t)(w0l - T0), (int32_t)(w1l - T1), (int32_t)w0n, (int32_t)w1n, B.per});
+        B.per += w0n * w1n;
+        B.items.push_back(c);
+    }
+    std::vector<int32_t> contrib;
+    if (!build_tiles(boxes, B.t_rows, B.t_cols, B.tiles, contrib, err)) return PC_ERR_UNSUPPORTED;
+    B.cboxes.resize(contrib.size());
+    for (size_t i = 0; i < contrib.size(); ++i) B.cboxes[i] = boxes[(size_t)contrib[i]];
+    return PC_OK;
+}
+
 // ======================================================================
 pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     // ---------------------------------------------------------- arguments

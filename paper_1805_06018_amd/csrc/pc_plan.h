@@ -98,6 +98,23 @@ const Dft64& dft64(int n);
 // reduction tiles and contributor boxes of both directions from the
 // per-item staging boxes (ascending item order)
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);
+// Block apply (Sec. 3.3): OUT_T = A~[T, S] U_S or A~*[T, S] U_S, with U_S
+// row-major over the box S and OUT_T over the box T (d <= 2).  Every work
+// item whose gather box meets S and whose written box meets T takes part,
+// both boxes clipped; the FFT of the whole item is kept, so the clipped
+// convolution is exact.  Gather coordinates are S-local, reduction tiles
+// T-local.
+struct BlockPlan {
+    std::vector<Item> items;
+    std::vector<Tile> tiles;
+    std::vector<Box> cboxes;
+    int64_t per = 0;                 // staging elements per vector
+    int t_rows = 0, t_cols = 0;      // T in the 2-D view
+    int s_rows = 0, s_cols = 0;      // S in the 2-D view
+};
+pc_status build_block(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                      const int64_t* shi, BlockPlan& B, std::string& err);
+
 // 3-D operators (called by build_plan after the argument checks)
 pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err);
 

@@ -233,6 +233,58 @@ def test_emulated_entries_form_the_dense_matrix():
     lib.pc_emu_destroy(h)
 
 
+def _box_vec(shape, lo, hi, full):
+    sl = tuple(slice(int(a), int(b) + 1) for a, b in zip(lo, hi))
+    return np.ascontiguousarray(full.reshape(shape)[sl]).ravel()
+
+
+def _emu_block(lib, h, adj, t_box, s_box, US):
+    lib.pc_emu_apply_block.argtypes = [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 4 + \
+        [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]
+    b = [np.ascontiguousarray(v, dtype=np.int64) for v in (t_box[0], t_box[1], s_box[0], s_box[1])]
+    nT = int(np.prod(b[1] - b[0] + 1))
+    US = np.ascontiguousarray(US, dtype=np.float64)
+    out = np.full((US.shape[0], nT), np.nan)
+    rc = lib.pc_emu_apply_block(h, int(adj), b[0].ctypes.data, b[1].ctypes.data, b[2].ctypes.data,
+                                b[3].ctypes.data, US.shape[0], US.ctypes.data, US.shape[1], out.ctypes.data, nT)
+    return rc, out
+
+
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect45x301"])
+def test_emulated_block_apply_matches_oracle(name):
+    """Block applies (Sec. 3.3): A~[T, S] u_S and A~*[T, S] v_S equal the
+    oracle's full apply of the zero-extended vector restricted to T, for
+    overlapping, disjoint, nested and whole-domain boxes."""
+    w = dict(small_cases())[name]
+    lib = _emu_lib()
+    h = _emu_handle(lib, w)
+    ora = OracleOperator.from_workload(w)
+    n = np.array(w.shape)
+    rng = np.random.default_rng(31)
+    boxes = [((np.zeros(w.d, int), n - 1), (np.zeros(w.d, int), n - 1))]
+    for _ in range(4):
+        a, b = np.sort(rng.integers(0, n, (2, w.d)), axis=0)
+        c, e = np.sort(rng.integers(0, n, (2, w.d)), axis=0)
+        boxes.append(((a, b), (c, e)))
+    for t_box, s_box in boxes:
+        full = rng.standard_normal(w.N)
+        ext = np.zeros(w.N)
+        sl = tuple(slice(int(x), int(y) + 1) for x, y in zip(*s_box))
+        ext.reshape(w.shape)[sl] = full.reshape(w.shape)[sl]
+        US = _box_vec(w.shape, *s_box, full)[None, :]
+        for adj in (False, True):
+            rc, got = _emu_block(lib, h, adj, t_box, s_box, US)
+            assert rc == 0
+            ref = _box_vec(w.shape, *t_box, (ora.apply_adjoint if adj else ora.apply)(ext))
+            scale = max(np.abs(ref).max(), 1e-300)
+            assert np.abs(got[0] - ref).max() <= 1e-12 * max(scale, 1.0), (name, adj, t_box, s_box)
+    # boxes outside Omega are rejected
+    rc, _ = _emu_block(lib, h, False, (np.zeros(w.d, int), n), (np.zeros(w.d, int), n - 1),
+                       np.zeros((1, w.N)))
+    assert rc != 0
+    lib.pc_emu_destroy(h)
+
+
 def test_emulated_kernels_under_address_sanitizer():
     """Same emulation built with AddressSanitizer, run in a child process with
     the sanitizer runtime preloaded: any out-of-range index aborts it."""
@@ -245,12 +297,16 @@ def test_emulated_kernels_under_address_sanitizer():
         "from tests.test_lib_cpu import _emu_lib, emu_apply\n"
         "from tests.libhelpers import small_cases, small_cases_3d\n"
         "lib = _emu_lib(%r)\n"
-        "from tests.test_lib_cpu import _emu_handle, _emu_entries\n"
+        "from tests.test_lib_cpu import _emu_handle, _emu_entries, _emu_block\n"
         "for name, w in small_cases() + small_cases_3d():\n"
         "    U = np.random.default_rng(1).standard_normal((2, w.N))\n"
         "    h = _emu_handle(lib, w)\n"
         "    xs = np.random.default_rng(2).integers(0, np.array(w.shape), (50, w.d))\n"
         "    _emu_entries(lib, h, np.clip(xs + 3, 0, np.array(w.shape) - 1), xs)\n"
+        "    if w.d < 3:\n"
+        "        lo = np.array(w.shape) // 4; hi = np.array(w.shape) - 2\n"
+        "        _emu_block(lib, h, 0, (lo, hi), (lo // 2, hi - 1), np.ones((1, int(np.prod(hi - lo // 2)))))\n"
+        "        _emu_block(lib, h, 1, (lo, hi), (lo // 2, hi - 1), np.ones((1, int(np.prod(hi - lo // 2)))))\n"
         "    lib.pc_emu_destroy(h)\n"
         "    for dt in (0, 1):\n"
         "        for fl in (0, 1):\n"
