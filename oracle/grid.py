@@ -81,6 +81,30 @@ class Grid:
                 pts.add(tuple(int(hi[i] if b else lo[i]) for i, b in enumerate(bits)))
         return np.array(sorted(pts), dtype=np.int64).reshape(-1, self.d)
 
+    def facet_parts(self, c, axis, side):
+        """The facet of leaf c normal to ``axis`` (side 0: at lo, 1: at hi) as
+        the union of (d-1)-dimensional boxes (Sec. 2.4): where the leaves on
+        the other side are smaller the facet is broken into their facets
+        (clipped to it); a facet on the domain boundary, or facing one larger
+        leaf, is a single box.  Returns a list of (lo, hi) with lo[axis] =
+        hi[axis] = the facet's coordinate."""
+        lo, hi = self.leaf_lo[c], self.leaf_hi[c]
+        v = hi[axis] if side else lo[axis]
+        flo, fhi = lo.copy(), hi.copy()
+        flo[axis] = fhi[axis] = v
+        other = self.leaf_lo[:, axis] == v if side else self.leaf_hi[:, axis] == v
+        parts = []
+        for e in np.nonzero(other)[0]:
+            if e == c:
+                continue
+            plo = np.maximum(flo, self.leaf_lo[e])
+            phi = np.minimum(fhi, self.leaf_hi[e])
+            plo[axis] = phi[axis] = v
+            ok = all(phi[i] > plo[i] for i in range(self.d) if i != axis and fhi[i] > flo[i])
+            if ok:
+                parts.append((plo, phi))
+        return parts if parts else [(flo, fhi)]
+
     def leaf_of_each_point_mask(self):
         """Boolean (L, N) membership of grid points in leaves (tiny grids only)."""
         N = int(np.prod(self.shape))

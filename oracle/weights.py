@@ -9,8 +9,9 @@ Laplace equation (the positive definite graph Laplacian, i.e. the Kronecker-sum
 finite-difference Laplacian) with the already computed lower-dimensional
 values as Dirichlet data.  w_k is zero off U_k.
 
-Broken 2-D facets (3-D grids with hanging nodes) are not handled here: that
-case raises NotImplementedError.
+In 3-D a facet that contains hanging nodes (a broken facet) is replaced by
+the smaller boxes it is made of, the facets of the smaller leaves on its
+other side (Sec. 2.4); each of those boxes is solved on its own.
 """
 import itertools
 import numpy as np
@@ -62,11 +63,13 @@ def _laplace_dirichlet(box):
     return box
 
 
-def harmonic_on_box(lo, hi, pts, vals):
+def harmonic_on_box(lo, hi, pts, vals, facet_parts=None):
     """Recursive harmonic extension on the inclusive box [lo, hi].
 
     pts: (P, d) sample points lying in the box; vals: (P, nrhs) prescribed
-    values there.  Returns an array of shape (hi-lo+1) + (nrhs,).
+    values there.  facet_parts(i, side) -> list of (lo, hi) boxes making up
+    the facet normal to axis i (for a 3-D box with broken facets); None: every
+    facet is one box.  Returns an array of shape (hi-lo+1) + (nrhs,).
     """
     lo = np.asarray(lo)
     hi = np.asarray(hi)
@@ -93,25 +96,22 @@ def harmonic_on_box(lo, hi, pts, vals):
         shp = [1] * d
         shp[i] = S[i]
         return line.reshape(tuple(shp) + (nrhs,)) * np.ones(S + (1,))
-    if len(live) >= 3:
-        # every facet must be an unbroken box: no sample points except corners
-        corners = {tuple(int(hi[i] if b else lo[i]) for i, b in enumerate(bits))
-                   for bits in itertools.product((0, 1), repeat=d)}
-        for p in pts:
-            if tuple(int(v) for v in p) not in corners:
-                raise NotImplementedError("broken facets in 3-D (hanging nodes) are not supported")
-    # boundary: every facet, recursively
+    # boundary: every facet (or the boxes a broken facet is made of), recursively
     for i in live:
-        for side in (lo[i], hi[i]):
-            flo = lo.copy()
-            fhi = hi.copy()
-            flo[i] = side
-            fhi[i] = side
-            on = np.all((pts >= flo) & (pts <= fhi), axis=1)
-            fv = harmonic_on_box(flo, fhi, pts[on], vals[on])
-            sl = [slice(None)] * d
-            sl[i] = slice(side - lo[i], side - lo[i] + 1)
-            out[tuple(sl)] = fv
+        for sd, side in ((0, lo[i]), (1, hi[i])):
+            if facet_parts is not None and len(live) >= 3:
+                parts = facet_parts(i, sd)
+            else:
+                flo = lo.copy()
+                fhi = hi.copy()
+                flo[i] = side
+                fhi[i] = side
+                parts = [(flo, fhi)]
+            for plo, phi in parts:
+                on = np.all((pts >= plo) & (pts <= phi), axis=1)
+                fv = harmonic_on_box(plo, phi, pts[on], vals[on])
+                sl = tuple(slice(int(plo[j] - lo[j]), int(phi[j] - lo[j] + 1)) for j in range(d))
+                out[sl] = fv
     return _laplace_dirichlet(out)
 
 
@@ -143,7 +143,7 @@ def leaf_weights(grid, c, closed_form=True):
     if closed_form and len(idx) == ncorner:
         return idx, multilinear_on_box(lo, hi, pts)
     vals = np.eye(len(idx))
-    return idx, harmonic_on_box(lo, hi, pts, vals)
+    return idx, harmonic_on_box(lo, hi, pts, vals, facet_parts=lambda i, sd: grid.facet_parts(c, i, sd))
 
 
 def harmonic_weights(grid, closed_form=True):

@@ -14,7 +14,7 @@ from oracle import OracleOperator, Grid, TilingError, estimate, harmonic_weights
 from oracle.extension import extended_kernels, split_weights
 from oracle.weights import leaf_weights, harmonic_on_box
 from workloads import make_config, BlurOperator, uniform_nodes, tensor_leaves
-from tests.tilings import hanging_2d, const_blur, workload_from, tensor, refine
+from tests.tilings import hanging_2d, hanging_3d, extrude, const_blur, workload_from, tensor, refine
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -34,7 +34,7 @@ def _pu_check(op, tol=1e-14):
 
 
 # ---------------------------------------------------------------- weights (Sec. 2.4)
-@pytest.mark.parametrize("case", ["cfg0", "hanging", "hanging_solve", "1d", "3d"])
+@pytest.mark.parametrize("case", ["cfg0", "hanging", "hanging_solve", "1d", "3d", "3d_hanging"])
 def test_partition_of_unity(case):
     if case == "cfg0":
         op = OracleOperator.from_workload(make_config(0))
@@ -46,9 +46,12 @@ def test_partition_of_unity(case):
         lo = np.array([[0], [5], [7], [15]])
         hi = np.array([[5], [7], [15], [20]])
         op = OracleOperator.from_workload(const_blur((21,), 1.0, lo, hi))
-    else:
+    elif case == "3d":
         lo, hi = tensor((9, 8, 7), 3)
         op = OracleOperator.from_workload(const_blur((9, 8, 7), 0.8, lo, hi), closed_form_weights=False)
+    else:
+        lo, hi = hanging_3d(9)
+        op = OracleOperator.from_workload(const_blur((9, 9, 9), 0.8, lo, hi))
     _pu_check(op)
 
 
@@ -99,6 +102,83 @@ def test_hanging_cell_is_discrete_harmonic():
             kinks = np.abs(second) > 1e-12
             assert kinks.sum() <= 2 * len(idx)
     assert nhang > 0
+
+
+def test_3d_broken_facets_extruded_tiling_is_2d_times_hat():
+    """A 3-D tiling made of a 2-D hanging-node tiling times z intervals: its
+    harmonic weights are the 2-D weights times the linear hats in z (the
+    product of a discrete-harmonic 2-D function and a linear function is
+    discrete-harmonic for the Kronecker-sum Laplacian, and the extension is
+    unique).  Ties the 3-D face and volume solves to the pinned 2-D ones."""
+    lo2, hi2 = hanging_2d(17, corner=(16, 0), levels=2)
+    zn = [0, 3, 8]
+    lo, hi = extrude(lo2, hi2, zn)
+    g3 = Grid((17, 17, 9), lo, hi)
+    g2 = Grid((17, 17), lo2, hi2)
+    assert any(len(ix) > 8 for ix in g3.leaf_points)          # broken facets present
+    W3 = harmonic_weights(g3, closed_form=False)
+    W2 = harmonic_weights(g2, closed_form=False)
+    for k, p in enumerate(g3.points):
+        k2 = g2.index[(int(p[0]), int(p[1]))]
+        z = np.arange(g3.u_lo[k, 2], g3.u_hi[k, 2] + 1)
+        j = zn.index(int(p[2]))
+        hat = np.zeros(z.size)
+        for a, b in zip(zn[:-1], zn[1:]):
+            m = (z >= a) & (z <= b)
+            if p[2] == a:
+                hat[m] = np.maximum(hat[m], 1.0 - (z[m] - a) / (b - a))
+            elif p[2] == b:
+                hat[m] = np.maximum(hat[m], (z[m] - a) / (b - a))
+        assert j >= 0
+        sl = tuple(slice(int(g3.u_lo[k, i] - g2.u_lo[k2, i]), int(g3.u_hi[k, i] - g2.u_lo[k2, i] + 1))
+                   for i in range(2))
+        ref = W2[k2][sl][:, :, None] * hat[None, None, :]
+        assert np.abs(W3[k] - ref).max() < 1e-12, k
+
+
+def test_3d_broken_facets_are_discrete_harmonic_and_continuous():
+    """Octant-refined 9^3 tiling: on every leaf the weights satisfy the
+    7-point Laplacian in the interior and the 5-point one inside each box a
+    facet is made of; adjacent leaves give the same values on shared facets;
+    sample-point values are delta."""
+    lo, hi = hanging_3d(9)
+    g = Grid((9, 9, 9), lo, hi)
+    per_leaf = {c: leaf_weights(g, c, closed_form=False) for c in range(len(lo))}
+    nbroken = 0
+    for c, (idx, v) in per_leaf.items():
+        res = (v[2:, 1:-1, 1:-1] + v[:-2, 1:-1, 1:-1] + v[1:-1, 2:, 1:-1] + v[1:-1, :-2, 1:-1] +
+               v[1:-1, 1:-1, 2:] + v[1:-1, 1:-1, :-2] - 6 * v[1:-1, 1:-1, 1:-1])
+        assert np.abs(res).max() < 1e-12 if res.size else True
+        for i in range(3):
+            for sd in (0, 1):
+                parts = g.facet_parts(c, i, sd)
+                nbroken += len(parts) > 1
+                for plo, phi in parts:
+                    sl = tuple(slice(int(plo[j] - lo[c][j]), int(phi[j] - lo[c][j] + 1)) for j in range(3))
+                    f = np.squeeze(v[sl], axis=i)
+                    if min(f.shape[:2]) >= 3:
+                        r2 = f[2:, 1:-1] + f[:-2, 1:-1] + f[1:-1, 2:] + f[1:-1, :-2] - 4 * f[1:-1, 1:-1]
+                        assert np.abs(r2).max() < 1e-12
+        pts = g.points[idx]
+        for j, p in enumerate(pts):
+            assert abs(v[tuple(p - lo[c])][j] - 1.0) < 1e-14
+    assert nbroken > 0
+    # continuity: values of each point's weight agree on the intersection of two leaves
+    for c in range(len(lo)):
+        for e in range(c + 1, len(lo)):
+            a = np.maximum(lo[c], lo[e])
+            b = np.minimum(hi[c], hi[e])
+            if np.any(a > b):
+                continue
+            ic, vc = per_leaf[c]
+            ie, ve = per_leaf[e]
+            for j, k in enumerate(ic):
+                if k not in ie:
+                    continue
+                je = int(np.nonzero(ie == k)[0][0])
+                sc = tuple(slice(int(a[i] - lo[c][i]), int(b[i] - lo[c][i] + 1)) for i in range(3))
+                se = tuple(slice(int(a[i] - lo[e][i]), int(b[i] - lo[e][i] + 1)) for i in range(3))
+                assert np.abs(vc[sc][..., j] - ve[se][..., je]).max() < 1e-12
 
 
 # ---------------------------------------------------------------- extension (Sec. 2.5)
@@ -178,7 +258,7 @@ def test_prop1_product_partition_of_unity():
 
 
 # ---------------------------------------------------------------- apply (eq. (2.5))
-@pytest.mark.parametrize("case", ["1d", "2d_uniform", "2d_hanging", "3d"])
+@pytest.mark.parametrize("case", ["1d", "2d_uniform", "2d_hanging", "3d", "3d_hanging"])
 def test_exact_for_convolutions(case):
     """Thm. 1 with F = 0: a restricted convolution is reproduced exactly by any
     tiling, hanging nodes included (no boundary artifacts)."""
@@ -193,6 +273,9 @@ def test_exact_for_convolutions(case):
     elif case == "2d_hanging":
         lo, hi = hanging_2d(25, corner=(24, 0), levels=3)
         w = const_blur((25, 25), 1.9, lo, hi)
+    elif case == "3d_hanging":
+        lo, hi = hanging_3d(9)
+        w = const_blur((9, 9, 9), 0.8, lo, hi)
     else:
         lo, hi = tensor((9, 10, 8), 3)
         w = const_blur((9, 10, 8), 0.9, lo, hi)

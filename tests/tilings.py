@@ -58,3 +58,25 @@ def const_blur(shape, s, lo, hi):
 
 def tensor(shape, m):
     return tensor_leaves([uniform_nodes(n, m) for n in shape])
+
+
+def hanging_3d(n=9, min_width=2):
+    """n^3 domain refined (all axes at once) towards the corner (0, 0, 0) down
+    to leaves of width min_width: every face between the refined octants and
+    the coarse leaves is broken."""
+    def rule(lo, hi):
+        w = max(h - l for l, h in zip(lo, hi))
+        return w > min_width and (w >= n - 1 or all(l == 0 for l in lo))
+    return refine((n, n, n), rule)
+
+
+def extrude(lo2, hi2, znodes):
+    """3-D tiling: every 2-D leaf times every interval between z nodes."""
+    lo, hi = [], []
+    for a, b in zip(lo2, hi2):
+        for z0, z1 in zip(znodes[:-1], znodes[1:]):
+            lo.append([a[0], a[1], z0])
+            hi.append([b[0], b[1], z1])
+    lo, hi = np.array(lo, dtype=np.int64), np.array(hi, dtype=np.int64)
+    order = np.lexsort(lo.T[::-1])
+    return lo[order], hi[order]
