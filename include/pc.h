@@ -86,14 +86,15 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *  s                    : stream used for the uploads (synchronised before
  *                         return).
  *  out                  : receives the operator.
- * Weights w_k are the harmonic partition of unity of Sec. 2.4 (multilinear
- * hats on cells without hanging nodes); 2-D hanging nodes are supported.
- * For d = 3 every leaf must carry only its own corners (a conforming
- * tiling, trilinear weights); a 3-D leaf with hanging nodes on its faces or
- * edges gives PC_ERR_UNSUPPORTED.  PC_ERR_UNSUPPORTED is also returned when
- * a patch's FFT box exceeds the kernels' limits (FFT lengths up to 256 along
- * axis 0 (and axis 1 in 3-D), real length up to 256 along the last axis,
- * one LDS-resident plane per workgroup).
+ * Weights w_k are the harmonic partition of unity of Sec. 2.4: multilinear
+ * hats on cells without hanging nodes; on cells with hanging nodes the
+ * discrete harmonic extension, recursively in dimension (edges cut at the
+ * points on them, facets - a broken 3-D facet as the facets of the smaller
+ * leaves on its other side - then the cell), solved exactly.
+ * PC_ERR_UNSUPPORTED is returned when a patch's FFT box exceeds the
+ * kernels' limits (FFT lengths up to 256 along axis 0 (and axis 1 in 3-D),
+ * real length up to 256 along the last axis, one LDS-resident plane per
+ * workgroup; 2-D patches are cut into pieces, 3-D ones are not).
  */
 pc_status pc_create(int d, const int64_t* shape,
                     int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,

@@ -126,25 +126,23 @@ void edge_hat(const std::vector<int64_t>& cuts, int64_t pos, int64_t c0, int64_t
     }
 }
 
-// Sine eigenbasis of the tridiagonal T_n = tridiag(-1, 2, -1):
-// T_n = S diag(lambda) S with S symmetric orthogonal.
-struct SineBasis {
-    int n = 0;
-    std::vector<double> S, lam;
-    explicit SineBasis(int n_) : n(n_), S((size_t)n_ * n_), lam((size_t)n_) {
-        const double sc = std::sqrt(2.0 / (n + 1));
-        for (int i = 0; i < n; ++i)
-            for (int a = 0; a < n; ++a) S[(size_t)i * n + a] = sc * std::sin(kPi * (i + 1) * (a + 1) / (n + 1));
-        for (int a = 0; a < n; ++a) lam[(size_t)a] = 2.0 - 2.0 * std::cos(kPi * (a + 1) / (n + 1));
-    }
-};
-
 // Dirichlet problem for the 5-point graph Laplacian on the interior (p x q)
 // of a box, L U = R with L = T_p (x) I + I (x) T_q, solved exactly in the
 // sine eigenbasis: U = Sp [(Sp R Sq) / (lambda_a + mu_b)] Sq.  R holds the
 // boundary values next to the border only: R = e_0 t' + e_{p-1} b' + l e_0'
 // + r e_{q-1}' (t, b: top and bottom rows; l, r: left and right columns), so
 // Sp R Sq is a sum of four outer products.  Result in U (p x q, row-major).
+}  // namespace
+
+SineBasis::SineBasis(int n_) : n(n_), S((size_t)n_ * n_), lam((size_t)n_) {
+    const double sc = std::sqrt(2.0 / (n + 1));
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) S[(size_t)i * n + a] = sc * std::sin(kPi * (i + 1) * (a + 1) / (n + 1));
+    for (int a = 0; a < n; ++a) lam[(size_t)a] = 2.0 - 2.0 * std::cos(kPi * (a + 1) / (n + 1));
+}
+
+namespace {
+
 void dst_solve_border(const SineBasis& P, const SineBasis& Q, const double* t, const double* b, const double* l,
                       const double* r, std::vector<double>& U) {
     const int p = P.n, q = Q.n;

@@ -95,6 +95,13 @@ struct Dft64 {
 };
 // cached plan of length n (per thread)
 const Dft64& dft64(int n);
+// Sine eigenbasis of the tridiagonal T_n = tridiag(-1, 2, -1):
+// T_n = S diag(lambda) S with S symmetric orthogonal (row-major n x n).
+struct SineBasis {
+    int n = 0;
+    std::vector<double> S, lam;
+    explicit SineBasis(int n_);
+};
 // reduction tiles and contributor boxes of both directions from the
 // per-item staging boxes (ascending item order)
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);

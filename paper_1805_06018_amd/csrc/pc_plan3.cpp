@@ -1,9 +1,13 @@
 // Host planner of 3-D product-convolution operators (see pc_plan.h).
 //
-// Conforming leaves only: every leaf carries exactly its 2^d' corners (d' the
-// number of axes along which it has positive width), so the harmonic weights
-// of Sec. 2.4 are the trilinear hats of the leaf.  Tilings with hanging nodes
-// in 3-D are rejected with PC_ERR_UNSUPPORTED.
+// Weights (Sec. 2.4): on a leaf that carries only its 2^d' corners (d' the
+// number of axes along which it has positive width) the harmonic weights are
+// the trilinear hats.  On a leaf with hanging nodes they are built
+// recursively in dimension: point values, linear interpolation on segments
+// cut at the points on them, the 2-D harmonic extension on every facet (a
+// broken facet replaced by the facets of the smaller leaves on its other
+// side, clipped to it), then the 3-D harmonic extension of the facet values;
+// the Dirichlet problems are solved exactly in the sine eigenbasis.
 //
 // One work item per patch, no pieces: the FFT box nz x n1 x 2m is processed
 // plane by plane (2-D FFTs along axes 1, 2 in LDS) with an axis-0 pass over
@@ -14,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <map>
 #include <set>
 
@@ -29,6 +35,142 @@ int next_row_len(int need) {
         if (fft_factor(m, &a, &b) && b <= 10) return m;
     }
     return -1;
+}
+
+struct IBox {
+    int64_t lo[3], hi[3];
+};
+
+// Interior of the box (extents n, degenerate axes have n = 1) from its
+// boundary values: L U = R with L the Kronecker sum of T_{n_i - 2} over the
+// live axes, R the boundary neighbours; solved in the sine eigenbasis.
+void dirichlet_interior(const int64_t n[3], std::vector<double>& V) {
+    int64_t m[3], o[3];
+    bool live[3];
+    for (int i = 0; i < 3; ++i) {
+        live[i] = n[i] > 1;
+        m[i] = live[i] ? n[i] - 2 : 1;
+        o[i] = live[i] ? 1 : 0;
+        if (live[i] && m[i] <= 0) return;
+    }
+    auto at = [&](int64_t a, int64_t b, int64_t c) -> double& { return V[(size_t)((a * n[1] + b) * n[2] + c)]; };
+    const int64_t M = m[0] * m[1] * m[2];
+    std::vector<double> R((size_t)M, 0.0), T((size_t)M);
+    for (int64_t a = 0; a < m[0]; ++a)
+        for (int64_t b = 0; b < m[1]; ++b)
+            for (int64_t c = 0; c < m[2]; ++c) {
+                double s = 0.0;
+                const int64_t A = a + o[0], B = b + o[1], Cc = c + o[2];
+                if (live[0]) s += (a == 0 ? at(0, B, Cc) : 0.0) + (a == m[0] - 1 ? at(n[0] - 1, B, Cc) : 0.0);
+                if (live[1]) s += (b == 0 ? at(A, 0, Cc) : 0.0) + (b == m[1] - 1 ? at(A, n[1] - 1, Cc) : 0.0);
+                if (live[2]) s += (c == 0 ? at(A, B, 0) : 0.0) + (c == m[2] - 1 ? at(A, B, n[2] - 1) : 0.0);
+                R[(size_t)((a * m[1] + b) * m[2] + c)] = s;
+            }
+    std::unique_ptr<SineBasis> SB[3];
+    for (int i = 0; i < 3; ++i)
+        if (live[i]) SB[i].reset(new SineBasis((int)m[i]));
+    const int64_t stride[3] = {m[1] * m[2], m[2], 1};
+    auto transform = [&](std::vector<double>& X) {   // X <- (S (x) S (x) S) X over the live axes
+        for (int i = 0; i < 3; ++i) {
+            if (!live[i]) continue;
+            const SineBasis& B = *SB[i];
+            std::fill(T.begin(), T.end(), 0.0);
+            for (int64_t idx = 0; idx < M; ++idx) {
+                const int64_t ai = (idx / stride[i]) % m[i];
+                const int64_t base = idx - ai * stride[i];
+                const double x = X[(size_t)idx];
+                if (x == 0.0) continue;
+                for (int64_t k = 0; k < m[i]; ++k) T[(size_t)(base + k * stride[i])] += B.S[(size_t)(k * m[i] + ai)] * x;
+            }
+            X.swap(T);
+        }
+    };
+    transform(R);
+    for (int64_t a = 0; a < m[0]; ++a)
+        for (int64_t b = 0; b < m[1]; ++b)
+            for (int64_t c = 0; c < m[2]; ++c) {
+                double den = 0.0;
+                if (live[0]) den += SB[0]->lam[(size_t)a];
+                if (live[1]) den += SB[1]->lam[(size_t)b];
+                if (live[2]) den += SB[2]->lam[(size_t)c];
+                R[(size_t)((a * m[1] + b) * m[2] + c)] /= den;
+            }
+    transform(R);
+    for (int64_t a = 0; a < m[0]; ++a)
+        for (int64_t b = 0; b < m[1]; ++b)
+            for (int64_t c = 0; c < m[2]; ++c) at(a + o[0], b + o[1], c + o[2]) = R[(size_t)((a * m[1] + b) * m[2] + c)];
+}
+
+// Harmonic extension on the box b of the values pv[i] at the points
+// pts[i] lying on it (Sec. 2.4), recursively in dimension; parts(i, side)
+// gives the boxes a 3-D facet is made of.  Values row-major over b.
+void harmonic_box(const IBox& b, const int64_t* Pt, const std::vector<int64_t>& pts, const std::vector<double>& pv,
+                  const std::function<std::vector<IBox>(int, int)>* parts, std::vector<double>& out) {
+    int64_t n[3];
+    int live = 0, ax = -1;
+    for (int i = 0; i < 3; ++i) {
+        n[i] = b.hi[i] - b.lo[i] + 1;
+        if (n[i] > 1) {
+            ++live;
+            ax = i;
+        }
+    }
+    out.assign((size_t)(n[0] * n[1] * n[2]), 0.0);
+    auto inside = [&](int64_t k, const IBox& x) {
+        for (int i = 0; i < 3; ++i)
+            if (Pt[3 * k + i] < x.lo[i] || Pt[3 * k + i] > x.hi[i]) return false;
+        return true;
+    };
+    if (live == 0) {
+        for (size_t j = 0; j < pts.size(); ++j)
+            if (inside(pts[j], b)) out[0] = pv[j];
+        return;
+    }
+    if (live == 1) {   // linear between consecutive points on the segment
+        std::vector<std::pair<int64_t, double>> cut;
+        for (size_t j = 0; j < pts.size(); ++j)
+            if (inside(pts[j], b)) cut.push_back({Pt[3 * pts[j] + ax], pv[j]});
+        std::sort(cut.begin(), cut.end());
+        for (size_t q = 0; q + 1 < cut.size(); ++q) {
+            const int64_t x0 = cut[q].first, x1 = cut[q + 1].first;
+            for (int64_t x = x0; x <= x1; ++x) {
+                const double t = (double)(x - x0) / (double)(x1 - x0);
+                out[(size_t)(x - b.lo[ax])] = cut[q].second * (1.0 - t) + cut[q + 1].second * t;
+            }
+        }
+        return;
+    }
+    std::vector<double> fv;
+    for (int i = 0; i < 3; ++i) {
+        if (n[i] <= 1) continue;
+        for (int side = 0; side < 2; ++side) {
+            std::vector<IBox> fs;
+            if (live == 3 && parts) {
+                fs = (*parts)(i, side);
+            } else {
+                IBox f = b;
+                f.lo[i] = f.hi[i] = side ? b.hi[i] : b.lo[i];
+                fs.push_back(f);
+            }
+            for (const IBox& f : fs) {
+                std::vector<int64_t> fp;
+                std::vector<double> fval;
+                for (size_t j = 0; j < pts.size(); ++j)
+                    if (inside(pts[j], f)) {
+                        fp.push_back(pts[j]);
+                        fval.push_back(pv[j]);
+                    }
+                harmonic_box(f, Pt, fp, fval, nullptr, fv);
+                const int64_t fn[3] = {f.hi[0] - f.lo[0] + 1, f.hi[1] - f.lo[1] + 1, f.hi[2] - f.lo[2] + 1};
+                for (int64_t a = 0; a < fn[0]; ++a)
+                    for (int64_t c = 0; c < fn[1]; ++c)
+                        for (int64_t e = 0; e < fn[2]; ++e)
+                            out[(size_t)(((f.lo[0] - b.lo[0] + a) * n[1] + (f.lo[1] - b.lo[1] + c)) * n[2] +
+                                         (f.lo[2] - b.lo[2] + e))] = fv[(size_t)((a * fn[1] + c) * fn[2] + e)];
+            }
+        }
+    }
+    dirichlet_interior(n, out);
 }
 
 struct Geo3 {
@@ -69,15 +211,6 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
                 cells[k].push_back(c);
             }
         }
-    for (int64_t c = 0; c < L; ++c) {
-        int live = 0;
-        for (int i = 0; i < 3; ++i) live += hi(c, i) > lo(c, i);
-        if ((int64_t)leaf_pts[c].size() != (int64_t)(1 << live)) {
-            err = "leaf " + std::to_string(c) +
-                  " has hanging nodes: 3-D operators need a conforming tiling (trilinear weights)";
-            return PC_ERR_UNSUPPORTED;
-        }
-    }
     std::vector<std::vector<int64_t>> nbrs(r);
     std::vector<int64_t> Ulo(3 * r, INT64_MAX), Uhi(3 * r, INT64_MIN);
     for (int64_t k = 0; k < r; ++k) {
@@ -113,24 +246,91 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         }
     }
     std::vector<double> W((size_t)w_base[r], 0.0);
+    // leaves are independent: weights solved in parallel, scattered in leaf order
+    std::vector<std::vector<std::vector<double>>> leaf_vals((size_t)L);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < L; ++c) {
-        double H[3];
-        for (int i = 0; i < 3; ++i) H[i] = (double)(hi(c, i) - lo(c, i));
-        for (int64_t k : leaf_pts[c]) {
-            const int64_t um1 = Uhi[3 * k + 1] - Ulo[3 * k + 1] + 1, um2 = Uhi[3 * k + 2] - Ulo[3 * k + 2] + 1;
-            for (int64_t y0 = lo(c, 0); y0 <= hi(c, 0); ++y0) {
-                const double f0 = H[0] > 0 ? 1.0 - std::fabs((double)(y0 - Pt[k * 3])) / H[0] : 1.0;
-                for (int64_t y1 = lo(c, 1); y1 <= hi(c, 1); ++y1) {
-                    const double f1 = H[1] > 0 ? 1.0 - std::fabs((double)(y1 - Pt[k * 3 + 1])) / H[1] : 1.0;
-                    double* row = &W[(size_t)(w_base[k] + ((y0 - Ulo[3 * k]) * um1 + (y1 - Ulo[3 * k + 1])) * um2)];
-                    for (int64_t y2 = lo(c, 2); y2 <= hi(c, 2); ++y2) {
-                        const double f2 =
-                            H[2] > 0 ? 1.0 - std::fabs((double)(y2 - Pt[k * 3 + 2])) / H[2] : 1.0;
-                        row[y2 - Ulo[3 * k + 2]] = f0 * f1 * f2;
+        const std::vector<int64_t>& lp = leaf_pts[c];
+        bool any = false;
+        for (int64_t k : lp) any = any || p.sel[(size_t)k];
+        if (!any) continue;
+        int live = 0;
+        for (int i = 0; i < 3; ++i) live += hi(c, i) > lo(c, i);
+        const int64_t n0 = hi(c, 0) - lo(c, 0) + 1, n1 = hi(c, 1) - lo(c, 1) + 1, n2 = hi(c, 2) - lo(c, 2) + 1;
+        std::vector<std::vector<double>>& vals = leaf_vals[(size_t)c];
+        vals.assign(lp.size(), std::vector<double>());
+        if ((int64_t)lp.size() == (int64_t)(1 << live)) {   // conforming leaf: trilinear hats
+            double H[3];
+            for (int i = 0; i < 3; ++i) H[i] = (double)(hi(c, i) - lo(c, i));
+            for (size_t j = 0; j < lp.size(); ++j) {
+                const int64_t k = lp[j];
+                std::vector<double>& V = vals[j];
+                V.resize((size_t)(n0 * n1 * n2));
+                for (int64_t y0 = 0; y0 < n0; ++y0) {
+                    const double f0 = H[0] > 0 ? 1.0 - std::fabs((double)(lo(c, 0) + y0 - Pt[k * 3])) / H[0] : 1.0;
+                    for (int64_t y1 = 0; y1 < n1; ++y1) {
+                        const double f1 =
+                            H[1] > 0 ? 1.0 - std::fabs((double)(lo(c, 1) + y1 - Pt[k * 3 + 1])) / H[1] : 1.0;
+                        for (int64_t y2 = 0; y2 < n2; ++y2) {
+                            const double f2 =
+                                H[2] > 0 ? 1.0 - std::fabs((double)(lo(c, 2) + y2 - Pt[k * 3 + 2])) / H[2] : 1.0;
+                            V[(size_t)((y0 * n1 + y1) * n2 + y2)] = f0 * f1 * f2;
+                        }
                     }
                 }
             }
+            continue;
         }
+        // hanging nodes: the facets as the smaller leaves' facets (Sec. 2.4)
+        IBox box;
+        for (int i = 0; i < 3; ++i) {
+            box.lo[i] = lo(c, i);
+            box.hi[i] = hi(c, i);
+        }
+        std::function<std::vector<IBox>(int, int)> parts = [&](int axis, int side) {
+            const int64_t v = side ? hi(c, axis) : lo(c, axis);
+            IBox f = box;
+            f.lo[axis] = f.hi[axis] = v;
+            std::vector<IBox> out;
+            for (int64_t e = 0; e < L; ++e) {
+                if (e == c || (side ? lo(e, axis) : hi(e, axis)) != v) continue;
+                IBox g;
+                bool ok = true;
+                for (int i = 0; i < 3; ++i) {
+                    g.lo[i] = std::max(f.lo[i], lo(e, i));
+                    g.hi[i] = std::min(f.hi[i], hi(e, i));
+                    if (i != axis && f.hi[i] > f.lo[i] && g.hi[i] <= g.lo[i]) ok = false;
+                }
+                g.lo[axis] = g.hi[axis] = v;
+                if (ok) out.push_back(g);
+            }
+            if (out.empty()) out.push_back(f);
+            return out;
+        };
+        std::vector<double> pv(lp.size());
+        for (size_t j = 0; j < lp.size(); ++j) {
+            std::fill(pv.begin(), pv.end(), 0.0);
+            pv[j] = 1.0;
+            harmonic_box(box, Pt, lp, pv, &parts, vals[j]);
+        }
+    }
+    for (int64_t c = 0; c < L; ++c) {
+        const std::vector<std::vector<double>>& vals = leaf_vals[(size_t)c];
+        if (vals.empty()) continue;
+        const int64_t n1 = hi(c, 1) - lo(c, 1) + 1, n2 = hi(c, 2) - lo(c, 2) + 1;
+        const std::vector<int64_t>& lp = leaf_pts[c];
+        for (size_t j = 0; j < lp.size(); ++j) {
+            const int64_t k = lp[j];
+            if (!p.sel[(size_t)k]) continue;
+            const int64_t um1 = Uhi[3 * k + 1] - Ulo[3 * k + 1] + 1, um2 = Uhi[3 * k + 2] - Ulo[3 * k + 2] + 1;
+            for (int64_t y0 = lo(c, 0); y0 <= hi(c, 0); ++y0)
+                for (int64_t y1 = lo(c, 1); y1 <= hi(c, 1); ++y1) {
+                    double* row = &W[(size_t)(w_base[k] + ((y0 - Ulo[3 * k]) * um1 + (y1 - Ulo[3 * k + 1])) * um2)];
+                    const double* src = &vals[j][(size_t)(((y0 - lo(c, 0)) * n1 + (y1 - lo(c, 1))) * n2)];
+                    for (int64_t y2 = lo(c, 2); y2 <= hi(c, 2); ++y2) row[y2 - Ulo[3 * k + 2]] = src[y2 - lo(c, 2)];
+                }
+        }
+        std::vector<std::vector<double>>().swap(leaf_vals[(size_t)c]);
     }
     p.wts = std::move(W);
     // ------------------------------------------- geometry of every patch

@@ -2,7 +2,7 @@
 import numpy as np
 
 from workloads import make_config, cosine_field
-from tests.tilings import hanging_2d, const_blur, workload_from, tensor
+from tests.tilings import hanging_2d, hanging_3d, const_blur, workload_from, tensor
 
 # Per-vector relative L2 bars against the FP64 oracle.
 TOL = {0: 1e-5, 1: 1e-12}     # PC_F32, PC_F64
@@ -40,8 +40,9 @@ def small_cases():
 
 def small_cases_3d():
     """3-D (name, workload) pairs: a rectangular box with per-axis widths
-    varying along their own axes, and a cube with cosine width fields (the
-    3-D workload's recipe at 24^3, 4 x 4 x 4 points)."""
+    varying along their own axes, a cube with cosine width fields (the 3-D
+    workload's recipe at 24^3, 4 x 4 x 4 points) and a 17^3 tiling refined
+    towards one corner (hanging nodes, broken facets)."""
     lo, hi = tensor((12, 17, 23), 3)
     x0, x1, x2 = np.meshgrid(np.arange(12), np.arange(17), np.arange(23), indexing="ij")
     s0 = 0.7 + 0.8 * x0 / 11
@@ -53,4 +54,10 @@ def small_cases_3d():
     f = [cosine_field((n, n, n), 0.8, 3.0, 2, 2, rng=rng)[0] for _ in range(3)]
     lo, hi = tensor((n, n, n), 4)
     cases.append(("cube24", workload_from(np.stack(f), lo, hi)))
+    # hanging nodes: 17^3 refined towards one corner (broken facets)
+    m = 17
+    x0, x1, x2 = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    lo, hi = hanging_3d(m, min_width=4)
+    sig = np.stack([0.7 + 0.5 * x0 / 16, 0.9 + 0.3 * np.cos(x1 / 5.0), 0.8 + 0.4 * x2 / 16])
+    cases.append(("hang3d", workload_from(sig, lo, hi)))
     return cases

@@ -228,7 +228,7 @@ def test_large_pieces_blur2048_start_grid(lib):
 
 
 # ------------------------------------------------------------------- 3-D
-@pytest.mark.parametrize("idx", range(2))
+@pytest.mark.parametrize("idx", range(3))
 def test_small_cases_3d_parity(lib, idx):
     from tests.libhelpers import small_cases_3d
     name, w = small_cases_3d()[idx]
@@ -340,7 +340,7 @@ def test_full_size_blur3d_128(lib, dtype):
 
 
 # ------------------------------------------------------------ matrix entries
-@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24"])
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24", "hang3d"])
 def test_entries_match_oracle(lib, name):
     """pc_entries (Sec. 3.1) against the oracle's entry formula, FP64 and
     FP32; out-of-range pairs give NaN; entries agree with applies to unit

@@ -71,13 +71,11 @@ def test_create_rejects_bad_input():
     assert st == PC_ERR_ARG, msg
     st, msg = raw_create(**a, flags=1 << 5)
     assert st == PC_ERR_ARG, msg
-    # 3-D tiling with hanging nodes (one octant refined): trilinear weights
-    # need a conforming tiling
-    lo3, hi3 = refine((9, 9, 9), lambda l, h: max(b - a for a, b in zip(l, h)) >= 8 or
-                      (max(b - a for a, b in zip(l, h)) >= 4 and max(l) == 0))
-    x = np.full((3, 9, 9, 9), 1.2)
+    # a 3-D patch beyond the FFT lengths of the kernels (no pieces in 3-D)
+    x = np.full((3, 300, 6, 6), 1.2)
+    lo3, hi3 = np.array([[0, 0, 0]]), np.array([[299, 5, 5]])
     st, msg = raw_create(**_args(workload_from(x, lo3, hi3)))
-    assert st == PC_ERR_UNSUPPORTED and "hanging" in msg, msg
+    assert st == PC_ERR_UNSUPPORTED and "FFT" in msg, msg
 
 
 # ------------------------------------------------------------- CPU emulation
@@ -117,7 +115,7 @@ def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None):
     return out
 
 
-@pytest.mark.parametrize("idx", range(8))
+@pytest.mark.parametrize("idx", range(9))
 def test_emulated_kernels_match_oracle(idx):
     name, w = (small_cases() + small_cases_3d())[idx]
     lib = _emu_lib()
@@ -134,7 +132,7 @@ def test_emulated_kernels_match_oracle(idx):
                 assert e.max() <= TOL[dtype], (name, flags, dtype, adj, e)
 
 
-@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24"])
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "cube24", "hang3d"])
 def test_emulated_term_subsets_match_oracle(name):
     """Operators restricted to a subset of the terms (pc_create_patches) against
     the oracle's sum over the same terms; the empty subset gives zero."""
@@ -191,7 +189,7 @@ def _emu_entries(lib, h, ys, xs):
     return out
 
 
-@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect3d"])
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect3d", "hang3d"])
 def test_emulated_entries_match_oracle(name):
     """Matrix entries (Sec. 3.1) from the library's entry function against
     the oracle's entry formula: random pairs with y near x (inside the kernel
