@@ -27,6 +27,9 @@ def _load():
         lib.blur_adjoint3.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
                                       ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int, P]
         lib.blur_adjoint3.restype = ctypes.c_int
+        lib.blur_forward.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int, P]
+        lib.blur_forward.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -81,4 +84,48 @@ class GpuBlurAdjoint:
                       torch.cuda.current_stream().cuda_stream)
         if rc != 0:
             raise RuntimeError("blur_adjoint launch failed")
+        return OUT
+
+
+class GpuBlur:
+    """Exact forward blur A (2-D or 1-D BlurOperator) on the GPU."""
+
+    def __init__(self, op, dtype=torch.float32, device="cuda"):
+        if op.d == 3:
+            raise NotImplementedError("the exact forward blur is provided for 1-D and 2-D operators")
+        if op.d == 1:
+            s0, s1 = np.ones(op.shape), op.sig[0]
+            r0, r1 = np.zeros(op.shape, dtype=np.int32), op.radius[0]
+            self.n0, self.n1 = 1, int(op.shape[0])
+        else:
+            s0, s1 = op.sig[0], op.sig[1]
+            r0, r1 = op.radius[0], op.radius[1]
+            self.n0, self.n1 = int(op.shape[0]), int(op.shape[1])
+        self.N = self.n0 * self.n1
+        # 1 / Z(x): the Gaussian summed over the full radius box (separable)
+        def axis_sum(sv, rv):
+            sv, rv = np.ravel(sv).astype(np.float64), np.ravel(rv)
+            tot = np.ones_like(sv)
+            for a in range(1, int(rv.max()) + 1):
+                tot += np.where(a <= rv, 2.0 * np.exp(-a * a / (2.0 * sv * sv)), 0.0)
+            return tot
+        z = axis_sum(s0, r0) * axis_sum(s1, r1)
+        self.rmax0, self.rmax1 = int(np.max(r0)), int(np.max(r1))
+        to = lambda a: torch.from_numpy(np.ascontiguousarray(a).ravel()).to(device=device, dtype=dtype)
+        self.s0, self.s1, self.inv_z = to(s0), to(s1), to(1.0 / z)
+        self.r0 = torch.from_numpy(np.ascontiguousarray(r0, dtype=np.int32).ravel()).to(device)
+        self.r1 = torch.from_numpy(np.ascontiguousarray(r1, dtype=np.int32).ravel()).to(device)
+        self.code = 1 if dtype == torch.float64 else 0
+        self.dtype = dtype
+
+    def __call__(self, U, OUT=None):
+        U = U.reshape(-1, self.N)
+        if OUT is None:
+            OUT = torch.empty_like(U)
+        rc = _load().blur_forward(self.code, self.s0.data_ptr(), self.s1.data_ptr(), self.r0.data_ptr(),
+                                  self.r1.data_ptr(), self.inv_z.data_ptr(), self.n0, self.n1, self.rmax0,
+                                  self.rmax1, U.data_ptr(), U.stride(0), OUT.data_ptr(), OUT.stride(0), U.shape[0],
+                                  torch.cuda.current_stream().cuda_stream)
+        if rc != 0:
+            raise RuntimeError("blur_forward launch failed")
         return OUT

@@ -57,6 +57,41 @@ __global__ __launch_bounds__(kThreads) void blur_adjoint_kernel(const T* s0, con
     }
 }
 
+// Forward blur, 2-D: (A u)[y] = sum_x A[y, x] u[x].  One thread per y
+// gathers over the x with |y_i - x_i| <= rmax_i (the largest radii) and
+// keeps those with |y_i - x_i| <= R_i(x); inv_z[x] = 1 / Z(x) comes from the
+// host.
+template <class T>
+__global__ __launch_bounds__(kThreads) void blur_forward_kernel(const T* s0, const T* s1, const int32_t* r0,
+                                                                const int32_t* r1, const T* inv_z, int n0, int n1,
+                                                                int rmax0, int rmax1, const T* in, int64_t ldin,
+                                                                T* out, int64_t ldout, int B) {
+    const int64_t y = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (y >= (int64_t)n0 * n1) return;
+    const int y0 = (int)(y / n1), y1 = (int)(y % n1);
+    for (int v0 = 0; v0 < B; v0 += kVec) {
+        T acc[kVec];
+        for (int v = 0; v < kVec; ++v) acc[v] = T(0);
+        for (int x0 = y0 - rmax0; x0 <= y0 + rmax0; ++x0) {
+            if (x0 < 0 || x0 >= n0) continue;
+            const int d0 = y0 - x0;
+            for (int x1 = y1 - rmax1; x1 <= y1 + rmax1; ++x1) {
+                if (x1 < 0 || x1 >= n1) continue;
+                const int64_t x = (int64_t)x0 * n1 + x1;
+                const int d1 = y1 - x1;
+                if (abs(d0) > r0[x] || abs(d1) > r1[x]) continue;
+                const T sa = s0[x], sb = s1[x];
+                const T w = exp(-(T)(d0 * d0) / (2 * sa * sa) - (T)(d1 * d1) / (2 * sb * sb)) * inv_z[x];
+#pragma unroll
+                for (int v = 0; v < kVec; ++v)
+                    if (v0 + v < B) acc[v] += w * in[(int64_t)(v0 + v) * ldin + x];
+            }
+        }
+        for (int v = 0; v < kVec; ++v)
+            if (v0 + v < B) out[(int64_t)(v0 + v) * ldout + y] = acc[v];
+    }
+}
+
 // 3-D: one thread per x; the axis-2 Gaussian factors come from the exact
 // recurrence g(z+1) = g(z) r(z), r(z+1) = r(z) exp(-1/s^2) in FP64 (no exp
 // per tap), the axis-0 and axis-1 factors from exp.
@@ -128,6 +163,26 @@ int blur_adjoint(int dtype, const void* s0, const void* s1, const int32_t* r0, c
         hipLaunchKernelGGL(blur_adjoint_kernel<float>, dim3(grid), dim3(kThreads), 0, stream,
                            static_cast<const float*>(s0), static_cast<const float*>(s1), r0, r1, n0, n1,
                            static_cast<const float*>(in), ldin, static_cast<float*>(out), ldout, B);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+// Forward blur, 2-D (d = 1 as one row): out = A in.  inv_z: 1 / Z(x) per x
+// (device, dtype); rmax0, rmax1: the largest radii along each axis.
+int blur_forward(int dtype, const void* s0, const void* s1, const int32_t* r0, const int32_t* r1, const void* inv_z,
+                 int n0, int n1, int rmax0, int rmax1, const void* in, int64_t ldin, void* out, int64_t ldout, int B,
+                 hipStream_t stream) {
+    const int64_t N = (int64_t)n0 * n1;
+    const unsigned grid = (unsigned)((N + kThreads - 1) / kThreads);
+    if (dtype == 1)
+        hipLaunchKernelGGL(blur_forward_kernel<double>, dim3(grid), dim3(kThreads), 0, stream,
+                           static_cast<const double*>(s0), static_cast<const double*>(s1), r0, r1,
+                           static_cast<const double*>(inv_z), n0, n1, rmax0, rmax1, static_cast<const double*>(in),
+                           ldin, static_cast<double*>(out), ldout, B);
+    else
+        hipLaunchKernelGGL(blur_forward_kernel<float>, dim3(grid), dim3(kThreads), 0, stream,
+                           static_cast<const float*>(s0), static_cast<const float*>(s1), r0, r1,
+                           static_cast<const float*>(inv_z), n0, n1, rmax0, rmax1, static_cast<const float*>(in),
+                           ldin, static_cast<float*>(out), ldout, B);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
