@@ -186,9 +186,8 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
  * Only the work items whose gather box meets S (adjoint: whose output box
  * meets S) and whose written box meets T run, both boxes clipped, so the
  * cost follows the paper's O(r_S sigma log sigma) (adjoint: r_T).  Results
- * equal the restriction to T of the full apply to U_S extended by zero, to
- * rounding.  d = 3 gives PC_ERR_UNSUPPORTED.  Each call copies its small
- * tables to the device synchronously. */
+ * equal the restriction to T of the full apply to U_S extended by zero.
+ * Each call copies its small tables to the device synchronously. */
 pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64_t* thi,
                          const int64_t* slo, const int64_t* shi, int64_t B,
                          const void* U, int64_t ldu, void* OUT, int64_t ldo, hipStream_t s);

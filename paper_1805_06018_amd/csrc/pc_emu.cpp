@@ -70,35 +70,38 @@ void reduce_all(const pc::Plan& P, bool adj, int64_t B, const std::vector<T>& sl
 
 // 3-D: the three kernels of pc_phases3.h, one simulated block after another,
 // on one scratch area holding every item and vector (the layout of a launch
-// over all items with B vectors).
+// over all items with B vectors).  items/per/tiles/cboxes: the operator's or
+// a block apply's; in_pitch, in_prow: gather view; out_cols: reduction pitch.
 template <class T>
-void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
+void emu_3d(const pc::Plan& P, const std::vector<pc::Item3>& items, int64_t per, const std::vector<pc::Tile>& tiles,
+            const std::vector<pc::Box>& cboxes, int64_t n_in, int64_t in_pitch, int64_t in_prow, int64_t n_out,
+            int out_cols, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
     using C = pc::cx<T>;
-    const int64_t N = P.N;
     std::vector<T> spec(P.spec.begin(), P.spec.end());
     std::vector<T> wts(P.wts.begin(), P.wts.end());
     std::vector<T> tw(P.tw.begin(), P.tw.end());
     const C* specc = reinterpret_cast<const C*>(spec.data());
     const C* twc = reinterpret_cast<const C*>(tw.data());
-    const int64_t per = adj ? P.slot_adj : P.slot_fwd;
-    std::vector<T> in((size_t)(B * N));
-    for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * N)], U + b * ldu, sizeof(T) * (size_t)N);
-    std::vector<T> slots((size_t)(B * per), T(0));
-    std::vector<C> scratch((size_t)(P.scratch_per_vec * B), C{T(1e30), T(1e30)});
+    std::vector<T> in((size_t)(B * n_in));
+    for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * n_in)], U + b * ldu, sizeof(T) * (size_t)n_in);
+    std::vector<T> slots((size_t)std::max<int64_t>(B * per, 1), T(0));
+    int64_t sc_total = 0;
+    for (const pc::Item3& I : items) sc_total = std::max(sc_total, I.scratch_off + I.nz * pc::plane_elems(I));
+    std::vector<C> scratch((size_t)std::max<int64_t>(sc_total * B, 1), C{T(1e30), T(1e30)});
     const int NT = pc::kPlaneThreads;
     const int COLS = pc::axis_cols(P.dtype), LDA = pc::axis_ld(COLS);
-    const int64_t pitch = P.cols, plane_pitch = (int64_t)P.prow * P.cols;
-    for (const pc::Item3& I : P.items3) {
+    const int64_t plane_pitch = in_prow * in_pitch;
+    for (const pc::Item3& I : items) {
         const pc::Planes pl = pc::planes_of(I, adj);
         const int64_t pe = pc::plane_elems(I);
         for (int64_t b = 0; b < B; ++b) {
-            const T* iv = &in[(size_t)(b * N)];
+            const T* iv = &in[(size_t)(b * n_in)];
             T* sv = &slots[(size_t)(b * per)];
             C* sc = pc::item_scratch(scratch.data(), 0, I, (int)B, (int)b);
             for (int q = 0; q < pl.s_n; ++q) {
                 std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
                 const pc::Ctx<T> c =
-                    pc::plane_ctx_gather<T>(I, adj, q, iv, sv, wts.data(), specc, twc, pitch, plane_pitch);
+                    pc::plane_ctx_gather<T>(I, adj, q, iv, sv, wts.data(), specc, twc, in_pitch, plane_pitch);
                 for (int t = 0; t < NT; ++t) pc::phA0(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phA(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phB(c, buf.data(), t, NT);
@@ -119,7 +122,7 @@ void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ld
             }
             for (int q = 0; q < pl.d_n; ++q) {
                 std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
-                const pc::Ctx<T> c = pc::plane_ctx_write<T>(I, adj, q, iv, sv, wts.data(), specc, twc, pitch);
+                const pc::Ctx<T> c = pc::plane_ctx_write<T>(I, adj, q, iv, sv, wts.data(), specc, twc, in_pitch);
                 for (int t = 0; t < NT; ++t) pc::plane_load(c, buf.data(), sc + (int64_t)(pl.d_off + q) * pe, t, NT);
                 for (int t = 0; t < NT; ++t) pc::phD_inv(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phE(c, buf.data(), t, NT);
@@ -129,7 +132,19 @@ void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ld
             }
         }
     }
-    reduce_all(P, adj, B, slots, per, OUT, ldo);
+    std::vector<T> out((size_t)(B * n_out), T(0));
+    for (int64_t b = 0; b < B; ++b)
+        for (const pc::Tile& t : tiles)
+            for (int col = 0; col < pc::kReduceCols; ++col)
+                pc::reduce_tile<T>(t, col, cboxes.data(), &slots[(size_t)(b * per)], &out[(size_t)(b * n_out)],
+                                   out_cols);
+    for (int64_t b = 0; b < B; ++b) std::memcpy(OUT + b * ldo, &out[(size_t)(b * n_out)], sizeof(T) * (size_t)n_out);
+}
+
+template <class T>
+void emu_apply_3d(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
+    emu_3d<T>(P, P.items3, adj ? P.slot_adj : P.slot_fwd, adj ? P.tiles_adj : P.tiles_fwd,
+              adj ? P.cboxes_adj : P.cboxes_fwd, P.N, P.cols, P.prow, P.N, P.cols, adj, B, U, ldu, OUT, ldo);
 }
 
 }  // namespace
@@ -223,7 +238,12 @@ int pc_emu_apply_block(pc_emu* e, int adj, const int64_t* tlo, const int64_t* th
     using C = pc::cx<double>;
     const C* spec = reinterpret_cast<const C*>(P.spec.data());
     const C* tw = reinterpret_cast<const C*>(P.tw.data());
-    const int64_t nS = (int64_t)bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
+    const int64_t nS = (int64_t)bp.s_planes * bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
+    if (P.d == 3) {
+        emu_3d<double>(P, bp.items3, bp.per, bp.tiles, bp.cboxes, nS, bp.s_cols, bp.s_rows, nT, bp.t_cols, adj != 0,
+                       B, U, ldu, OUT, ldo);
+        return 0;
+    }
     for (int64_t b = 0; b < B; ++b) {
         std::vector<double> in(U + b * ldu, U + b * ldu + nS);
         std::vector<double> slots((size_t)std::max<int64_t>(bp.per, 1), 0.0);

@@ -185,11 +185,12 @@ pc_status ensure_aux(pc_op* op) {
 
 // 3-D: vector chunks sized by the staging buffer; within a chunk, contiguous
 // item groups sized by the scratch buffer each run the three kernels of
-// pc_phases3.h; one reduction per chunk.
-pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
-                       hipStream_t s, bool acc, double alpha) {
+// pc_phases3.h; one reduction per chunk.  items: host copy of the items Dc
+// points to (the operator's, or a block apply's); Dr: the reduction tables.
+pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPlan& Dc, const pc::DevPlan& Dr,
+                 int64_t per, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                 hipStream_t s, bool acc, double alpha) {
     const pc::Plan& P = op->plan;
-    const int64_t per = adj ? P.slot_adj : P.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     const size_t cx_bytes = 2 * op->esz;
     int64_t chunk = 1;
@@ -199,11 +200,11 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
         chunk = op->tune_chunk > 0 ? std::min<int64_t>(op->tune_chunk, B) : std::min<int64_t>(cap, B);
     }
     const size_t scap = op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
-    const int n = (int)P.items3.size();
+    const int n = (int)items.size();
     const int cols = pc::axis_cols(P.dtype);
-    auto scratch_of = [&](int i) { return P.items3[(size_t)i].scratch_off; };
+    auto scratch_of = [&](int i) { return items[(size_t)i].scratch_off; };
     auto scratch_end = [&](int i) {
-        const pc::Item3& I = P.items3[(size_t)i];
+        const pc::Item3& I = items[(size_t)i];
         return I.scratch_off + (int64_t)I.nz * I.p.n0 * (I.p.m + 1);
     };
     // item groups for chunk vectors (smaller chunks reuse them)
@@ -219,7 +220,7 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
         L.item_hi = j;
         L.scratch_base = scratch_of(i);
         for (int k = i; k < j; ++k) {
-            const pc::Item3& I = P.items3[(size_t)k];
+            const pc::Item3& I = items[(size_t)k];
             const pc::Planes pl = pc::planes_of(I, adj);
             L.max_gather = std::max(L.max_gather, pl.s_n);
             L.max_write = std::max(L.max_write, pl.d_n);
@@ -250,16 +251,22 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
             L.slot_stride = per;
             L.scratch = op->scratch;
             prof_begin(op, s, &ev);
-            e = pc::launch_conv3(op->dev, L, s);
+            e = pc::launch_conv3(Dc, L, s);
             if (e != hipSuccess) return hip_fail(e, "3-D conv launch");
             prof_end(op, s, ev, 0, g == 0 ? nb : 0);
         }
         prof_begin(op, s, &ev);
-        e = pc::launch_reduce(op->dev, adj, nb, op->slots, per, out, ldo, s, acc, alpha);
+        e = pc::launch_reduce(Dr, adj, nb, op->slots, per, out, ldo, s, acc, alpha);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
         prof_end(op, s, ev, 1, nb);
     }
     return PC_OK;
+}
+
+pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                       hipStream_t s, bool acc, double alpha) {
+    const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
+    return run_3d(op, op->plan.items3, op->dev, op->dev, per, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
 }
 
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
@@ -571,15 +578,16 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     std::string err;
     st = pc::build_block(op->plan, adjoint != 0, tlo, thi, slo, shi, bp, err);
     if (st != PC_OK) return fail(st, err);
-    const int64_t nS = (int64_t)bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
+    const int64_t nS = (int64_t)bp.s_planes * bp.s_rows * bp.s_cols, nT = (int64_t)bp.t_rows * bp.t_cols;
     if (B == 0) return PC_OK;
     if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
     if (ldu < nS || ldo < nT) return fail(PC_ERR_ARG, "leading dimension smaller than the block box");
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
     // per-call tables: items | tiles | contributor boxes
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t bi = al(bp.items.size() * sizeof(pc::Item)), bt = al(bp.tiles.size() * sizeof(pc::Tile)),
-                 bc = al(bp.cboxes.size() * sizeof(pc::Box));
+    const bool d3 = op->plan.d == 3;
+    const size_t bi = d3 ? al(bp.items3.size() * sizeof(pc::Item3)) : al(bp.items.size() * sizeof(pc::Item)),
+                 bt = al(bp.tiles.size() * sizeof(pc::Tile)), bc = al(bp.cboxes.size() * sizeof(pc::Box));
     hipError_t e;
     if (op->blk_done) {
         e = hipEventSynchronize(op->blk_done);   // the previous block call may still read the tables
@@ -592,6 +600,8 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     if (st != PC_OK) return st;
     char* base = static_cast<char*>(op->blk);
     if (!bp.items.empty()) e = hipMemcpy(base, bp.items.data(), bp.items.size() * sizeof(pc::Item), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !bp.items3.empty())
+        e = hipMemcpy(base, bp.items3.data(), bp.items3.size() * sizeof(pc::Item3), hipMemcpyHostToDevice);
     if (e == hipSuccess && !bp.tiles.empty())
         e = hipMemcpy(base + bi, bp.tiles.data(), bp.tiles.size() * sizeof(pc::Tile), hipMemcpyHostToDevice);
     if (e == hipSuccess && !bp.cboxes.empty())
@@ -607,6 +617,16 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     Dr.cboxes_fwd = Dr.cboxes_adj = reinterpret_cast<const pc::Box*>(base + bi + bt);
     Dr.rows = bp.t_rows;
     Dr.cols = bp.t_cols;
+    if (d3) {
+        Dc.items3 = reinterpret_cast<const pc::Item3*>(base);
+        Dc.n_items3 = (int)bp.items3.size();
+        Dc.prow = bp.s_rows;           // plane pitch of S = s_rows * s_cols
+        st = run_3d(op, bp.items3, Dc, Dr, bp.per, adjoint != 0, false, B, U, ldu, OUT, ldo, s, false, 1.0);
+        if (st != PC_OK) return st;
+        e = hipEventRecord(op->blk_done, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        return PC_OK;
+    }
     const size_t per_bytes = (size_t)std::max<int64_t>(bp.per, 1) * op->esz;
     const int64_t chunk = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t)(kSlotCapBytes / per_bytes)));
     st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");

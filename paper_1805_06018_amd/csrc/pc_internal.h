@@ -56,7 +56,7 @@ struct Item3 {
     int32_t nz, az, bz, twz;                 // axis-0 FFT length, radices, twiddle table
     int32_t gz, in_offz, in_nz, out_nz;      // axis-0 origin, input box offset/extent, output extent
     int32_t w_plane;                         // weight table plane stride (m1 * m2)
-    int32_t pad_;
+    int32_t out_offz;                        // axis-0 FFT offset of the output box (0 except in block applies)
     int64_t scratch_off;                     // complex elements, per vector
 };
 

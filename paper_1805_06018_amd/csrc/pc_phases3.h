@@ -25,8 +25,8 @@ struct Planes {
 };
 
 __host__ __device__ inline Planes planes_of(const Item3& I, bool adj) {
-    if (!adj) return Planes{I.in_offz, I.in_nz, 0, I.out_nz};
-    return Planes{0, I.out_nz, I.in_offz, I.in_nz};
+    if (!adj) return Planes{I.in_offz, I.in_nz, I.out_offz, I.out_nz};
+    return Planes{I.out_offz, I.out_nz, I.in_offz, I.in_nz};
 }
 
 __host__ __device__ inline int64_t plane_elems(const Item3& I) { return (int64_t)I.p.n0 * (I.p.m + 1); }

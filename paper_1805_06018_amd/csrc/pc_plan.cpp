@@ -259,7 +259,7 @@ void leaf_weights_2d(const int64_t* lo, const int64_t* hi, const std::vector<int
 // Reduction tiles of the rows x cols view and, for every tile, the staging
 // boxes that overlap it in ascending box order (boxes are listed in ascending
 // item order, so every tile sums its contributors in ascending patch order).
-static bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<Tile>& tiles,
+bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<Tile>& tiles,
                  std::vector<int32_t>& contrib, std::string& err) {
     const int ntr = (rows + kReduceRows - 1) / kReduceRows, ntc = (cols + kReduceCols - 1) / kReduceCols;
     std::vector<std::vector<int32_t>> per((size_t)ntr * ntc);
@@ -311,14 +311,11 @@ bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::stri
 
 pc_status build_block(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
                       const int64_t* shi, BlockPlan& B, std::string& err) {
-    if (P.d == 3) {
-        err = "block applies of 3-D operators are not implemented";
-        return PC_ERR_UNSUPPORTED;
-    }
     if (!tlo || !thi || !slo || !shi) {
         err = "null box pointer";
         return PC_ERR_ARG;
     }
+    if (P.d == 3) return build_block3(P, adjoint, tlo, thi, slo, shi, B, err);
     const int d = P.d;
     for (int i = 0; i < d; ++i)
         if (tlo[i] < 0 || thi[i] >= P.shape[i] || tlo[i] > thi[i] || slo[i] < 0 || shi[i] >= P.shape[i] ||

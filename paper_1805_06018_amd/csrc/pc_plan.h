@@ -102,6 +102,10 @@ struct SineBasis {
     std::vector<double> S, lam;
     explicit SineBasis(int n_);
 };
+// reduction tiles of a rows x cols view with, per tile, the boxes meeting it
+// in ascending box order
+bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<Tile>& tiles,
+                 std::vector<int32_t>& contrib, std::string& err);
 // reduction tiles and contributor boxes of both directions from the
 // per-item staging boxes (ascending item order)
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);
@@ -112,17 +116,22 @@ bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::stri
 // convolution is exact.  Gather coordinates are S-local, reduction tiles
 // T-local.
 struct BlockPlan {
-    std::vector<Item> items;
+    std::vector<Item> items;         // d <= 2
+    std::vector<Item3> items3;       // d = 3 (scratch offsets local to the call)
     std::vector<Tile> tiles;
     std::vector<Box> cboxes;
     int64_t per = 0;                 // staging elements per vector
-    int t_rows = 0, t_cols = 0;      // T in the 2-D view
-    int s_rows = 0, s_cols = 0;      // S in the 2-D view
+    int t_rows = 0, t_cols = 0;      // T in the reduction view (d = 3: rows = T0 * T1)
+    int s_rows = 0, s_cols = 0;      // S in the gather view (d = 3: rows per plane)
+    int s_planes = 1, t_prow = 1;    // d = 3: planes of S, rows per plane of T
 };
 pc_status build_block(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
                       const int64_t* shi, BlockPlan& B, std::string& err);
 
 // 3-D operators (called by build_plan after the argument checks)
 pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err);
+// 3-D block plan (called by build_block)
+pc_status build_block3(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                       const int64_t* shi, BlockPlan& B, std::string& err);
 
 }  // namespace pc

@@ -588,3 +588,93 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
 }
 
 }  // namespace pc
+
+namespace pc {
+
+pc_status build_block3(const Plan& P, bool adjoint, const int64_t* tlo, const int64_t* thi, const int64_t* slo,
+                       const int64_t* shi, BlockPlan& B, std::string& err) {
+    for (int i = 0; i < 3; ++i)
+        if (tlo[i] < 0 || thi[i] >= P.shape[i] || tlo[i] > thi[i] || slo[i] < 0 || shi[i] >= P.shape[i] ||
+            slo[i] > shi[i]) {
+            err = "block boxes must be non-empty and inside Omega";
+            return PC_ERR_ARG;
+        }
+    int64_t Tn[3], Sn[3];
+    for (int i = 0; i < 3; ++i) {
+        Tn[i] = thi[i] - tlo[i] + 1;
+        Sn[i] = shi[i] - slo[i] + 1;
+    }
+    if (Tn[0] * Tn[1] > INT32_MAX || Sn[1] * Sn[2] > INT32_MAX) {
+        err = "block boxes too large";
+        return PC_ERR_ARG;
+    }
+    B = BlockPlan();
+    B.t_rows = (int)(Tn[0] * Tn[1]);
+    B.t_cols = (int)Tn[2];
+    B.t_prow = (int)Tn[1];
+    B.s_planes = (int)Sn[0];
+    B.s_rows = (int)Sn[1];
+    B.s_cols = (int)Sn[2];
+    auto clip = [](int64_t alo, int64_t an, int64_t blo, int64_t bn, int64_t& lo, int64_t& n) {
+        lo = std::max(alo, blo);
+        n = std::min(alo + an, blo + bn) - lo;
+        return n > 0;
+    };
+    std::vector<Box> boxes;
+    int64_t scratch = 0;
+    for (const Item3& I : P.items3) {
+        const Item& q = I.p;
+        // input box and output box in Omega coordinates (axis 0, 1, 2)
+        const int64_t Ilo[3] = {I.gz + I.in_offz, q.g0 + q.in_off0, q.g1 + q.in_off1};
+        const int64_t In[3] = {I.in_nz, q.in_n0, q.in_n1};
+        const int64_t Olo[3] = {I.gz, q.g0, q.g1};
+        const int64_t On[3] = {I.out_nz, q.out_n0, q.out_n1};
+        const int64_t* glo = adjoint ? Olo : Ilo;
+        const int64_t* gn = adjoint ? On : In;
+        const int64_t* wlo = adjoint ? Ilo : Olo;
+        const int64_t* wn = adjoint ? In : On;
+        int64_t Gl[3], Gn[3], Wl[3], Wn[3];
+        bool ok = true;
+        for (int i = 0; i < 3 && ok; ++i)
+            ok = clip(glo[i], gn[i], slo[i], Sn[i], Gl[i], Gn[i]) && clip(wlo[i], wn[i], tlo[i], Tn[i], Wl[i], Wn[i]);
+        if (!ok) continue;
+        Item3 c = I;
+        Item& cp = c.p;
+        const int64_t* Al = adjoint ? Wl : Gl;   // the clipped input (weighted) box
+        const int64_t* An = adjoint ? Wn : Gn;
+        const int64_t* Bl = adjoint ? Gl : Wl;   // the clipped output box
+        const int64_t* Bn = adjoint ? Gn : Wn;
+        c.in_offz = (int32_t)(Al[0] - I.gz);
+        c.in_nz = (int32_t)An[0];
+        cp.in_off0 = (int32_t)(Al[1] - q.g0);
+        cp.in_n0 = (int32_t)An[1];
+        cp.in_off1 = (int32_t)(Al[2] - q.g1);
+        cp.in_n1 = (int32_t)An[2];
+        cp.w_off = q.w_off + (Al[0] - Ilo[0]) * I.w_plane + (Al[1] - Ilo[1]) * q.w_ld + (Al[2] - Ilo[2]);
+        c.out_offz = (int32_t)(Bl[0] - I.gz);
+        c.out_nz = (int32_t)Bn[0];
+        cp.out_off0 = (int32_t)(Bl[1] - q.g0);
+        cp.out_n0 = (int32_t)Bn[1];
+        cp.out_off1 = (int32_t)(Bl[2] - q.g1);
+        cp.out_n1 = (int32_t)Bn[2];
+        c.gz = (int32_t)(I.gz - slo[0]);        // gather in S-local coordinates
+        cp.g0 = (int32_t)(q.g0 - slo[1]);
+        cp.g1 = (int32_t)(q.g1 - slo[2]);
+        cp.slot_fwd = cp.slot_adj = B.per;
+        c.scratch_off = scratch;
+        scratch += (int64_t)I.nz * q.n0 * (q.m + 1);
+        const int64_t pa = Wn[1] * Wn[2];
+        for (int64_t z = 0; z < Wn[0]; ++z)
+            boxes.push_back(Box{(int32_t)((Wl[0] - tlo[0] + z) * Tn[1] + (Wl[1] - tlo[1])), (int32_t)(Wl[2] - tlo[2]),
+                                (int32_t)Wn[1], (int32_t)Wn[2], B.per + z * pa});
+        B.per += Wn[0] * pa;
+        B.items3.push_back(c);
+    }
+    std::vector<int32_t> contrib;
+    if (!build_tiles(boxes, B.t_rows, B.t_cols, B.tiles, contrib, err)) return PC_ERR_UNSUPPORTED;
+    B.cboxes.resize(contrib.size());
+    for (size_t i = 0; i < contrib.size(); ++i) B.cboxes[i] = boxes[(size_t)contrib[i]];
+    return PC_OK;
+}
+
+}  // namespace pc

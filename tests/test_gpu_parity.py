@@ -428,3 +428,35 @@ def test_block_apply_equals_restricted_full_apply(lib, dtype):
     op0.apply_block(t_box, s_box, US, got)
     ref = ora.apply(ext).reshape(64, 64)[5:41, 10:64].ravel()
     assert np.abs(got.cpu().numpy()[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["cube24", "hang3d"])
+def test_block_apply_3d_equals_restricted_full_apply(lib, name):
+    from tests.libhelpers import small_cases_3d
+    w = dict(small_cases_3d())[name]
+    n = np.array(w.shape)
+    rng = np.random.default_rng(43)
+    pairs = [((np.zeros(3, int), n - 1), (np.zeros(3, int), n - 1)),
+             ((np.array([2, 3, 1]), np.array([12, 15, 9])), (np.array([5, 0, 4]), np.array([14, 10, 16]))),
+             ((np.array([0, 0, 0]), np.array([4, 4, 4])), (n - 5, n - 1))]
+    for dtype in (lib.PC_F32, lib.PC_F64):
+        tdt, ndt = _dt(dtype)
+        op = lib.PcOperator.from_workload(w, dtype=dtype)
+        for t_box, s_box in pairs:
+            full = torch.from_numpy(rng.standard_normal((3, w.N)).astype(ndt)).cuda()
+            sl = (slice(None),) + tuple(slice(int(a), int(b) + 1) for a, b in zip(*s_box))
+            ext = torch.zeros_like(full).reshape((3,) + tuple(w.shape))
+            ext[sl] = full.reshape((3,) + tuple(w.shape))[sl]
+            ext = ext.reshape(3, -1)
+            US = full.reshape((3,) + tuple(w.shape))[sl].reshape(3, -1).contiguous()
+            tl = (slice(None),) + tuple(slice(int(a), int(b) + 1) for a, b in zip(*t_box))
+            nT = int(np.prod(t_box[1] - t_box[0] + 1))
+            for adj in (False, True):
+                ref_full = torch.zeros_like(full)
+                (op.apply_adjoint_batch if adj else op.apply_batch)(ext, ref_full)
+                got = torch.full((3, nT), float("nan"), dtype=tdt, device="cuda")
+                op.apply_block(t_box, s_box, US, got, adjoint=adj)
+                torch.cuda.synchronize()
+                ref = ref_full.reshape((3,) + tuple(w.shape))[tl].reshape(3, -1)
+                assert torch.equal(got, ref), (name, dtype, adj, t_box, s_box)
+        op.close()

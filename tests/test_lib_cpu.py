@@ -248,12 +248,12 @@ def _emu_block(lib, h, adj, t_box, s_box, US):
     return rc, out
 
 
-@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect45x301"])
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "1d", "rect45x301", "rect3d", "hang3d"])
 def test_emulated_block_apply_matches_oracle(name):
     """Block applies (Sec. 3.3): A~[T, S] u_S and A~*[T, S] v_S equal the
     oracle's full apply of the zero-extended vector restricted to T, for
-    overlapping, disjoint, nested and whole-domain boxes."""
-    w = dict(small_cases())[name]
+    overlapping, disjoint, nested and whole-domain boxes (2-D and 3-D)."""
+    w = dict(small_cases() + small_cases_3d())[name]
     lib = _emu_lib()
     h = _emu_handle(lib, w)
     ora = OracleOperator.from_workload(w)
@@ -301,7 +301,7 @@ def test_emulated_kernels_under_address_sanitizer():
         "    h = _emu_handle(lib, w)\n"
         "    xs = np.random.default_rng(2).integers(0, np.array(w.shape), (50, w.d))\n"
         "    _emu_entries(lib, h, np.clip(xs + 3, 0, np.array(w.shape) - 1), xs)\n"
-        "    if w.d < 3:\n"
+        "    if True:\n"
         "        lo = np.array(w.shape) // 4; hi = np.array(w.shape) - 2\n"
         "        _emu_block(lib, h, 0, (lo, hi), (lo // 2, hi - 1), np.ones((1, int(np.prod(hi - lo // 2)))))\n"
         "        _emu_block(lib, h, 1, (lo, hi), (lo // 2, hi - 1), np.ones((1, int(np.prod(hi - lo // 2)))))\n"
