@@ -34,12 +34,20 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
     std::vector<T> slots((size_t)(B * per), T(0));
     for (int64_t b = 0; b < B; ++b) {
         for (const pc::Item& it : P.items) {
-            std::vector<C> buf((size_t)it.n0 * it.ld);
+            std::vector<C> buf((size_t)(it.n0 * it.ld + pc::tw_lds_elems(it)));
             for (auto& v : buf) v = C{T(1e30), T(1e30)};   // poison: unwritten reads show up
             pc::Ctx<T> c = pc::make_ctx<T>(it, adj, &in[(size_t)(b * N)], &slots[(size_t)(b * per)], wts.data(),
                                            reinterpret_cast<const C*>(spec.data()),
                                            reinterpret_cast<const C*>(tw.data()), P.cols);
             const int nth = P.conv_threads;
+            {
+                pc::Ctx<T> c0 = c;
+                for (int t = 0; t < nth; ++t) {
+                    c0 = c;
+                    pc::twiddles_to_lds(c0, buf.data() + (int64_t)it.n0 * it.ld, t, nth);
+                }
+                c = c0;
+            }
             for (int t = 0; t < nth; ++t) pc::phA0(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phA(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phB(c, buf.data(), t, nth);
@@ -99,9 +107,17 @@ void emu_3d(const pc::Plan& P, const std::vector<pc::Item3>& items, int64_t per,
             T* sv = &slots[(size_t)(b * per)];
             C* sc = pc::item_scratch(scratch.data(), 0, I, (int)B, (int)b);
             for (int q = 0; q < pl.s_n; ++q) {
-                std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
-                const pc::Ctx<T> c =
+                std::vector<C> buf((size_t)(I.p.n0 * I.p.ld + pc::tw_lds_elems(I.p)), C{T(1e30), T(1e30)});
+                pc::Ctx<T> c =
                     pc::plane_ctx_gather<T>(I, adj, q, iv, sv, wts.data(), specc, twc, in_pitch, plane_pitch);
+                {
+                    pc::Ctx<T> c0 = c;
+                    for (int t = 0; t < NT; ++t) {
+                        c0 = c;
+                        pc::twiddles_to_lds(c0, buf.data() + (int64_t)I.p.n0 * I.p.ld, t, NT);
+                    }
+                    c = c0;
+                }
                 for (int t = 0; t < NT; ++t) pc::phA0(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phA(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phB(c, buf.data(), t, NT);
@@ -111,9 +127,17 @@ void emu_3d(const pc::Plan& P, const std::vector<pc::Item3>& items, int64_t per,
             }
             for (int64_t c_lo = 0; c_lo < pe; c_lo += COLS) {
                 const int ncols = (int)std::min<int64_t>(COLS, pe - c_lo);
-                std::vector<C> buf((size_t)I.nz * LDA, C{T(1e30), T(1e30)});
-                const pc::Ctx<T> c = pc::axis_ctx<T>(I, adj, (int)c_lo, ncols, LDA, specc, twc);
+                std::vector<C> buf((size_t)(I.nz * LDA + I.nz), C{T(1e30), T(1e30)});
+                pc::Ctx<T> c = pc::axis_ctx<T>(I, adj, (int)c_lo, ncols, LDA, specc, twc);
                 const int AT = pc::kAxisThreads;
+                {
+                    pc::Ctx<T> c0 = c;
+                    for (int t = 0; t < AT; ++t) {
+                        c0 = c;
+                        pc::axis_twiddles_to_lds(c0, buf.data() + (int64_t)I.nz * LDA, t, AT);
+                    }
+                    c = c0;
+                }
                 for (int t = 0; t < AT; ++t) pc::axis_load(c, buf.data(), sc + c_lo, pe, t, AT);
                 for (int t = 0; t < AT; ++t) pc::phC(c, buf.data(), t, AT);
                 for (int t = 0; t < AT; ++t) pc::phD(c, buf.data(), t, AT);
@@ -121,8 +145,16 @@ void emu_3d(const pc::Plan& P, const std::vector<pc::Item3>& items, int64_t per,
                 for (int t = 0; t < AT; ++t) pc::axis_store(c, buf.data(), sc + c_lo, pe, t, AT);
             }
             for (int q = 0; q < pl.d_n; ++q) {
-                std::vector<C> buf((size_t)I.p.n0 * I.p.ld, C{T(1e30), T(1e30)});
-                const pc::Ctx<T> c = pc::plane_ctx_write<T>(I, adj, q, iv, sv, wts.data(), specc, twc, in_pitch);
+                std::vector<C> buf((size_t)(I.p.n0 * I.p.ld + pc::tw_lds_elems(I.p)), C{T(1e30), T(1e30)});
+                pc::Ctx<T> c = pc::plane_ctx_write<T>(I, adj, q, iv, sv, wts.data(), specc, twc, in_pitch);
+                {
+                    pc::Ctx<T> c0 = c;
+                    for (int t = 0; t < NT; ++t) {
+                        c0 = c;
+                        pc::twiddles_to_lds(c0, buf.data() + (int64_t)I.p.n0 * I.p.ld, t, NT);
+                    }
+                    c = c0;
+                }
                 for (int t = 0; t < NT; ++t) pc::plane_load(c, buf.data(), sc + (int64_t)(pl.d_off + q) * pe, t, NT);
                 for (int t = 0; t < NT; ++t) pc::phD_inv(c, buf.data(), t, NT);
                 for (int t = 0; t < NT; ++t) pc::phE(c, buf.data(), t, NT);
@@ -248,10 +280,18 @@ int pc_emu_apply_block(pc_emu* e, int adj, const int64_t* tlo, const int64_t* th
         std::vector<double> in(U + b * ldu, U + b * ldu + nS);
         std::vector<double> slots((size_t)std::max<int64_t>(bp.per, 1), 0.0);
         for (const pc::Item& it : bp.items) {
-            std::vector<C> buf((size_t)it.n0 * it.ld, C{1e30, 1e30});
+            std::vector<C> buf((size_t)(it.n0 * it.ld + pc::tw_lds_elems(it)), C{1e30, 1e30});
             pc::Ctx<double> c = pc::make_ctx<double>(it, adj != 0, in.data(), slots.data(), P.wts.data(), spec, tw,
                                                      bp.s_cols);
             const int nth = P.conv_threads;
+            {
+                pc::Ctx<double> c0 = c;
+                for (int t = 0; t < nth; ++t) {
+                    c0 = c;
+                    pc::twiddles_to_lds(c0, buf.data() + (int64_t)it.n0 * it.ld, t, nth);
+                }
+                c = c0;
+            }
             for (int t = 0; t < nth; ++t) pc::phA0(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phA(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phB(c, buf.data(), t, nth);

@@ -35,9 +35,10 @@ __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     const int rhs = l % A.B;
     if (item >= A.n_items) return;
     const Item it = A.items[A.item_lo + item];
-    const Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
-                                 A.wts, A.spec, A.tw, A.pitch);
+    Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
+                           A.wts, A.spec, A.tw, A.pitch);
     const int tid = threadIdx.x;
+    twiddles_to_lds(c, buf + (int64_t)it.n0 * it.ld, tid, NT);
     phA0(c, buf, tid, NT);
     __syncthreads();
     phA(c, buf, tid, NT);
@@ -91,9 +92,10 @@ __global__ __launch_bounds__(kPlaneThreads) void plane_fwd_kernel(Conv3Args<T> A
     const bool adj = A.adj != 0;
     const Planes pl = planes_of(I, adj);
     if (q >= pl.s_n) return;
-    const Ctx<T> c = plane_ctx_gather<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
-                                         A.wts, A.spec, A.tw, A.pitch, A.plane_pitch);
+    Ctx<T> c = plane_ctx_gather<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
+                                   A.wts, A.spec, A.tw, A.pitch, A.plane_pitch);
     const int tid = threadIdx.x;
+    twiddles_to_lds(c, buf + (int64_t)I.p.n0 * I.p.ld, tid, NT);
     phA0(c, buf, tid, NT);
     __syncthreads();
     phA(c, buf, tid, NT);
@@ -127,9 +129,10 @@ __global__ __launch_bounds__(kAxisThreads) void axis_kernel(Conv3Args<T> A) {
     const int c_lo = tile * COLS;
     if (c_lo >= pe) return;
     const int ncols = (int)(pe - c_lo < COLS ? pe - c_lo : COLS);
-    const Ctx<T> c = axis_ctx<T>(I, A.adj != 0, c_lo, ncols, axis_ld(COLS), A.spec, A.tw);
+    Ctx<T> c = axis_ctx<T>(I, A.adj != 0, c_lo, ncols, axis_ld(COLS), A.spec, A.tw);
     cx<T>* sc = item_scratch(A.scratch, A.scratch_base, I, A.B, rhs) + c_lo;
     const int tid = threadIdx.x;
+    axis_twiddles_to_lds(c, buf + (int64_t)I.nz * axis_ld(COLS), tid, NT);
     axis_load(c, buf, sc, pe, tid, NT);
     __syncthreads();
     phC(c, buf, tid, NT);
@@ -154,9 +157,10 @@ __global__ __launch_bounds__(kPlaneThreads) void plane_inv_kernel(Conv3Args<T> A
     const bool adj = A.adj != 0;
     const Planes pl = planes_of(I, adj);
     if (q >= pl.d_n) return;
-    const Ctx<T> c = plane_ctx_write<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
-                                        A.wts, A.spec, A.tw, A.pitch);
+    Ctx<T> c = plane_ctx_write<T>(I, adj, q, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
+                                  A.wts, A.spec, A.tw, A.pitch);
     const int tid = threadIdx.x;
+    twiddles_to_lds(c, buf + (int64_t)I.p.n0 * I.p.ld, tid, NT);
     plane_load(c, buf, item_scratch(A.scratch, A.scratch_base, I, A.B, rhs) + (int64_t)(pl.d_off + q) * plane_elems(I),
                tid, NT);
     __syncthreads();

@@ -87,6 +87,29 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
     return c;
 }
 
+// The item's twiddle tables (w_{n0}, w_m, w_{2m}: n0 + 3m complex) are
+// copied into LDS right after the FFT box, cooperatively and before the first
+// barrier; the phases then read their twiddles from LDS.
+__host__ __device__ inline int64_t tw_lds_elems(const Item& it) { return (int64_t)it.n0 + 3 * (int64_t)it.m; }
+
+template <class T>
+__host__ __device__ inline void twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth) {
+    const int n0 = c.it.n0, m = c.it.m, n = n0 + 3 * m;
+    for (int t = tid; t < n; t += nth) {
+        cx<T> v;
+        if (t < n0)
+            v = c.tw0[t];
+        else if (t < n0 + m)
+            v = c.twm[t - n0];
+        else
+            v = c.tw2m[t - n0 - m];
+        dst[t] = v;
+    }
+    c.tw0 = dst;
+    c.twm = dst + n0;
+    c.tw2m = dst + n0 + m;
+}
+
 #define PC_RADIX_SWITCH(R, FN, ...)               \
     switch (R) {                                  \
         case 1: FN<1>(__VA_ARGS__); break;        \

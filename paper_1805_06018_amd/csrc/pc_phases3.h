@@ -145,6 +145,16 @@ __host__ __device__ inline void axis_store(const Ctx<T>& c, const cx<T>* buf, cx
     }
 }
 
+// Axis-0 twiddles (w_nz, nz complex) copied into LDS after the block's box.
+template <class T>
+__host__ __device__ inline void axis_twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth) {
+    const int n = c.it.n0;
+    for (int t = tid; t < n; t += nth) dst[t] = c.tw0[t];
+    c.tw0 = dst;
+    c.twm = dst;
+    c.tw2m = dst;
+}
+
 // LDS row stride of the axis-0 block (odd, at least the column count + 1).
 __host__ __device__ constexpr int axis_ld(int cols) { return (cols + 1) % 2 ? cols + 1 : cols + 2; }
 

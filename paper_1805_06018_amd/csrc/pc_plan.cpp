@@ -764,7 +764,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 const int64_t h0 = (m[0] + P0 - 1) / P0;
                 const int n0p = (d == 1) ? 1 : next_fft_size((int)(h0 + K[0] - 1));
                 if (n0p < 0) continue;
-                if ((int64_t)n0p * ld_p * (int64_t)csz > lds_cap) continue;
+                if (((int64_t)n0p * ld_p + n0p + 3 * Mp) * (int64_t)csz > lds_cap) continue;   // box + twiddles
                 const double nn = (double)n0p * 2.0 * Mp;
                 const double cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
                 if (cost < best_cost) {
@@ -876,7 +876,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
             p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
             p.sum_fft_points += (int64_t)po.n0 * 2 * po.M;
-            p.max_lds = std::max(p.max_lds, (int)(po.n0 * ldr * csz));
+            p.max_lds = std::max(p.max_lds, (int)(((int64_t)po.n0 * ldr + po.n0 + 3 * po.M) * csz));
             p.items.push_back(it);
         }
     }

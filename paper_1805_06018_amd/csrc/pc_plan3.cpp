@@ -371,8 +371,8 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         }
         int ld = M + 1;
         if (ld % 2 == 0) ++ld;
-        g.lds_plane = (int)((size_t)n1 * ld * csz);
-        g.lds_axis = (int)((size_t)nz * ld_axis * csz);
+        g.lds_plane = (int)(((size_t)n1 * ld + n1 + 3 * (size_t)M) * csz);   // plane box + twiddles
+        g.lds_axis = (int)(((size_t)nz * ld_axis + nz) * csz);
         if (g.lds_plane > kLdsBytes || g.lds_axis > kLdsBytes) {
             g.st = PC_ERR_UNSUPPORTED;
             g.err = "patch " + std::to_string(k) + " does not fit the LDS-resident plane FFT";
