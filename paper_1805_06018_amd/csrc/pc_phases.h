@@ -34,6 +34,16 @@
 
 namespace pc {
 
+// a * b for operands below 2^23: one full-rate 24-bit multiply on the GPU
+// (a 32-bit product is a quarter-rate instruction there).
+__host__ __device__ __forceinline__ int imul24(int a, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
 // floor(x / d) for 0 <= x < 2^22 with inv = 1.0f / d (exact: the fraction
 // (x + 1/2) / d stays at least 1/(2d) away from an integer).
 __host__ __device__ inline int fdiv(int x, float inv) { return (int)(((float)x + 0.5f) * inv); }
@@ -49,7 +59,7 @@ struct Ctx {
     T* dst;                           // staging box of this item and vector
     const T* w;                       // weight table of the item's input box
     const cx<T>* spec;
-    int64_t spec_ld;                  // spectrum row stride (m + 1 for 2-D items)
+    int spec_ld;                      // spectrum row stride (m + 1 for 2-D items)
     const cx<T>* tw0;                 // w_{n0}^e
     const cx<T>* twm;                 // w_m^e
     const cx<T>* tw2m;                // w_{2m}^e
@@ -161,8 +171,8 @@ __host__ __device__ inline void phA0(const Ctx<T>& c, cx<T>* buf, int tid, int n
     const int e = col - c.s_off1;        // column inside the gathered box
     const bool live = (unsigned)e < (unsigned)c.s_n1;
     const bool wgt = live && !c.adj;
-    T* rows = reinterpret_cast<T*>(buf) + (int64_t)c.s_off0 * (2 * c.it.ld) + col;
-    const int64_t rstride = 2 * (int64_t)c.it.ld;
+    T* rows = reinterpret_cast<T*>(buf) + c.s_off0 * (2 * c.it.ld) + col;
+    const int rstride = 2 * c.it.ld;
     const T* src = c.src + (int64_t)(c.it.g0 + c.s_off0) * c.pitch + c.it.g1 + col;
     const T* w = c.w + e;
     int q = r0;
@@ -189,14 +199,15 @@ __host__ __device__ inline void phA_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int bm = c.it.bm, ld = c.it.ld;
     const int ntask = c.s_n0 * bm;
     for (int t = tid; t < ntask; t += nth) {
-        const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
-        cx<T>* p = buf + (int64_t)(c.s_off0 + q) * ld + j0;
+        const int q = fdiv(t, c.inv_bm), j0 = t - imul24(q, bm);
+        cx<T>* p = buf + (imul24(c.s_off0 + q, ld) + j0);
         cx<T> x[A];
 #pragma unroll
         for (int j1 = 0; j1 < A; ++j1) x[j1] = p[bm * j1];
         Dft<A, -1>::run(x);
+        int e = 0;   // twiddle exponent j0 k1
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) p[bm * k1] = cmul(x[k1], c.twm[j0 * k1]);
+        for (int k1 = 0; k1 < A; ++k1, e += j0) p[bm * k1] = cmul(x[k1], c.twm[e]);
     }
 }
 template <class T>
@@ -237,16 +248,18 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int H = am / 2 + 1;
     const int ntask = c.s_n0 * H;
     for (int t = tid; t < ntask; t += nth) {
-        const int k1 = fdiv(t, c.inv_sn0), r = t - k1 * c.s_n0;
-        cx<T>* p = buf + (int64_t)(c.s_off0 + r) * ld;
+        const int k1 = fdiv(t, c.inv_sn0), r = t - imul24(k1, c.s_n0);
+        cx<T>* p = buf + imul24(c.s_off0 + r, ld);
         const int k1b = (k1 == 0) ? 0 : am - k1;
+        cx<T>* pa = p + imul24(Bm, k1);
+        cx<T>* pb = p + imul24(Bm, k1b);
         cx<T> za[Bm], zb[Bm];
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = p[Bm * k1 + k0];
+        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = pa[k0];
         Dft<Bm, -1>::run(za);
         if (k1b != k1) {
 #pragma unroll
-            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = p[Bm * k1b + k0];
+            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
             Dft<Bm, -1>::run(zb);
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) {
@@ -257,7 +270,7 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
                 zb[Bm - 1 - k0] = Xm;
             }
 #pragma unroll
-            for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1b + k0] = zb[k0];
+            for (int k0 = 0; k0 < Bm; ++k0) pb[k0] = zb[k0];
         } else if (k1 == 0) {
             // k = am k0 pairs with am (bm - k0); k0 = 0 gives X[0] and X[m]
             const cx<T> z0 = za[0];
@@ -283,7 +296,7 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             }
         }
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1 + k0] = za[k0];
+        for (int k0 = 0; k0 < Bm; ++k0) pa[k0] = za[k0];
     }
 }
 template <class T>
@@ -297,17 +310,19 @@ __host__ __device__ inline void phC_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * b0;
     for (int t = tid; t < ntask; t += nth) {
-        const int j0 = fdiv(t, c.inv_nc), col = t - j0 * NC;
+        const int j0 = fdiv(t, c.inv_nc), col = t - imul24(j0, NC);
+        cx<T>* p = buf + (imul24(j0, ld) + col);
+        const int step = b0 * ld;
         cx<T> x[A0];
 #pragma unroll
         for (int j1 = 0; j1 < A0; ++j1) {
             const int row = b0 * j1 + j0;
-            x[j1] = ((unsigned)(row - c.s_off0) < (unsigned)c.s_n0) ? buf[(int64_t)row * ld + col]
-                                                                    : cx<T>{T(0), T(0)};
+            x[j1] = ((unsigned)(row - c.s_off0) < (unsigned)c.s_n0) ? p[j1 * step] : cx<T>{T(0), T(0)};
         }
         Dft<A0, -1>::run(x);
+        int e = 0;   // twiddle exponent j0 k1
 #pragma unroll
-        for (int k1 = 0; k1 < A0; ++k1) buf[(int64_t)(b0 * k1 + j0) * ld + col] = cmul(x[k1], c.tw0[j0 * k1]);
+        for (int k1 = 0; k1 < A0; ++k1, e += j0) p[k1 * step] = cmul(x[k1], c.tw0[e]);
     }
 }
 template <class T>
@@ -324,30 +339,36 @@ __host__ __device__ inline void phD_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int a0 = c.it.a0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * a0;
     for (int t = tid; t < ntask; t += nth) {
-        const int k1 = fdiv(t, c.inv_nc), col = t - k1 * NC;
-        cx<T>* p = buf + (int64_t)(B0 * k1) * ld + col;
+        const int k1 = fdiv(t, c.inv_nc), col = t - imul24(k1, NC);
+        cx<T>* p = buf + (imul24(k1, B0 * ld) + col);
         cx<T> x[B0];
         if (MODE == 0) {
-            const cx<T>* sp = c.spec + (int64_t)(B0 * k1) * c.spec_ld + col;
+            const int sld = c.spec_ld;
+            const unsigned so = (unsigned)(imul24(k1, B0 * sld) + col);
             cx<T> s[B0];
 #pragma unroll
-            for (int k0 = 0; k0 < B0; ++k0) s[k0] = sp[(int64_t)k0 * c.spec_ld];
+            for (int k0 = 0; k0 < B0; ++k0) s[k0] = c.spec[so + (unsigned)(k0 * sld)];
 #pragma unroll
-            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
+            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[k0 * ld];
             Dft<B0, -1>::run(x);
+            if (c.adj) {
 #pragma unroll
-            for (int k0 = 0; k0 < B0; ++k0) x[k0] = c.adj ? cmulc(x[k0], s[k0]) : cmul(x[k0], s[k0]);
+                for (int k0 = 0; k0 < B0; ++k0) x[k0] = cmulc(x[k0], s[k0]);
+            } else {
+#pragma unroll
+                for (int k0 = 0; k0 < B0; ++k0) x[k0] = cmul(x[k0], s[k0]);
+            }
             Dft<B0, 1>::run(x);
         } else {
 #pragma unroll
-            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[(int64_t)k0 * ld];
+            for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[k0 * ld];
             if (MODE == 1)
                 Dft<B0, -1>::run(x);
             else
                 Dft<B0, 1>::run(x);
         }
 #pragma unroll
-        for (int k0 = 0; k0 < B0; ++k0) p[(int64_t)k0 * ld] = x[k0];
+        for (int k0 = 0; k0 < B0; ++k0) p[k0 * ld] = x[k0];
     }
 }
 template <int B0, class T>
@@ -375,15 +396,18 @@ __host__ __device__ inline void phE_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int b0 = c.it.b0, ld = c.it.ld, NC = c.it.m + 1;
     const int ntask = NC * b0;
     for (int t = tid; t < ntask; t += nth) {
-        const int j0 = fdiv(t, c.inv_nc), col = t - j0 * NC;
+        const int j0 = fdiv(t, c.inv_nc), col = t - imul24(j0, NC);
+        cx<T>* p = buf + (imul24(j0, ld) + col);
+        const int step = b0 * ld;
         cx<T> x[A0];
+        int e = 0;   // twiddle exponent j0 k1
 #pragma unroll
-        for (int k1 = 0; k1 < A0; ++k1) x[k1] = cmulc(buf[(int64_t)(b0 * k1 + j0) * ld + col], c.tw0[j0 * k1]);
+        for (int k1 = 0; k1 < A0; ++k1, e += j0) x[k1] = cmulc(p[k1 * step], c.tw0[e]);
         Dft<A0, 1>::run(x);
 #pragma unroll
         for (int j1 = 0; j1 < A0; ++j1) {
             const int row = b0 * j1 + j0;
-            if ((unsigned)(row - c.d_off0) < (unsigned)c.d_n0) buf[(int64_t)row * ld + col] = x[j1];
+            if ((unsigned)(row - c.d_off0) < (unsigned)c.d_n0) p[j1 * step] = x[j1];
         }
     }
 }
@@ -401,15 +425,17 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int H = am / 2 + 1;
     const int ntask = c.d_n0 * H;
     for (int t = tid; t < ntask; t += nth) {
-        const int k1 = fdiv(t, c.inv_dn0), r = t - k1 * c.d_n0;
-        cx<T>* p = buf + (int64_t)(c.d_off0 + r) * ld;
+        const int k1 = fdiv(t, c.inv_dn0), r = t - imul24(k1, c.d_n0);
+        cx<T>* p = buf + imul24(c.d_off0 + r, ld);
         const int k1b = (k1 == 0) ? 0 : am - k1;
+        cx<T>* pa = p + imul24(Bm, k1);
+        cx<T>* pb = p + imul24(Bm, k1b);
         cx<T> za[Bm], zb[Bm];
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = p[Bm * k1 + k0];
+        for (int k0 = 0; k0 < Bm; ++k0) za[k0] = pa[k0];
         if (k1b != k1) {
 #pragma unroll
-            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = p[Bm * k1b + k0];
+            for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) {
                 const int k = k1 + am * k0;
@@ -420,7 +446,7 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             }
             Dft<Bm, 1>::run(zb);
 #pragma unroll
-            for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1b + k0] = zb[k0];
+            for (int k0 = 0; k0 < Bm; ++k0) pb[k0] = zb[k0];
         } else if (k1 == 0) {
             const cx<T> X0 = za[0], XM = p[M];
 #pragma unroll
@@ -446,7 +472,7 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         }
         Dft<Bm, 1>::run(za);
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) p[Bm * k1 + k0] = za[k0];
+        for (int k0 = 0; k0 < Bm; ++k0) pa[k0] = za[k0];
     }
 }
 template <class T>
@@ -463,11 +489,12 @@ __host__ __device__ inline void phG_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     const int bm = c.it.bm, ld = c.it.ld;
     const int ntask = c.d_n0 * bm;
     for (int t = tid; t < ntask; t += nth) {
-        const int q = fdiv(t, c.inv_bm), j0 = t - q * bm;
-        cx<T>* p = buf + (int64_t)(c.d_off0 + q) * ld + j0;
+        const int q = fdiv(t, c.inv_bm), j0 = t - imul24(q, bm);
+        cx<T>* p = buf + (imul24(c.d_off0 + q, ld) + j0);
         cx<T> x[A];
+        int e = 0;   // twiddle exponent j0 k1
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) x[k1] = cmulc(p[bm * k1], c.twm[j0 * k1]);
+        for (int k1 = 0; k1 < A; ++k1, e += j0) x[k1] = cmulc(p[bm * k1], c.twm[e]);
         Dft<A, 1>::run(x);
 #pragma unroll
         for (int j1 = 0; j1 < A; ++j1) p[bm * j1] = x[j1];
@@ -490,8 +517,8 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     const int rps = nth / n1;            // rows per sweep (n1 <= 256 <= nth)
     const int r0 = tid / n1, e = tid - r0 * n1;
     if (r0 >= rps) return;
-    const T* rows = reinterpret_cast<const T*>(buf) + (int64_t)c.d_off0 * (2 * c.it.ld) + c.d_off1 + e;
-    const int64_t rstride = 2 * (int64_t)c.it.ld;
+    const T* rows = reinterpret_cast<const T*>(buf) + c.d_off0 * (2 * c.it.ld) + c.d_off1 + e;
+    const int rstride = 2 * c.it.ld;
     const T* w = c.w + e;
     T* dst = c.dst + e;
     int q = r0;

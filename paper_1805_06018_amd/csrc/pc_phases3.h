@@ -115,7 +115,7 @@ __host__ __device__ inline Ctx<T> axis_ctx(const Item3& I, bool adj, int c_lo, i
     c.dst = nullptr;
     c.w = nullptr;
     c.spec = spec + I.p.spec_off + c_lo;
-    c.spec_ld = plane_elems(I);
+    c.spec_ld = (int)plane_elems(I);
     c.tw0 = tw + I.twz;
     c.twm = c.tw0;
     c.tw2m = c.tw0;
