@@ -97,15 +97,17 @@ def main():
     # timed region (kernel events recorded on the same stream)
     op.read_profile()
     op.set_profiling(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive applies: per-apply latency percentiles
+    # and the total come from the same stream timeline
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         op.apply_batch(U, OUT)
-    stop.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
+    ms_total = ev[0].elapsed_time(ev[-1])
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     op.set_profiling(False)
     prof = op.read_profile()
     ms_step = ms_total / args.steps
@@ -144,7 +146,7 @@ def main():
     else:
         wl = f"blur2d_1024x1024_quadtree_r{w.r}_b{B}"
     rec = {
-        "metric": "PC apply grid-points/s (FP32, 1e-5 rel.L2) vs plain apply",
+        "metric": "PC apply grid-points/s (FP32, 1e-5 rel.L2) vs plain apply; HBM %; p50/p99 lat",
         "value": value,
         "unit": "grid-points/s",
         "n_gpus": 1,
@@ -165,6 +167,8 @@ def main():
                     "reduce_ms_per_step": prof["reduce_ms"] / args.steps,
                     "alg_flops_per_vector": st["alg_flops_per_rhs"]},
         "hbm_alg_frac": alg_bytes_step / (ms_step * 1e-3) / PEAK_HBM,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "applies": int(lat.size)},
         "plain": {"ms_per_step": plain_ms, "value": (w.N * B / (plain_ms * 1e-3)) if plain_ms else None,
                   "bitwise_equal_to_fused": same},
     }
