@@ -1,7 +1,7 @@
 """Benchmark of the product-convolution apply on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--workload blur1024|blur3d] [--dtype f32|f64]
+                [--workload blur1024|blur3d] [--dtype f32|f64] [--graph]
 
 A step is one pc_apply_batch of the whole hot path (gather with weights,
 forward FFT, spectral product, inverse FFT, deterministic scatter-add) with
@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--workload", choices=["blur1024", "blur3d"], default="blur1024")
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of the apply recorded into a HIP graph (stream capture)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the 256 MiB input (a known-size "
                          "reference for hardware byte counters)")
@@ -120,6 +122,26 @@ def main():
     peak = PEAK_FP64_VALU if f64 else PEAK_FP32_VALU
     alg_bytes_step = 2.0 * esz * w.N * B + esz * st["kernel_elems"]
 
+    graph = None
+    if args.graph:
+        ref_out = OUT.clone()
+        g = op.graph(U, OUT)
+        for _ in range(3):
+            g.replay()
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        gev[0].record()
+        for i in range(args.steps):
+            g.replay()
+            gev[i + 1].record()
+        torch.cuda.synchronize()
+        glat = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps)])
+        gms = gev[0].elapsed_time(gev[-1]) / args.steps
+        graph = {"ms_per_step": gms, "value": w.N * B / (gms * 1e-3),
+                 "p50_ms": float(np.percentile(glat, 50)), "p99_ms": float(np.percentile(glat, 99)),
+                 "bitwise_equal_to_eager": bool(torch.equal(OUT, ref_out))}
+        del g
+
     if args.copy_probe:
         probe = torch.empty_like(U)
         probe.copy_(U)
@@ -169,6 +191,7 @@ def main():
         "hbm_alg_frac": alg_bytes_step / (ms_step * 1e-3) / PEAK_HBM,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "applies": int(lat.size)},
+        "graph": graph,
         "plain": {"ms_per_step": plain_ms, "value": (w.N * B / (plain_ms * 1e-3)) if plain_ms else None,
                   "bitwise_equal_to_fused": same},
     }

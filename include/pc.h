@@ -26,6 +26,19 @@
  *  - An operator is read-only after pc_create.  Calls on one operator must be
  *    serialised by the caller (they share the operator's work buffers);
  *    different operators are independent.
+ *  - Graph capture: pc_apply, pc_apply_batch, pc_apply_adjoint_batch,
+ *    pc_apply_batch_plain, the two _axpy calls and pc_entries only launch
+ *    kernels on s once the operator's work buffers are large enough, so a
+ *    caller may record them into a HIP graph by stream capture after one
+ *    call of at least the same batch size (same entry point and tuning)
+ *    outside the capture.  A captured call whose buffers would have to grow
+ *    returns PC_ERR_ARG without enqueuing anything.  The graph replays with
+ *    the pointers given at capture and keeps using the operator's buffers:
+ *    replays must not overlap other calls on the same operator, and a later
+ *    call that needs larger buffers frees the old ones, after which graphs
+ *    recorded earlier must not be replayed.
+ *    pc_apply_block, pc_estimate_sums and pc_error_estimate synchronise the
+ *    host and return PC_ERR_ARG under capture.
  */
 #ifndef PC_H_
 #define PC_H_

@@ -186,6 +186,18 @@ class PcOperator:
     def apply_batch_plain(self, U, OUT, stream=None):
         return self._batch(_lib.pc_apply_batch_plain, U, OUT, stream)
 
+    def graph(self, U, OUT, adjoint=False):
+        """Records one batched apply (adjoint: A~* apply) from U into OUT as a
+        torch.cuda.CUDAGraph.  One eager call first sizes the operator's work
+        buffers; each replay recomputes OUT from the current contents of U."""
+        fn = self.apply_adjoint_batch if adjoint else self.apply_batch
+        fn(U, OUT)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(U, OUT)
+        return g
+
     def _axpy(self, fn, U, alpha, OUT, stream):
         B = 1 if U.dim() == 1 else U.shape[0]
         _check(fn(self._h, B, _dev(U, self.torch_dtype, "U"), _ld(U, "U"), float(alpha),

@@ -124,8 +124,17 @@ pc_status upload_real(pc_op* op, const std::vector<double>& v, void** dptr) {
     return upload(op, f, dptr);
 }
 
-pc_status ensure(void** buf, size_t* have, size_t need, const char* what) {
+// True while s records a graph (stream capture).
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+pc_status ensure(void** buf, size_t* have, size_t need, const char* what, bool in_capture = false) {
     if (*have >= need) return PC_OK;
+    if (in_capture)   // growing would synchronise the device and allocate inside the capture
+        return fail(PC_ERR_ARG, std::string(what) + ": the buffer is smaller than this call needs; make one call "
+                                                    "of at least this size before the stream capture");
     if (*buf) {
         hipError_t e = hipDeviceSynchronize();   // a previous call may still use it
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -153,7 +162,7 @@ hipEvent_t get_event(pc_op* op) {
 // Records the start event of a timed launch (no-op when not profiling).
 void prof_begin(pc_op* op, hipStream_t s, hipEvent_t* ev) {
     *ev = nullptr;
-    if (!op->profiling) return;
+    if (!op->profiling || capturing(s)) return;   // no event nodes in a captured graph
     *ev = get_event(op);
     if (*ev) hipEventRecord(*ev, s);
 }
@@ -230,9 +239,10 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
         groups.push_back(L);
         i = j;
     }
-    pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    const bool cap = capturing(s);
+    pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)", cap);
     if (st != PC_OK) return st;
-    st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)");
+    st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)", cap);
     if (st != PC_OK) return st;
     const char* u = static_cast<const char*>(U);
     char* o = static_cast<char*>(OUT);
@@ -293,8 +303,10 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     const int64_t nchunks = (B + chunk - 1) / chunk;
     const bool overlap = !plain && op->tune_overlap && nchunks > 1;
     const size_t buf_bytes = (size_t)chunk * per_bytes;
-    st = ensure(&op->slots, &op->slots_bytes, (overlap ? 2 : 1) * buf_bytes, "hipMalloc (staging)");
+    const bool cap = capturing(s);
+    st = ensure(&op->slots, &op->slots_bytes, (overlap ? 2 : 1) * buf_bytes, "hipMalloc (staging)", cap);
     if (st != PC_OK) return st;
+    if (overlap && cap && !op->aux) return fail(PC_ERR_ARG, "make one overlapped call before the stream capture");
     if (overlap && (st = ensure_aux(op)) != PC_OK) return st;
     const char* u = static_cast<const char*>(U);
     char* o = static_cast<char*>(OUT);
@@ -573,6 +585,7 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
                          hipStream_t s) {
     pc_status st = check_op(op);
     if (st != PC_OK) return st;
+    if (capturing(s)) return fail(PC_ERR_ARG, "pc_apply_block copies its tables synchronously: not capturable");
     if (B < 0) return fail(PC_ERR_ARG, "negative batch size");
     pc::BlockPlan bp;
     std::string err;
@@ -652,6 +665,7 @@ pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs,
     if (n < 0) return fail(PC_ERR_ARG, "negative entry count");
     if (n == 0) return PC_OK;
     if (!ys || !xs || !out) return fail(PC_ERR_ARG, "null coordinate or output pointer");
+    if (!op->ent_phiE && capturing(s)) return fail(PC_ERR_ARG, "make one pc_entries call before the stream capture");
     if ((st = ensure_entries(op)) != PC_OK) return st;
     hipError_t e = pc::launch_entries(op->ent, op->plan.dtype, op->d_wts, op->ent_phiE, n, ys, xs, out, s);
     if (e != hipSuccess) return hip_fail(e, "entries launch");
@@ -665,6 +679,7 @@ pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, co
     const int64_t N = op->plan.N;
     if (q < 1 || !Yt || !Y || ldt < N || ldy < N) return fail(PC_ERR_ARG, "invalid estimator blocks");
     if (!eta_abs || !eta_rel) return fail(PC_ERR_ARG, "null output scalar");
+    if (capturing(s)) return fail(PC_ERR_ARG, "the estimator returns host scalars: not capturable");
     return est_sums(op, q, Yt, ldt, Y, ldy, eta_leaf, eta_abs, eta_rel, s);
 }
 
@@ -678,6 +693,7 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, co
     if (!eta_abs || !eta_rel) return fail(PC_ERR_ARG, "null output scalar");
     if (!Y_or_null && !exact_adjoint) return fail(PC_ERR_ARG, "need Y or an exact-adjoint callback");
     if (Y_or_null && ldy < N) return fail(PC_ERR_ARG, "ldy smaller than N");
+    if (capturing(s)) return fail(PC_ERR_ARG, "the estimator returns host scalars: not capturable");
     const size_t vec = (size_t)N * op->esz;
     const size_t need = (size_t)q * vec * (Y_or_null ? 1 : 2);
     st = ensure(&op->work, &op->work_bytes, need, "hipMalloc (estimator work)");

@@ -460,3 +460,68 @@ def test_block_apply_3d_equals_restricted_full_apply(lib, name):
                 ref = ref_full.reshape((3,) + tuple(w.shape))[tl].reshape(3, -1)
                 assert torch.equal(got, ref), (name, dtype, adj, t_box, s_box)
         op.close()
+
+
+@pytest.mark.parametrize("name", ["hanging33", "rect3d"])
+def test_graph_replays_equal_eager_applies(lib, name):
+    """A batched apply (and adjoint apply) recorded into a HIP graph by stream
+    capture: every replay, with new input in the captured buffer and eager
+    work on the same operator in between, equals the eager apply bitwise and
+    the oracle within the FP32 tolerance."""
+    from tests.libhelpers import small_cases_3d
+    w = dict(small_cases() + small_cases_3d())[name]
+    ora = OracleOperator.from_workload(w)
+    rng = np.random.default_rng(61)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    for adj in (False, True):
+        _note(f"case={name} graph adjoint={adj}")
+        U = torch.zeros((3, w.N), dtype=torch.float32, device="cuda")
+        OUT = torch.zeros_like(U)
+        g = op.graph(U, OUT, adjoint=adj)
+        eager = op.apply_adjoint_batch if adj else op.apply_batch
+        for rep in range(3):
+            Un = rng.standard_normal((3, w.N)).astype(np.float32)
+            U.copy_(torch.from_numpy(Un))
+            E = torch.empty_like(U)
+            eager(U, E)                       # eager work on the operator between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(OUT, E), (name, adj, rep)
+            ref = ora.apply_batch(Un.astype(np.float64), adjoint=adj)
+            assert relerr(OUT.cpu().numpy(), ref).max() <= TOL[lib.PC_F32], (name, adj, rep)
+        del g
+    op.close()
+
+
+def test_calls_that_synchronise_refuse_capture(lib):
+    """Block applies and the estimator return host data or copy tables
+    synchronously: under stream capture they fail with PC_ERR_ARG before
+    enqueuing anything, and the capture stays usable."""
+    w = small_cases()[0][1]
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    U = torch.zeros((2, w.N), dtype=torch.float32, device="cuda")
+    OUT = torch.zeros_like(U)
+    op.apply_batch(U, OUT)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    errs = []
+    with torch.cuda.graph(g):
+        op.apply_batch(U, OUT)
+        box = (np.zeros(w.d, int), np.array(w.shape) - 1)
+        try:
+            op.apply_block(box, box, U, OUT)
+        except lib.PcError as e:
+            errs.append(e.status)
+        try:
+            op.estimate_sums(U, OUT)
+        except lib.PcError as e:
+            errs.append(e.status)
+    assert errs == [lib.PC_ERR_ARG, lib.PC_ERR_ARG]
+    U.copy_(torch.from_numpy(np.random.default_rng(3).standard_normal((2, w.N)).astype(np.float32)))
+    E = torch.empty_like(U)
+    op.apply_batch(U, E)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(OUT, E)
+    op.close()
