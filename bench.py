@@ -1,7 +1,7 @@
 """Benchmark of the product-convolution apply on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--workload blur1024|blur3d] [--dtype f32|f64] [--graph]
+                [--workload blur1024|blur3d] [--dtype f32|f64] [--graph] [--no-autotune]
 
 A step is one pc_apply_batch of the whole hot path (gather with weights,
 forward FFT, spectral product, inverse FFT, deterministic scatter-add) with
@@ -26,28 +26,30 @@ PEAK_FP64_VALU = 78.6e12       # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E B/s
 
 # HBM bytes per convolution launch from the committed counter runs (FETCH_SIZE
-# x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy); valid only while the
-# kernel and planner sources hash to the recorded value.
+# x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy), one line per launch
+# size; valid only while the kernel and planner sources hash to the recorded
+# value.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_kernel_blur1024_b64.md")
 TRAFFIC_SOURCES = ["paper_1805_06018_amd/csrc/" + f
                    for f in ("pc_kernels.hip", "pc_phases.h", "pc_fft.h", "pc_internal.h", "pc_plan.cpp")]
 
 
-def measured_traffic():
+def measured_traffic(vectors_per_launch):
     import hashlib
     import re
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch=([0-9.eE+]+) sources_sha256=([0-9a-f]{64})", text)
-    if not m:
-        return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+    for m in re.finditer(r"traffic vectors_per_launch=(\d+) bytes_per_launch=([0-9.eE+]+) "
+                         r"sources_sha256=([0-9a-f]{64})", text):
+        if int(m.group(1)) == vectors_per_launch and m.group(3) == h.hexdigest():
+            return float(m.group(2))
+    return None
 
 
 def main():
@@ -59,6 +61,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--workload", choices=["blur1024", "blur3d"], default="blur1024")
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default schedule instead of the autotuner's choice")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the apply recorded into a HIP graph (stream capture)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -91,6 +95,18 @@ def main():
     OUT = torch.empty_like(U)
     print(f"# workload {w.name}: N={w.N} r={w.r} B={B} items={st['n_items']} create={t_create:.2f}s",
           file=sys.stderr, flush=True)
+
+    schedule = {"autotuned": False}
+    if not args.no_autotune:
+        from paper_1805_06018_amd import tune
+        t_tune = time.time()
+        # reductions stay on the launch stream: the convolution kernel then
+        # runs alone and its per-launch time is its own
+        res = tune.autotune(op, U, OUT, allow_overlap=False)
+        schedule = {"autotuned": True, "chosen": tune.names(res["best"]), "best_ms": res["best_ms"],
+                    "default_ms": res["default_ms"], "candidates": len(res["table"]),
+                    "tune_s": time.time() - t_tune}
+        print(f"# autotune: {schedule}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         op.apply_batch(U, OUT)
@@ -163,6 +179,12 @@ def main():
     else:
         same = None
 
+    # the committed counter runs cover FP32 2-D launches of 8, 16 and 32 vectors
+    vec_per_launch = prof["conv_vectors"] / max(prof["conv_launches"], 1)
+    traffic = None
+    if not three_d and not f64 and vec_per_launch == int(vec_per_launch):
+        traffic = measured_traffic(int(vec_per_launch))
+
     if three_d:
         wl = f"blur3d_128x128x128_tensor9_r{w.r}_b{B}"
     else:
@@ -180,10 +202,11 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": wl, "grid": list(w.shape), "r": w.r, "batch": B, "items": st["n_items"]},
+        "config": {"workload": wl, "grid": list(w.shape), "r": w.r, "batch": B, "items": st["n_items"],
+                   "schedule": schedule},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None if (three_d or f64) else measured_traffic()},
+                     "traffic": traffic},
         "kernels": {"conv_ms_per_launch": conv_avg_s * 1e3, "conv_launches_per_step": prof["conv_launches"] / args.steps,
                     "conv_ms_per_step": prof["conv_ms"] / args.steps,
                     "reduce_ms_per_step": prof["reduce_ms"] / args.steps,

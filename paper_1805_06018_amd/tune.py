@@ -1,0 +1,110 @@
+"""Autotuner of the apply schedule.
+
+The library's schedule knobs (pc_set_tuning) change how a batched apply is
+cut into launches, never what it computes: vectors per convolution launch
+(PC_TUNE_CHUNK), reduction overlapped on a second stream (PC_TUNE_OVERLAP,
+1-D/2-D operators) and the plane-spectrum scratch per item group
+(PC_TUNE_SCRATCH, 3-D operators).  autotune() times each candidate setting
+on the caller's own vectors, checks that every schedule gives the bitwise
+same result, applies the fastest and returns the whole table.  Results can
+be cached in a JSON file keyed by the operator's shape, size and batch.
+"""
+import json
+import os
+
+import torch
+
+from . import _lib
+
+_MiB = 1 << 20
+
+
+def candidates(op, B, allow_overlap=True):
+    """Candidate settings {key: value} for an operator and batch size; the
+    first one is the library default.  allow_overlap=False keeps every
+    reduction on the caller's stream (each kernel then runs alone, which is
+    what per-kernel timing needs)."""
+    default = {_lib.PC_TUNE_CHUNK: 0, _lib.PC_TUNE_OVERLAP: 0, _lib.PC_TUNE_SCRATCH: 0}
+    out = [dict(default)]
+    chunks = sorted({c for c in (B // 8, B // 4, B // 2, B) if 1 <= c <= B})
+    if op.d == 3:
+        for scratch in (0, 128 * _MiB, 256 * _MiB, 1024 * _MiB):
+            for chunk in [0] + [c for c in chunks if c >= 2]:
+                c = dict(default)
+                c[_lib.PC_TUNE_CHUNK] = chunk
+                c[_lib.PC_TUNE_SCRATCH] = scratch
+                if c != default:
+                    out.append(c)
+    else:
+        for overlap in ((0, 1) if allow_overlap else (0,)):
+            for chunk in [0] + chunks:
+                c = dict(default)
+                c[_lib.PC_TUNE_CHUNK] = chunk
+                c[_lib.PC_TUNE_OVERLAP] = overlap
+                if c != default:
+                    out.append(c)
+    return out
+
+
+def _key(op, B, adjoint):
+    st = op.stats()
+    return f"d{op.d}_N{op.N}_items{st['n_items']}_dt{int(op.torch_dtype == torch.float64)}_B{B}_adj{int(adjoint)}"
+
+
+def _apply_settings(op, setting):
+    for k, v in setting.items():
+        op.set_tuning(int(k), int(v))
+
+
+def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=True):
+    """Times every candidate schedule for applying op (adjoint: its adjoint)
+    to the batch U into OUT, leaves the fastest one set on op and returns
+    {"best": {key: value}, "best_ms": t, "default_ms": t0, "table": [...]}.
+    Raises if two schedules disagree bitwise."""
+    B = 1 if U.dim() == 1 else U.shape[0]
+    key = _key(op, B, adjoint) + ("" if allow_overlap else "_noovl")
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            best = {int(k): v for k, v in cache[key]["best"].items()}
+            _apply_settings(op, best)
+            return cache[key]
+    fn = op.apply_adjoint_batch if adjoint else op.apply_batch
+    ref = None
+    table = []
+    for setting in candidates(op, B, allow_overlap):
+        _apply_settings(op, setting)
+        fn(U, OUT)   # sizes the work buffers for this schedule
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = OUT.clone()
+        elif not torch.equal(OUT, ref):
+            raise RuntimeError(f"schedule {setting} changed the result")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            fn(U, OUT)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = min(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        table.append({"setting": {str(k): v for k, v in setting.items()}, "ms": ms})
+    best = min(table, key=lambda r: r["ms"])
+    res = {"best": best["setting"], "best_ms": best["ms"], "default_ms": table[0]["ms"], "table": table}
+    _apply_settings(op, {int(k): v for k, v in best["setting"].items()})
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        cache[key] = res
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return res
+
+
+def names(setting):
+    """Readable form of a setting: {"chunk": .., "overlap": .., "scratch_MiB": ..}."""
+    s = {int(k): v for k, v in setting.items()}
+    return {"chunk": s.get(_lib.PC_TUNE_CHUNK, 0), "overlap": s.get(_lib.PC_TUNE_OVERLAP, 0),
+            "scratch_MiB": s.get(_lib.PC_TUNE_SCRATCH, 0) // _MiB}

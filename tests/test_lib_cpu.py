@@ -313,3 +313,17 @@ def test_emulated_kernels_under_address_sanitizer():
     env = dict(os.environ, LD_PRELOAD=asan_rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0 and "ASAN-CLEAN" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
+
+
+def test_autotune_candidates():
+    """The autotuner's candidate schedules: the library default first, no
+    duplicates, 3-D candidates vary chunk and scratch, 2-D chunk and overlap."""
+    import types
+    from paper_1805_06018_amd import _lib, tune
+    for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP}), (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
+        c = tune.candidates(types.SimpleNamespace(d=d), 16)
+        assert all(v == 0 for v in c[0].values())
+        assert len({tuple(sorted(x.items())) for x in c}) == len(c)
+        varied = {k for x in c for k, v in x.items() if v != 0}
+        assert varied == keys, (d, varied)
+        assert all(1 <= x[_lib.PC_TUNE_CHUNK] <= 16 for x in c if x[_lib.PC_TUNE_CHUNK])
