@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kPlaneThreads) void plane_fwd_kernel(Conv3Args<T> A
                                    A.wts, A.spec, A.tw, A.pitch, A.plane_pitch);
     const int tid = threadIdx.x;
     twiddles_to_lds(c, buf + (int64_t)I.p.n0 * I.p.ld, tid, NT);
-    phA0(c, buf, tid, NT);
+    phA0<16>(c, buf, tid, NT);
     __syncthreads();
     phA(c, buf, tid, NT);
     __syncthreads();
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kPlaneThreads) void plane_inv_kernel(Conv3Args<T> A
     __syncthreads();
     phG(c, buf, tid, NT);
     __syncthreads();
-    phH(c, buf, tid, NT);
+    phH<8>(c, buf, tid, NT);
 }
 
 template <class T>

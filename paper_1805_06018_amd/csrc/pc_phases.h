@@ -161,9 +161,10 @@ constexpr int kMaxRowPass2Radix = 10;
 // sum: each gathered row holds the real samples 0..2m-1 (zero outside the
 // box) as m complex (even, odd) pairs.  A fixed set of threads owns each
 // column, so consecutive lanes read consecutive input columns.
-template <class T>
+// U: rows whose loads are in flight together (registers allowing: 8 in the
+// 1024-thread kernel, 16 in the 256-thread plane kernels).
+template <int U = 8, class T>
 __host__ __device__ inline void phA0(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    constexpr int U = 8;                 // rows whose loads are in flight together
     const int n = 2 * c.it.m;            // real samples per row
     const int rps = nth / n;             // rows per sweep (n <= 256 <= nth)
     const int r0 = tid / n, col = tid - r0 * n;
@@ -175,20 +176,22 @@ __host__ __device__ inline void phA0(const Ctx<T>& c, cx<T>* buf, int tid, int n
     const int rstride = 2 * c.it.ld;
     const T* src = c.src + (int64_t)(c.it.g0 + c.s_off0) * c.pitch + c.it.g1 + col;
     const T* w = c.w + e;
-    int q = r0;
-    for (; q + (U - 1) * rps < c.s_n0; q += U * rps) {
+    // predicated batches: every row of a batch is loaded before any is used
+    for (int q = r0; q < c.s_n0; q += U * rps) {
         T v[U], f[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = live ? src[(int64_t)(q + u * rps) * c.pitch] : T(0);
+        for (int u = 0; u < U; ++u) {
+            const int r = q + u * rps;
+            v[u] = (live && r < c.s_n0) ? src[(int64_t)r * c.pitch] : T(0);
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) f[u] = wgt ? w[(int64_t)(q + u * rps) * c.it.w_ld] : T(1);
+        for (int u = 0; u < U; ++u) {
+            const int r = q + u * rps;
+            f[u] = (wgt && r < c.s_n0) ? w[(int64_t)r * c.it.w_ld] : T(1);
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) rows[(q + u * rps) * rstride] = v[u] * f[u];
-    }
-    for (; q < c.s_n0; q += rps) {
-        T v = live ? src[(int64_t)q * c.pitch] : T(0);
-        if (wgt) v *= w[(int64_t)q * c.it.w_ld];
-        rows[q * rstride] = v;
+        for (int u = 0; u < U; ++u)
+            if (q + u * rps < c.s_n0) rows[(q + u * rps) * rstride] = v[u] * f[u];
     }
 }
 
@@ -510,9 +513,8 @@ __host__ __device__ inline void phG(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 // adjoint).  A fixed set of threads owns each column of the box, so
 // consecutive lanes write consecutive staging elements and no index is
 // divided per element.
-template <class T>
+template <int U = 4, class T>
 __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
-    constexpr int U = 4;
     const int n1 = c.d_n1;
     const int rps = nth / n1;            // rows per sweep (n1 <= 256 <= nth)
     const int r0 = tid / n1, e = tid - r0 * n1;
@@ -521,20 +523,22 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     const int rstride = 2 * c.it.ld;
     const T* w = c.w + e;
     T* dst = c.dst + e;
-    int q = r0;
-    for (; q + (U - 1) * rps < c.d_n0; q += U * rps) {
+    // predicated batches of U rows: LDS reads (and adjoint weights) first
+    for (int q = r0; q < c.d_n0; q += U * rps) {
         T v[U], f[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = rows[(q + u * rps) * rstride];
+        for (int u = 0; u < U; ++u) {
+            const int r = q + u * rps;
+            v[u] = r < c.d_n0 ? rows[r * rstride] : T(0);
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) f[u] = c.adj ? w[(int64_t)(q + u * rps) * c.it.w_ld] : T(1);
+        for (int u = 0; u < U; ++u) {
+            const int r = q + u * rps;
+            f[u] = (c.adj && r < c.d_n0) ? w[(int64_t)r * c.it.w_ld] : T(1);
+        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) dst[(int64_t)(q + u * rps) * n1] = v[u] * f[u];
-    }
-    for (; q < c.d_n0; q += rps) {
-        T v = rows[q * rstride];
-        if (c.adj) v *= w[(int64_t)q * c.it.w_ld];
-        dst[(int64_t)q * n1] = v;
+        for (int u = 0; u < U; ++u)
+            if (q + u * rps < c.d_n0) dst[(int64_t)(q + u * rps) * n1] = v[u] * f[u];
     }
 }
 
