@@ -262,6 +262,17 @@ typedef struct {
 
 pc_status   pc_set_profiling(pc_op* op, int enable);
 
+/* pc_debug_fail_launches -- failure injection for tests of a caller's error
+ * handling (no GPU fault is involved).  Counting the operator's convolution
+ * launches from 1 after this call, launches first .. first + count - 1 fail
+ * with PC_ERR_DEVICE before anything of theirs is enqueued; earlier
+ * launches of the same call may have run, so its outputs are undefined.
+ * Unlike a real device error, an injected one leaves the operator usable.
+ * count = 0 disables (first is then ignored); otherwise first >= 1, else
+ * PC_ERR_ARG.  The environment variable PC_DEBUG_FAIL_LAUNCH=n, read by
+ * pc_create and pc_create_patches, has the effect of (n, 1). */
+pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
+
 /* Schedule knobs (defaults chosen by the library; an autotuner may override).
  *  PC_TUNE_CHUNK    vectors per convolution launch (0 = library default:
  *                   as many as fit a 2 GiB staging buffer; 3-D operators

@@ -66,6 +66,8 @@ _lib.pc_error_estimate.argtypes = [_P, _I64, _P, _I64, _P, _I64, MATVEC_FN, _P, 
 _lib.pc_error_estimate.restype = ctypes.c_int
 _lib.pc_get_stats.argtypes = [_P, ctypes.POINTER(PcStats)]
 _lib.pc_get_stats.restype = ctypes.c_int
+_lib.pc_debug_fail_launches.argtypes = [_P, _I64, _I64]
+_lib.pc_debug_fail_launches.restype = ctypes.c_int
 _lib.pc_set_profiling.argtypes = [_P, ctypes.c_int]
 _lib.pc_set_profiling.restype = ctypes.c_int
 _lib.pc_set_tuning.argtypes = [_P, ctypes.c_int, _I64]
@@ -85,7 +87,7 @@ _lib.pc_last_error.restype = ctypes.c_char_p
 EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
             "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_apply_block", "pc_entries",
             "pc_estimate_sums",
-            "pc_error_estimate", "pc_get_stats", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
+            "pc_error_estimate", "pc_get_stats", "pc_debug_fail_launches", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
 
 
@@ -273,6 +275,12 @@ class PcOperator:
         st = PcStats()
         _check(_lib.pc_get_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in PcStats._fields_}
+
+    def debug_fail_launches(self, first, count=1):
+        """Test hook: convolution launches first .. first + count - 1 from
+        now on fail with PcError (PC_ERR_DEVICE) before they are enqueued;
+        the operator stays usable.  count = 0 disables."""
+        _check(_lib.pc_debug_fail_launches(self._h, int(first), int(count)))
 
     def set_profiling(self, enable=True):
         _check(_lib.pc_set_profiling(self._h, int(bool(enable))))

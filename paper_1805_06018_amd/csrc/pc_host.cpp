@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -71,6 +72,7 @@ struct pc_op {
     void* ent_phiE = nullptr;
     // profiling: event pairs of launches not yet read
     bool profiling = false;
+    int64_t dbg_first = 0, dbg_count = 0, dbg_seen = 0;   // injected launch failures (test hook)
     struct Timed {
         hipEvent_t a, b;
         int kind;        // 0 conv, 1 reduce
@@ -175,6 +177,16 @@ void prof_end(pc_op* op, hipStream_t s, hipEvent_t start, int kind, int vectors)
     op->timed.push_back({start, e, kind, vectors});
 }
 
+// Test hook: the operator's convolution launches numbered dbg_first ..
+// dbg_first + dbg_count - 1 (counted from the last pc_debug_fail_launches)
+// fail before anything of theirs is enqueued.
+bool injected_failure(pc_op* op) {
+    if (op->dbg_count <= 0) return false;
+    const int64_t k = ++op->dbg_seen;
+    return k >= op->dbg_first && k < op->dbg_first + op->dbg_count;
+}
+pc_status injected(void) { return fail(PC_ERR_DEVICE, "injected launch failure (pc_debug_fail_launches)"); }
+
 pc_status check_op(const pc_op* op) {
     if (!op) return fail(PC_ERR_ARG, "null operator");
     return PC_OK;
@@ -260,6 +272,7 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
             L.slots = op->slots;
             L.slot_stride = per;
             L.scratch = op->scratch;
+            if (injected_failure(op)) return injected();
             prof_begin(op, s, &ev);
             e = pc::launch_conv3(Dc, L, s);
             if (e != hipSuccess) return hip_fail(e, "3-D conv launch");
@@ -326,12 +339,14 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
         }
         if (plain) {
             for (int it = 0; it < n_items; ++it) {
+                if (injected_failure(op)) return injected();
                 prof_begin(op, s, &ev);
                 e = pc::launch_conv(op->dev, adj, it, it + 1, 1, in, ldu, slots, per, s);
                 if (e != hipSuccess) return hip_fail(e, "conv launch");
                 prof_end(op, s, ev, 0, 1);
             }
         } else {
+            if (injected_failure(op)) return injected();
             prof_begin(op, s, &ev);
             e = pc::launch_conv(op->dev, adj, 0, n_items, nb, in, ldu, slots, per, s);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
@@ -455,6 +470,13 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     }
     // spectra are only needed on the device from now on
     std::vector<double>().swap(P.spec);
+    if (const char* env = std::getenv("PC_DEBUG_FAIL_LAUNCH")) {   // test hook, as pc_debug_fail_launches(n, 1)
+        const long long n = std::atoll(env);
+        if (n > 0) {
+            op->dbg_first = n;
+            op->dbg_count = 1;
+        }
+    }
     *out = op;
     return PC_OK;
 }
@@ -648,6 +670,7 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     char* o = static_cast<char*>(OUT);
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        if (injected_failure(op)) return injected();
         e = pc::launch_conv(Dc, adjoint != 0, 0, Dc.n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu, op->slots,
                             bp.per, s);
         if (e != hipSuccess) return hip_fail(e, "block conv launch");
@@ -742,6 +765,16 @@ pc_status pc_get_stats(const pc_op* op, pc_stats* st) {
     st->device_bytes = (int64_t)op->resident;
     st->dtype = P.dtype;
     st->max_lds_bytes = P.max_lds;
+    return PC_OK;
+}
+
+pc_status pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    if (count < 0 || (count > 0 && first < 1)) return fail(PC_ERR_ARG, "first must be >= 1 and count >= 0");
+    op->dbg_first = first;
+    op->dbg_count = count;
+    op->dbg_seen = 0;
     return PC_OK;
 }
 

@@ -38,6 +38,9 @@ class Request:
     arrival: float       # seconds after the start of the run
     t_done: float = None
     result: object = None
+    retried: bool = False    # its batch failed once; it runs alone next
+    solo: bool = False
+    failed: bool = False     # failed again alone: result holds the error
 
 
 @dataclass
@@ -79,6 +82,23 @@ class Server:
         self.resident_bytes = sum(r.work_bytes for r in residents)
         if self.resident_bytes > self.budget:
             raise ValueError("resident operators exceed the HBM budget")
+        self.launch_failures = 0
+
+    def _failed(self, reqs, err, pending, t):
+        """A launch failed: nothing of it was enqueued and the operator stays
+        valid.  Every request of the batch goes back to the front of the
+        queue to run alone once more; a request whose own retry fails is
+        reported failed."""
+        self.launch_failures += 1
+        for q in reversed(reqs):
+            if q.retried:
+                q.result = f"failed: {err}"
+                q.failed = True
+                q.t_done = t
+            else:
+                q.retried = True
+                q.solo = True
+                pending.appendleft(q)
 
     def _launch_apply(self, op, reqs, stream, plain=False):
         r = self.ops[op]
@@ -142,12 +162,16 @@ class Server:
             stream = free[0]
             if mode != "batched":
                 q = pending.popleft()
-                if q.kind == "estimate":
-                    self._run_estimate(q, stream)
-                    q.t_done = now()
-                    batches.append(1)
+                try:
+                    if q.kind == "estimate":
+                        self._run_estimate(q, stream)
+                        q.t_done = now()
+                        batches.append(1)
+                        continue
+                    b = self._launch_apply(q.op, [q], stream, plain=(mode == "plain"))
+                except _lib.PcError as e:
+                    self._failed([q], e, pending, now())
                     continue
-                b = self._launch_apply(q.op, [q], stream, plain=(mode == "plain"))
                 inflight.append(b)
                 batches.append(1)
                 continue
@@ -157,7 +181,11 @@ class Server:
                 continue
             if head.kind == "estimate":
                 pending.remove(head)
-                self._run_estimate(head, stream)
+                try:
+                    self._run_estimate(head, stream)
+                except _lib.PcError as e:
+                    self._failed([head], e, pending, now())
+                    continue
                 head.t_done = now()
                 batches.append(1)
                 continue
@@ -166,6 +194,8 @@ class Server:
             for q in pending:
                 if q.op != head.op or q.kind != "apply":
                     continue
+                if take and (q.solo or head.solo):   # a retried request runs alone
+                    break
                 nb = 2 * (vecs + q.B) * r.N * 4
                 if vecs + q.B > self.max_batch or self.resident_bytes + inflight_bytes + nb > self.budget:
                     break
@@ -180,7 +210,11 @@ class Server:
                 continue
             for q in take:
                 pending.remove(q)
-            b = self._launch_apply(head.op, take, stream)
+            try:
+                b = self._launch_apply(head.op, take, stream)
+            except _lib.PcError as e:
+                self._failed(take, e, pending, now())
+                continue
             inflight.append(b)
             busy_ops.add(head.op)
             inflight_bytes += b.nbytes
@@ -189,6 +223,8 @@ class Server:
         t_end = now()
         out = summarize(reqs, t_end, batches, self.ops)
         out["peak_admitted_bytes"] = int(peak)
+        out["launch_failures"] = self.launch_failures
+        out["failed"] = sum(1 for q in reqs if q.failed)
         return out
 
 
@@ -198,6 +234,8 @@ def summarize(reqs, t_end, batches, ops):
     pts = 0
     rejected = 0
     for q in reqs:
+        if q.failed:
+            continue
         if isinstance(q.result, str):
             rejected += 1
             continue

@@ -52,3 +52,44 @@ def test_hbm_budget_admission(served):
             res[q.op].pc.apply_batch(res[q.op].U[:q.B], alone)
             torch.cuda.synchronize()
             assert torch.equal(alone, q.result)
+
+
+def test_failed_launch_is_isolated(served):
+    """Two injected launch failures on one operator (host-side test hook, no
+    kernel runs for them): the batch that hits the first is retried request
+    by request, the request whose retry hits the second is reported failed,
+    every other request completes with its alone result, and the operator
+    keeps working."""
+    serve, res = served
+    srv = serve.Server(res, hbm_budget=16 << 30)
+    reqs = serve.poisson_requests(40, len(res), 0.0, seed=8)
+    target = next(q.op for q in reqs if q.kind == "apply")
+    res[target].pc.debug_fail_launches(1, 2)
+    try:
+        out = srv.run(reqs, mode="batched")
+    finally:
+        res[target].pc.debug_fail_launches(0, 0)
+    assert out["launch_failures"] == 2 and out["failed"] == 1
+    failed = [q for q in reqs if q.failed]
+    assert failed[0].op == target and failed[0].result.startswith("failed:")
+    for q in reqs:
+        if q.failed:
+            continue
+        r = res[q.op]
+        if q.kind == "apply":
+            alone = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
+            r.pc.apply_batch(r.U[:q.B], alone)
+            torch.cuda.synchronize()
+            assert torch.equal(alone, q.result), q.rid
+        else:
+            eta, ea, er = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B])
+            assert np.array_equal(eta, q.result[0]) and ea == q.result[1] and er == q.result[2]
+    # the operator still applies correctly after the injected failures
+    q = failed[0]
+    r = res[q.op]
+    a = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    r.pc.apply_batch(r.U[:q.B], a)
+    r.pc.apply_batch_plain(r.U[:q.B], b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

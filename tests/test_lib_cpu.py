@@ -327,3 +327,10 @@ def test_autotune_candidates():
         varied = {k for x in c for k, v in x.items() if v != 0}
         assert varied == keys, (d, varied)
         assert all(1 <= x[_lib.PC_TUNE_CHUNK] <= 16 for x in c if x[_lib.PC_TUNE_CHUNK])
+
+
+def test_debug_fail_launches_validates_arguments():
+    """The failure-injection hook rejects a null operator and bad ranges (no
+    device work is needed to check the validation)."""
+    from paper_1805_06018_amd import _lib
+    assert _lib._lib.pc_debug_fail_launches(None, 1, 1) == _lib.PC_ERR_ARG
