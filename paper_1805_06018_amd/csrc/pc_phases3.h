@@ -72,7 +72,9 @@ template <class T>
 __host__ __device__ constexpr int copy_batch() { return sizeof(T) == 8 ? 1 : 8; }
 
 // LDS plane (n1 rows of m + 1 complex, row stride ld) <-> scratch plane
-// (row stride m + 1); consecutive threads on consecutive elements.
+// (row stride m + 1); consecutive threads on consecutive elements.  Scratch
+// is written once and read once, by the next kernel: the stores are
+// non-temporal (128^3 workload: 24.3 -> 23.5 ms per apply).
 template <class T>
 __host__ __device__ inline void plane_store(const Ctx<T>& c, const cx<T>* buf, cx<T>* dst, int tid, int nth) {
     constexpr int U = copy_batch<T>();
@@ -89,7 +91,10 @@ __host__ __device__ inline void plane_store(const Ctx<T>& c, const cx<T>* buf, c
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (t0 + u * nth < n) dst[t0 + u * nth] = v[u];
+            if (t0 + u * nth < n) {
+                __builtin_nontemporal_store(v[u].x, &dst[t0 + u * nth].x);
+                __builtin_nontemporal_store(v[u].y, &dst[t0 + u * nth].y);
+            }
     }
 }
 
@@ -201,7 +206,10 @@ __host__ __device__ inline void axis_store(const Ctx<T>& c, const cx<T>* buf, cx
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (gi[u] >= 0) sc[gi[u]] = v[u];
+            if (gi[u] >= 0) {
+                __builtin_nontemporal_store(v[u].x, &sc[gi[u]].x);
+                __builtin_nontemporal_store(v[u].y, &sc[gi[u]].y);
+            }
     }
 }
 
