@@ -179,11 +179,21 @@ def main():
     else:
         same = None
 
-    # the committed counter runs cover FP32 2-D launches of 8, 16 and 32 vectors
-    vec_per_launch = prof["conv_vectors"] / max(prof["conv_launches"], 1)
+    # per-launch HBM bytes: the committed counter runs cover the FP32 2-D
+    # launch sizes of every candidate schedule; a batch that the chunk does
+    # not divide ends with a shorter launch, so the bytes are averaged over
+    # the launches of one apply (as the launch time is)
     traffic = None
-    if not three_d and not f64 and vec_per_launch == int(vec_per_launch):
-        traffic = measured_traffic(int(vec_per_launch))
+    if not three_d and not f64:
+        per_vec = st["slot_elems_fwd"] * esz
+        cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's 2 GiB staging cap
+        chunk = schedule.get("chosen", {}).get("chunk", 0) if schedule["autotuned"] else 0
+        chunk = min(cap, chunk if chunk > 0 else B)
+        sizes = [chunk] * (B // chunk) + ([B % chunk] if B % chunk else [])
+        if len(sizes) == prof["conv_launches"] / args.steps:
+            per = [measured_traffic(v) for v in sizes]
+            if all(x is not None for x in per):
+                traffic = sum(per) / len(per)
 
     if three_d:
         wl = f"blur3d_128x128x128_tensor9_r{w.r}_b{B}"

@@ -26,7 +26,10 @@ def candidates(op, B, allow_overlap=True):
     what per-kernel timing needs)."""
     default = {_lib.PC_TUNE_CHUNK: 0, _lib.PC_TUNE_OVERLAP: 0, _lib.PC_TUNE_SCRATCH: 0}
     out = [dict(default)]
-    chunks = sorted({c for c in (B // 8, B // 4, B // 2, B) if 1 <= c <= B})
+    # powers of two and the sizes in between (for B = 64: 8, 10, 12, 16, 20,
+    # 22, 24, 28, 32, 64); a batch that a chunk does not divide ends with a
+    # shorter launch
+    chunks = sorted({c for c in (B * k // 64 for k in (8, 10, 12, 16, 20, 22, 24, 28, 32, 64)) if 1 <= c <= B})
     if op.d == 3:
         for scratch in (0, 128 * _MiB, 256 * _MiB, 1024 * _MiB):
             for chunk in [0] + [c for c in chunks if c >= 2]:
