@@ -71,7 +71,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the path has no multi-GPU mode in this build", file=sys.stderr)
+              "the library has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

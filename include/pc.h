@@ -61,7 +61,7 @@ typedef enum {
     PC_ERR_BUDGET = 4,       /* request exceeds a configured memory budget             */
     PC_ERR_DEVICE = 5,       /* a HIP call failed; destroy the operator                */
     PC_ERR_CALLBACK = 6,     /* the user's exact-adjoint callback returned non-zero    */
-    PC_ERR_UNSUPPORTED = 7   /* valid input outside what this build implements         */
+    PC_ERR_UNSUPPORTED = 7   /* valid input outside what the library implements       */
 } pc_status;
 
 typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
