@@ -179,6 +179,21 @@ def main():
     else:
         same = None
 
+    # context for the HBM readings: the rate of a plain device-to-device copy
+    # of 1 GiB (four times the 256 MB last-level cache), read plus write bytes
+    cp_src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    cp_dst = torch.empty_like(cp_src)
+    for _ in range(3):
+        cp_dst.copy_(cp_src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(20):
+        cp_dst.copy_(cp_src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_tbps = 2 * cp_src.numel() * 4 * 20 / (c0.elapsed_time(c1) * 1e-3) / 1e12
+    del cp_src, cp_dst
+
     # per-launch HBM bytes: the committed counter runs cover the FP32 2-D
     # launch sizes of every candidate schedule; a batch that the chunk does
     # not divide ends with a shorter launch, so the bytes are averaged over
@@ -222,6 +237,7 @@ def main():
                     "reduce_ms_per_step": prof["reduce_ms"] / args.steps,
                     "alg_flops_per_vector": st["alg_flops_per_rhs"]},
         "hbm_alg_frac": alg_bytes_step / (ms_step * 1e-3) / PEAK_HBM,
+        "hbm_copy_TBps": copy_tbps,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "applies": int(lat.size)},
         "graph": graph,
