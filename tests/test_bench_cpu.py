@@ -1,0 +1,31 @@
+"""Host-side checks of bench.py: the one-GPU contract and the committed
+counter figures it reports as HBM traffic."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_figures_match_the_current_sources():
+    # the counter table covers every launch size the autotuner can pick for
+    # the 64-vector 1024^2 workload, and only while the kernel and planner
+    # sources are the ones the counters were taken on
+    for v in (4, 8, 10, 12, 16, 20, 22, 24, 28, 32):
+        t = bench.measured_traffic(v)
+        assert t is not None, v
+        assert 1e8 < t < 1e10
+    assert bench.measured_traffic(7) is None
+    per_vec = [bench.measured_traffic(v) / v for v in (8, 16, 32)]
+    assert max(per_vec) / min(per_vec) < 1.25   # bytes grow with the vectors of a launch
