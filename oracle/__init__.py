@@ -15,6 +15,10 @@ Modules
   estimator  randomized a-posteriori estimator eta_C                     (Sec. 2.6)
   direct     ctypes wrapper of a plain C direct-summation core (same sums,
              used where NumPy loops are too slow)
+
+Parity unpinned: the extension's treatment of neighbours supplied on boxes of
+unequal radii (a reading of Sec. 2.5; see extension).  Everything else is
+pinned by the tests against worked values, closed forms and brute force.
 """
 from .grid import Grid, TilingError
 from .weights import harmonic_weights, leaf_weights
