@@ -129,6 +129,43 @@ def test_full_size_blur1024_batch64(lib):
     assert ea <= 1e-5, ea
 
 
+def test_full_size_blur1024_fp64(lib):
+    """The 1024^2 workload with an FP64 operator (512-thread kernel, FP64 row
+    pieces): 9 vectors, so the default 8-vector launches end with a ragged
+    1-vector launch; vector 0 against the full oracle apply, vectors 1 and 8
+    at sampled outputs, and the adjoint of vector 8 at sampled inputs."""
+    w = make_config(1)
+    _note(f"blur1024 fp64: r={w.r}")
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F64)
+    U = w.vectors(9, dtype=np.float64)
+    Ud = torch.from_numpy(U).cuda()
+    out = torch.zeros_like(Ud)
+    op.apply_batch(Ud, out)
+    outa = torch.zeros_like(Ud)
+    op.apply_adjoint_batch(Ud, outa)
+    torch.cuda.synchronize()
+    got, gota = out.cpu().numpy(), outa.cpu().numpy()
+    assert np.all(np.isfinite(got)) and np.all(np.isfinite(gota))
+    ora = OracleOperator.from_workload(w)
+    _note("oracle apply of vector 0")
+    ref0 = ora.apply(U[0])
+    e0 = np.linalg.norm(got[0] - ref0) / np.linalg.norm(ref0)
+    assert e0 <= 1e-12, e0
+    rng = np.random.default_rng(11)
+    ys = np.stack([rng.integers(0, 1024, 24), rng.integers(0, 1024, 24)], axis=1)
+    ys = np.vstack([ys, [[0, 0], [1023, 1023], [0, 1023], [1023, 0], [511, 512]]])
+    flat = ys[:, 0] * 1024 + ys[:, 1]
+    scale = np.abs(ref0).max()
+    for j in (1, 8):
+        refj = ora.apply_at(U[j], ys)
+        err = np.abs(got[j, flat] - refj).max() / scale
+        assert err <= 1e-12, (j, err)
+    _note("oracle adjoint of vector 8")
+    refa = ora.apply_adjoint(U[8])
+    ea = np.linalg.norm(gota[8] - refa) / np.linalg.norm(refa)
+    assert ea <= 1e-12, ea
+
+
 class _DevView:
     """A device array view built from a raw pointer (for the callback)."""
 
