@@ -16,9 +16,9 @@ Modules
   direct     ctypes wrapper of a plain C direct-summation core (same sums,
              used where NumPy loops are too slow)
 
-Parity unpinned: the extension's treatment of neighbours supplied on boxes of
-unequal radii (a reading of Sec. 2.5; see extension).  Everything else is
-pinned by the tests against worked values, closed forms and brute force.
+Every part is pinned by the tests against worked values, closed forms and
+brute force; the extension with neighbours supplied on boxes of unequal radii
+by hand-derived values (tests/golden/extension_unequal_radii.txt).
 """
 from .grid import Grid, TilingError
 from .weights import harmonic_weights, leaf_weights

@@ -14,11 +14,11 @@ phi_k^E is only ever evaluated at offsets y - x with y in Omega and x in U_k,
 so it is stored on Zbox_k = (Omega - bbox(U_k)) intersected with the union of
 the neighbours' patch boxes; it is zero outside.
 
-Parity unpinned: where neighbours were supplied on boxes of unequal radii, a
-neighbour counts in the average wherever its domain of definition covers the
-offset, also where its supplied box does not (it contributes 0 there).  The
-paper does not fix this case; it is a reading, checked only against the
-library.  The rest of the extension is pinned by worked values (tests/golden).
+Where neighbours were supplied on boxes of unequal radii, a neighbour counts
+in the average wherever its domain of definition covers the offset, also where
+its supplied box does not (it contributes 0 there): Sec. 2.5 states
+supp(phi_j) = Omega - p_j for the counting function c_k.  Pinned by
+hand-derived values with equal and with unequal radii (tests/golden).
 """
 import numpy as np
 

@@ -2,7 +2,7 @@
 import numpy as np
 
 from workloads import make_config, cosine_field
-from tests.tilings import hanging_2d, hanging_3d, const_blur, workload_from, tensor
+from tests.tilings import hanging_2d, hanging_3d, const_blur, workload_from, tensor, unequal_radii_3x3
 
 # Per-vector relative L2 bars against the FP64 oracle.
 TOL = {0: 1e-5, 1: 1e-12}     # PC_F32, PC_F64
@@ -35,6 +35,8 @@ def small_cases():
     s = 2.0 + 3.0 * (x0 / 69.0)
     cases.append(("oneleaf70", workload_from(np.stack([s, s]), lo, hi)))
     cases.append(("cfg1_small", make_config(1, scale=0.25)))
+    # the unequal-radii extension golden's tiling (radii 1, 2, 3 side by side)
+    cases.append(("unequal3x3", unequal_radii_3x3()))
     return cases
 
 

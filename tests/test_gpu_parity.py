@@ -39,7 +39,7 @@ def _dt(dtype):
     return (torch.float64, np.float64) if dtype == 1 else (torch.float32, np.float32)
 
 
-@pytest.mark.parametrize("idx", range(6))
+@pytest.mark.parametrize("idx", range(7))
 def test_small_cases_parity(lib, idx):
     name, w = small_cases()[idx]
     rng = np.random.default_rng(200 + idx)

@@ -115,7 +115,7 @@ def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None):
     return out
 
 
-@pytest.mark.parametrize("idx", range(9))
+@pytest.mark.parametrize("idx", range(10))
 def test_emulated_kernels_match_oracle(idx):
     name, w = (small_cases() + small_cases_3d())[idx]
     lib = _emu_lib()

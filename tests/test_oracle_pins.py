@@ -14,7 +14,8 @@ from oracle import OracleOperator, Grid, TilingError, estimate, harmonic_weights
 from oracle.extension import extended_kernels, split_weights
 from oracle.weights import leaf_weights, harmonic_on_box
 from workloads import make_config, BlurOperator, uniform_nodes, tensor_leaves
-from tests.tilings import hanging_2d, hanging_3d, extrude, const_blur, workload_from, tensor, refine
+from tests.tilings import (hanging_2d, hanging_3d, extrude, const_blur, workload_from, tensor, refine,
+                           unequal_radii_3x3)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -182,19 +183,14 @@ def test_3d_broken_facets_are_discrete_harmonic_and_continuous():
 
 
 # ---------------------------------------------------------------- extension (Sec. 2.5)
-def test_golden_extension_values():
-    lo, hi = tensor_leaves([[0, 1, 2], [0, 1, 2]])
-    g = Grid((3, 3), lo, hi)
-    R = np.full((9, 2), 2)
-    phi, off = [], [0]
-    for j in range(9):
-        z0, z1 = np.meshgrid(np.arange(-2, 3), np.arange(-2, 3), indexing="ij")
-        blk = 100.0 * (j + 1) + 10.0 * (z0 + 2) + (z1 + 2)
-        phi.append(blk.ravel())
-        off.append(off[-1] + blk.size)
-    phi = np.concatenate(phi)
-    off = np.array(off)
-    rows = np.loadtxt(os.path.join(GOLD, "extension_2d_3x3.txt"))
+def _golden_extension_case(radii, c):
+    w = unequal_radii_3x3(radii, c)
+    return Grid(w.shape, w.leaf_lo, w.leaf_hi), w.radius, w.phi, w.phi_off
+
+
+def _check_golden_extension(fname, radii, c):
+    g, R, phi, off = _golden_extension_case(radii, c)
+    rows = np.loadtxt(os.path.join(GOLD, fname))
     for extend, col in ((True, 3), (False, 4)):
         zlo, K = extended_kernels(g, R, phi, off, extend=extend)
         for row in rows:
@@ -204,7 +200,42 @@ def test_golden_extension_values():
                 val = 0.0
             else:
                 val = K[k][tuple(idx)]
-            assert val == row[col], (extend, k, z, val, row[col])
+            assert val == row[col], (fname, extend, k, z, val, row[col])
+
+
+UNEQUAL_RADII = [1, 2, 3, 2, 3, 1, 3, 1, 2]
+
+
+@pytest.mark.parametrize("fname,radii,c", [("extension_2d_3x3.txt", [2] * 9, 2),
+                                           ("extension_unequal_radii.txt", UNEQUAL_RADII, 3)])
+def test_golden_extension_values(fname, radii, c):
+    """Hand-derived phi_k^E (Sec. 2.5, eq. (2.7)-(2.8)) with equal and with
+    unequal neighbour radii (tests/golden)."""
+    _check_golden_extension(fname, radii, c)
+
+
+def test_golden_unequal_radii_rejects_box_support(monkeypatch):
+    """Planting the other reading in the oracle (a neighbour counts only where
+    its supplied box covers z) must break the unequal-radii golden: the pin
+    fixes the paper's supp(phi_j) = Omega - p_j."""
+    import oracle.extension as ext
+    g, R, _, _ = _golden_extension_case(UNEQUAL_RADII, 3)
+    rad = {tuple(int(v) for v in g.points[j]): int(R[j, 0]) for j in range(g.r)}
+    plain = ext._defined_mask
+
+    def box_mask(shape, p, zlo, zshape):
+        m = plain(shape, p, zlo, zshape)
+        r = rad[tuple(int(v) for v in p)]
+        for i in range(len(zlo)):
+            z = np.arange(zlo[i], zlo[i] + zshape[i])
+            sh = [1] * len(zlo)
+            sh[i] = zshape[i]
+            m = m & (np.abs(z) <= r).reshape(sh)
+        return m
+
+    monkeypatch.setattr(ext, "_defined_mask", box_mask)
+    with pytest.raises(AssertionError):
+        _check_golden_extension("extension_unequal_radii.txt", UNEQUAL_RADII, 3)
 
 
 def test_lemma2_split_weights_sum():

@@ -80,3 +80,21 @@ def extrude(lo2, hi2, znodes):
     lo, hi = np.array(lo, dtype=np.int64), np.array(hi, dtype=np.int64)
     order = np.lexsort(lo.T[::-1])
     return lo[order], hi[order]
+
+
+def unequal_radii_3x3(radii=(1, 2, 3, 2, 3, 1, 3, 1, 2), c=3):
+    """Omega = [0,2]^2 with four 1x1 leaves and the 3x3 sample points; point
+    k = 3a + b at (a, b) has the patch phi_k[z] = 100 (k+1) + 10 (z0+c) +
+    (z1+c) on the box |z_i| <= R_k (the extension goldens' tiling)."""
+    lo, hi = tensor_leaves([[0, 1, 2], [0, 1, 2]])
+    pts = corner_points(lo, hi)
+    R = np.repeat(np.asarray(radii, dtype=np.int64)[:, None], 2, axis=1)
+    phi, off = [], [0]
+    for j in range(9):
+        r = int(radii[j])
+        z0, z1 = np.meshgrid(np.arange(-r, r + 1), np.arange(-r, r + 1), indexing="ij")
+        blk = 100.0 * (j + 1) + 10.0 * (z0 + c) + (z1 + c)
+        phi.append(blk.ravel())
+        off.append(off[-1] + blk.size)
+    return Workload("unequal3x3", 2, (3, 3), lo, hi, pts, R, np.concatenate(phi),
+                    np.array(off, dtype=np.int64), None, 1, 0, {})
