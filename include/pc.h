@@ -153,6 +153,24 @@ pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ld
 pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu,
                                void* OUT, int64_t ldo, hipStream_t s);
 
+/* pc_apply_batch_noalloc -- pc_apply_batch for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same result,
+ * bit for bit, as pc_apply_batch.  Instead of the operator's grown work
+ * buffers it uses a fixed work area of 128 MiB per device, set up by the
+ * first pc_create on that device and held until the process ends; it
+ * allocates and frees nothing and creates no HIP objects.  Vectors run in
+ * chunks whose staging fits the area (3-D operators: one vector at a time,
+ * its staging plus the plane scratch of each item group).  An operator
+ * whose staging for one vector (or, in 3-D, one item's scratch beside it)
+ * does not fit returns PC_ERR_UNSUPPORTED before anything is enqueued; the
+ * 1024^2 blur with ~600 points needs 65 MB per vector in FP32.  All calls
+ * on one device share the area and each call leaves its contents behind:
+ * calls that may overlap on the device (different streams, or a replayed
+ * graph beside an eager call) race and must be serialised by the caller. */
+pc_status pc_apply_batch_noalloc(pc_op* op, int64_t B, const void* U, int64_t ldu,
+                                 void* OUT, int64_t ldo, hipStream_t s);
+
 /* pc_apply_batch_axpy / pc_apply_adjoint_batch_axpy -- OUT[:, j] += alpha *
  * A~ U[:, j] (eq. (2.5)) or OUT[:, j] += alpha * A~* V[:, j] (eq. (1.6)):
  * the deterministic patch sum of every output point is formed first, then

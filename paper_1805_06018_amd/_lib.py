@@ -50,7 +50,7 @@ _lib.pc_create_patches.argtypes = [ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P,
 _lib.pc_create_patches.restype = ctypes.c_int
 _lib.pc_apply.argtypes = [_P, _P, _P, _P]
 _lib.pc_apply.restype = ctypes.c_int
-for _name in ("pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain"):
+for _name in ("pc_apply_batch", "pc_apply_adjoint_batch", "pc_apply_batch_plain", "pc_apply_batch_noalloc"):
     getattr(_lib, _name).argtypes = [_P, _I64, _P, _I64, _P, _I64, _P]
     getattr(_lib, _name).restype = ctypes.c_int
 for _name in ("pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy"):
@@ -85,7 +85,7 @@ _lib.pc_last_error.argtypes = []
 _lib.pc_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
-            "pc_apply_batch_plain", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_apply_block", "pc_entries",
+            "pc_apply_batch_plain", "pc_apply_batch_noalloc", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_apply_block", "pc_entries",
             "pc_estimate_sums",
             "pc_error_estimate", "pc_get_stats", "pc_debug_fail_launches", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
@@ -187,6 +187,11 @@ class PcOperator:
 
     def apply_batch_plain(self, U, OUT, stream=None):
         return self._batch(_lib.pc_apply_batch_plain, U, OUT, stream)
+
+    def apply_batch_noalloc(self, U, OUT, stream=None):
+        """pc_apply_batch_noalloc: the batched apply on the device's fixed
+        work area (no allocation in the call)."""
+        return self._batch(_lib.pc_apply_batch_noalloc, U, OUT, stream)
 
     def graph(self, U, OUT, adjoint=False):
         """Records one batched apply (adjoint: A~* apply) from U into OUT as a

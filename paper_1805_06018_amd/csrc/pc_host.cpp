@@ -204,23 +204,36 @@ pc_status ensure_aux(pc_op* op) {
     return PC_OK;
 }
 
+// Caller-supplied work buffers (the allocation-free entry point): staging of
+// 'chunk' vectors at 'slots', then 3-D scratch of at most scratch_cap bytes.
+struct ExtBufs {
+    void* slots;
+    int64_t chunk;
+    void* scratch;
+    size_t scratch_cap;
+};
+
 // 3-D: vector chunks sized by the staging buffer; within a chunk, contiguous
 // item groups sized by the scratch buffer each run the three kernels of
 // pc_phases3.h; one reduction per chunk.  items: host copy of the items Dc
 // points to (the operator's, or a block apply's); Dr: the reduction tables.
+// ext: null, or buffers to use instead of the operator's (nothing is
+// allocated then; PC_ERR_UNSUPPORTED if one item's scratch exceeds them).
 pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPlan& Dc, const pc::DevPlan& Dr,
                  int64_t per, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
-                 hipStream_t s, bool acc, double alpha) {
+                 hipStream_t s, bool acc, double alpha, const ExtBufs* ext = nullptr) {
     const pc::Plan& P = op->plan;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     const size_t cx_bytes = 2 * op->esz;
     int64_t chunk = 1;
-    if (!plain) {
+    if (ext) {
+        chunk = std::min<int64_t>(ext->chunk, B);
+    } else if (!plain) {
         // an explicit chunk overrides the default staging cap
         const int64_t cap = (int64_t)std::max<size_t>(1, kSlotCapBytes / per_bytes);
         chunk = op->tune_chunk > 0 ? std::min<int64_t>(op->tune_chunk, B) : std::min<int64_t>(cap, B);
     }
-    const size_t scap = op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
+    const size_t scap = ext ? ext->scratch_cap : op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
     const int n = (int)items.size();
     const int cols = pc::axis_cols(P.dtype);
     auto scratch_of = [&](int i) { return items[(size_t)i].scratch_off; };
@@ -251,11 +264,25 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
         groups.push_back(L);
         i = j;
     }
-    const bool cap = capturing(s);
-    pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)", cap);
-    if (st != PC_OK) return st;
-    st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)", cap);
-    if (st != PC_OK) return st;
+    void* slots = nullptr;
+    void* scratch = nullptr;
+    if (ext) {
+        if (scratch_need > ext->scratch_cap)
+            return fail(PC_ERR_UNSUPPORTED, "one 3-D work item needs " + std::to_string(scratch_need) +
+                                                " bytes of plane scratch; the allocation-free work area leaves " +
+                                                std::to_string(ext->scratch_cap));
+        slots = ext->slots;
+        scratch = ext->scratch;
+    } else {
+        const bool cap = capturing(s);
+        pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)", cap);
+        if (st != PC_OK) return st;
+        st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)",
+                    cap);
+        if (st != PC_OK) return st;
+        slots = op->slots;
+        scratch = op->scratch;
+    }
     const char* u = static_cast<const char*>(U);
     char* o = static_cast<char*>(OUT);
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
@@ -269,9 +296,9 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
             L.B = nb;
             L.in = in;
             L.ld_in = ldu;
-            L.slots = op->slots;
+            L.slots = slots;
             L.slot_stride = per;
-            L.scratch = op->scratch;
+            L.scratch = scratch;
             if (injected_failure(op)) return injected();
             prof_begin(op, s, &ev);
             e = pc::launch_conv3(Dc, L, s);
@@ -279,7 +306,7 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
             prof_end(op, s, ev, 0, g == 0 ? nb : 0);
         }
         prof_begin(op, s, &ev);
-        e = pc::launch_reduce(Dr, adj, nb, op->slots, per, out, ldo, s, acc, alpha);
+        e = pc::launch_reduce(Dr, adj, nb, slots, per, out, ldo, s, acc, alpha);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
         prof_end(op, s, ev, 1, nb);
     }
@@ -421,6 +448,11 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     if (e != hipSuccess) {
         delete op;
         return hip_fail(e, "hipFuncSetAttribute");
+    }
+    e = pc::noalloc_area_init(op->device);   // once per device, this device current
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipGetSymbolAddress (allocation-free work area)");
     }
     op->esz = (dtype == PC_F64) ? 8 : 4;
     pc::Plan& P = op->plan;
@@ -590,6 +622,52 @@ pc_status pc_apply_adjoint_batch(pc_op* op, int64_t B, const void* V, int64_t ld
 pc_status pc_apply_batch_plain(pc_op* op, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
                                hipStream_t s) {
     return run_batch(op, false, true, B, U, ldu, OUT, ldo, s);
+}
+
+pc_status pc_apply_batch_noalloc(pc_op* op, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                                 hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    const pc::Plan& P = op->plan;
+    if (B < 0) return fail(PC_ERR_ARG, "negative batch size");
+    if (B == 0) return PC_OK;
+    if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
+    if (ldu < P.N || ldo < P.N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
+    if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
+    char* area = static_cast<char*>(pc::noalloc_area(op->device));
+    if (!area) return fail(PC_ERR_DEVICE, "the allocation-free work area of this device was not set up");
+    const size_t per_bytes = (size_t)std::max<int64_t>(P.slot_fwd, 1) * op->esz;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    if (al(per_bytes) > pc::kNoAllocBytes)
+        return fail(PC_ERR_UNSUPPORTED, "one vector needs " + std::to_string(per_bytes) +
+                                            " bytes of staging; the allocation-free work area holds " +
+                                            std::to_string(pc::kNoAllocBytes));
+    struct NoProfiling {   // no event objects are created on this path
+        pc_op* op;
+        bool was;
+        ~NoProfiling() { op->profiling = was; }
+    } guard{op, op->profiling};
+    op->profiling = false;
+    if (P.d == 3) {
+        // one vector at a time: its staging first, the plane scratch behind it
+        ExtBufs ext{area, 1, area + al(per_bytes), pc::kNoAllocBytes - al(per_bytes)};
+        return run_3d(op, P.items3, op->dev, op->dev, P.slot_fwd, false, false, B, U, ldu, OUT, ldo, s, false, 1.0,
+                      &ext);
+    }
+    const int64_t chunk = std::min<int64_t>(B, (int64_t)(pc::kNoAllocBytes / per_bytes));
+    const int n_items = (int)P.items.size();
+    const char* u = static_cast<const char*>(U);
+    char* o = static_cast<char*>(OUT);
+    for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        if (injected_failure(op)) return injected();
+        hipError_t e = pc::launch_conv(op->dev, false, 0, n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu, area,
+                                       P.slot_fwd, s);
+        if (e != hipSuccess) return hip_fail(e, "conv launch");
+        e = pc::launch_reduce(op->dev, false, nb, area, P.slot_fwd, o + (size_t)b0 * ldo * op->esz, ldo, s);
+        if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    }
+    return PC_OK;
 }
 
 pc_status pc_apply_batch_axpy(pc_op* op, int64_t B, const void* U, int64_t ldu, double alpha, void* OUT, int64_t ldo,

@@ -72,4 +72,13 @@ hipError_t launch_entries(const EntryTables& E, int dtype, const void* wts, cons
 
 hipError_t set_kernel_attributes();
 
+// Work area of the allocation-free entry point (pc_apply_batch_noalloc):
+// kNoAllocBytes of device memory per device, shared by every operator on
+// that device.  noalloc_area_init(device) looks up the area's device
+// address with 'device' current (once per device; later calls return at
+// once); noalloc_area(device) returns it, or null before the lookup.
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+hipError_t noalloc_area_init(int device);
+void* noalloc_area(int device);
+
 }  // namespace pc

@@ -1,9 +1,47 @@
 // HIP kernels of the product-convolution apply for gfx950.
+#include <mutex>
+
 #include "pc_kernels.h"
 #include "pc_entries.h"
 #include "pc_phases3.h"
 
 namespace pc {
+
+// ------------------------------------------------- allocation-free work area
+// Staging and 3-D scratch of pc_apply_batch_noalloc: a file-scope device
+// array, one copy per device, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address of each device's copy is looked up once,
+// with that device current, and kept per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_area_mu;
+void* g_area[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_area_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_area_mu);
+    if (g_area[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes the device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_area[device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_area(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_area_mu);
+    return g_area[device];
+}
 
 template <class T>
 struct ConvArgs {
