@@ -119,6 +119,45 @@ class OracleOperator:
             out[sl] += self.W[k] * self._corr_patch(k, g, backend)
         return out.ravel()
 
+    def apply_window(self, f, lo, hi):
+        """(A~ f)[y] for every y of the box [lo, hi] (inclusive), by the direct
+        sums of eq. (2.5) over the ascending terms whose outputs reach the
+        box; returned row-major over the box (full-size checks of whole rows,
+        planes or slabs)."""
+        from . import direct
+        lo = np.asarray(lo, dtype=np.int64).ravel()
+        hi = np.asarray(hi, dtype=np.int64).ravel()
+        f = np.asarray(f, dtype=np.float64).reshape(self.shape)
+        out = np.zeros(tuple(int(v) for v in hi - lo + 1))
+        for k in range(self.grid.r):
+            zlo = self.zlo[k]
+            zhi = zlo + np.array(self.K[k].shape) - 1
+            if np.any(self.u_lo[k] + zlo > hi) or np.any(self.u_hi[k] + zhi < lo):
+                continue
+            sl = tuple(slice(int(self.u_lo[k, i]), int(self.u_hi[k, i] + 1)) for i in range(self.d))
+            direct.conv_add(self.W[k] * f[sl], self.u_lo[k], self.K[k], zlo, out, olo=lo)
+        return out.ravel()
+
+    def apply_adjoint_window(self, g, lo, hi):
+        """(A~* g)[x] for every x of the box [lo, hi] (eq. (1.6)), row-major
+        over the box: per ascending term, the correlation with phi_k^E on the
+        part of bbox(U_k) inside the box, times w_k."""
+        from . import direct
+        lo = np.asarray(lo, dtype=np.int64).ravel()
+        hi = np.asarray(hi, dtype=np.int64).ravel()
+        g = np.asarray(g, dtype=np.float64).reshape(self.shape)
+        out = np.zeros(tuple(int(v) for v in hi - lo + 1))
+        for k in range(self.grid.r):
+            a = np.maximum(self.u_lo[k], lo)
+            b = np.minimum(self.u_hi[k], hi)
+            if np.any(a > b):
+                continue
+            c = direct.corr(g, a, b - a + 1, self.K[k], self.zlo[k])
+            wsl = tuple(slice(int(a[i] - self.u_lo[k, i]), int(b[i] - self.u_lo[k, i] + 1)) for i in range(self.d))
+            osl = tuple(slice(int(a[i] - lo[i]), int(b[i] - lo[i] + 1)) for i in range(self.d))
+            out[osl] += self.W[k][wsl] * c
+        return out.ravel()
+
     def apply_batch(self, F, adjoint=False, backend=None, patches=None):
         F = np.asarray(F, dtype=np.float64).reshape(-1, self.N)
         fn = self.apply_adjoint if adjoint else self.apply

@@ -29,7 +29,7 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
-        lib.oracle_conv_add.argtypes = [P] * 8
+        lib.oracle_conv_add.argtypes = [P] * 9
         lib.oracle_conv_add.restype = None
         lib.oracle_corr.argtypes = [P] * 8
         lib.oracle_corr.restype = None
@@ -46,14 +46,17 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def conv_add(t, tlo, K, zlo, out):
-    """out += (K * t) restricted to the domain (out's shape); FP64, in place."""
+def conv_add(t, tlo, K, zlo, out, olo=None):
+    """out += (K * t) restricted to a window of the domain: out is the window
+    starting at Omega point olo (default: the origin, out = the whole
+    domain); FP64, in place."""
     lib = _load()
     t = np.ascontiguousarray(t, dtype=np.float64)
     K = np.ascontiguousarray(K, dtype=np.float64)
     assert out.dtype == np.float64 and out.flags.c_contiguous
-    a = [_pad3(tlo, 0), _pad3(t.shape, 1), _pad3(zlo, 0), _pad3(K.shape, 1), _pad3(out.shape, 1)]
-    lib.oracle_conv_add(_p(t), _p(a[0]), _p(a[1]), _p(K), _p(a[2]), _p(a[3]), _p(out), _p(a[4]))
+    olo = np.zeros(out.ndim, dtype=np.int64) if olo is None else olo
+    a = [_pad3(tlo, 0), _pad3(t.shape, 1), _pad3(zlo, 0), _pad3(K.shape, 1), _pad3(olo, 0), _pad3(out.shape, 1)]
+    lib.oracle_conv_add(_p(t), _p(a[0]), _p(a[1]), _p(K), _p(a[2]), _p(a[3]), _p(out), _p(a[4]), _p(a[5]))
 
 
 def corr(g, tlo, m, K, zlo):

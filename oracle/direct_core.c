@@ -8,21 +8,23 @@
  */
 #include <stdint.h>
 
-/* out[y] += sum_x t[x] * K[y - x]
+/* out[y] += sum_x t[x] * K[y - x]  for the output points y of a window
  *   t   : input box of extent m[3] starting at Omega point tlo[3]
  *   K   : kernel box of extent kn[3] starting at offset zlo[3]
- *   out : whole domain, extent n[3]
- * Every output point of Omega reached by (t box + K box) is visited once. */
+ *   out : the window of Omega starting at olo[3] with extent on[3]
+ *         (the whole domain: olo = 0, on = n)
+ * Every output point of the window reached by (t box + K box) is visited
+ * once. */
 void oracle_conv_add(const double* t, const int64_t* tlo, const int64_t* m,
                      const double* K, const int64_t* zlo, const int64_t* kn,
-                     double* out, const int64_t* n)
+                     double* out, const int64_t* olo, const int64_t* on)
 {
     int64_t ylo[3], yhi[3];
     for (int i = 0; i < 3; ++i) {
         ylo[i] = tlo[i] + zlo[i];
         yhi[i] = tlo[i] + m[i] - 1 + zlo[i] + kn[i] - 1;
-        if (ylo[i] < 0) ylo[i] = 0;
-        if (yhi[i] > n[i] - 1) yhi[i] = n[i] - 1;
+        if (ylo[i] < olo[i]) ylo[i] = olo[i];
+        if (yhi[i] > olo[i] + on[i] - 1) yhi[i] = olo[i] + on[i] - 1;
         if (ylo[i] > yhi[i]) return;
     }
     #pragma omp parallel for collapse(2) schedule(static)
@@ -43,7 +45,7 @@ void oracle_conv_add(const double* t, const int64_t* tlo, const int64_t* m,
                 }
             }
         }
-        out[(y0 * n[1] + y1) * n[2] + y2] += s;
+        out[((y0 - olo[0]) * on[1] + (y1 - olo[1])) * on[2] + (y2 - olo[2])] += s;
     }
 }
 

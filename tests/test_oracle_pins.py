@@ -526,6 +526,27 @@ def test_c_core_matches_numpy_loops():
     assert np.abs(op.apply_at(u, ys) - a.reshape(64, 64)[ys[:, 0], ys[:, 1]]).max() < 1e-13
 
 
+@pytest.mark.parametrize("name", ["cfg0", "hanging33", "rect45x301", "cube24", "hang3d"])
+def test_window_applies_match_full_applies(name):
+    """apply_window / apply_adjoint_window (the C core restricted to a box of
+    outputs, used for the full-size checks over whole rows and planes) equal
+    the NumPy-loop full applies restricted to the box, for boxes inside,
+    touching the edges of, and covering Omega."""
+    from tests.libhelpers import small_cases, small_cases_3d
+    w = dict(small_cases() + small_cases_3d())[name]
+    op = OracleOperator.from_workload(w)
+    u = np.random.default_rng(23).standard_normal(op.N)
+    full = op.apply(u, backend="numpy").reshape(op.shape)
+    fulla = op.apply_adjoint(u, backend="numpy").reshape(op.shape)
+    n = np.array(op.shape)
+    boxes = [(n // 3, n // 3 + n // 4), (np.zeros_like(n), n - 1), (n - 1, n - 1), (np.zeros_like(n), n // 5)]
+    for lo, hi in boxes:
+        sl = tuple(slice(int(a), int(b) + 1) for a, b in zip(lo, hi))
+        scale = np.abs(full).max()
+        assert np.abs(op.apply_window(u, lo, hi) - full[sl].ravel()).max() <= 1e-13 * scale
+        assert np.abs(op.apply_adjoint_window(u, lo, hi) - fulla[sl].ravel()).max() <= 1e-13 * np.abs(fulla).max()
+
+
 def test_sampled_adjoint_matches_full_adjoint():
     """apply_adjoint_at (used for full-size sampled checks) against the full
     adjoint, itself pinned by the transpose and exactness tests."""
