@@ -24,8 +24,11 @@
  *    throws across the ABI; a failing call returns a status and sets a
  *    thread-local message readable with pc_last_error().
  *  - An operator is read-only after pc_create.  Calls on one operator must be
- *    serialised by the caller (they share the operator's work buffers);
- *    different operators are independent.
+ *    serialised by the caller (they share the operator's work buffers:
+ *    staging, 3-D scratch, estimator buffers); different operators are
+ *    independent.  A call whose work buffers must grow releases the old ones
+ *    in stream order after the operator's previous call has ended (an event;
+ *    neither the host nor other streams wait) and allocates on its stream.
  *  - Graph capture: pc_apply, pc_apply_batch, pc_apply_adjoint_batch,
  *    pc_apply_batch_plain, the two _axpy calls and pc_entries only launch
  *    kernels on s once the operator's work buffers are large enough, so a
@@ -96,8 +99,8 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *  dtype                : arithmetic of the apply (FP32 or FP64).  Setup is
  *                         FP64; the spectra are rounded once to dtype.
  *  flags                : PC_NO_EXTEND, PC_PLAN_HALF_LDS, or 0.
- *  s                    : stream used for the uploads (synchronised before
- *                         return).
+ *  s                    : stream of the uploads (synchronised before return;
+ *                         no device-wide synchronisation).
  *  out                  : receives the operator.
  * Weights w_k are the harmonic partition of unity of Sec. 2.4: multilinear
  * hats on cells without hanging nodes; on cells with hanging nodes the
@@ -207,7 +210,6 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz,
                             double* eta_leaf, double* eta_abs, double* eta_rel,
                             hipStream_t s);
 
-/* Plan statistics (for measurement and admission). */
 /* pc_apply_block -- apply a block of the operator (Sec. 3.3):
  *   adjoint = 0:  OUT_T[:, j] = A~[T, S] U_S[:, j]
  *   adjoint = 1:  OUT_T[:, j] = A~*[T, S] U_S[:, j]  ((A~*)[T, S] = A~[S, T]*)
@@ -246,6 +248,21 @@ pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt,
                            const void* Y, int64_t ldy, double* eta_leaf,
                            double* eta_abs, double* eta_rel, hipStream_t s);
 
+/* pc_estimate_sums_device -- the sums behind the estimator of Sec. 2.6
+ * (eq. (2.11)), left on the device in stream order, for callers that must
+ * not block (a serving loop reads them after an event):
+ *   sums[c]            = sum_{x in C} sum_i (Y~ - Y)^2 for each leaf c,
+ *   sums[n_leaves]     = sum over Omega (each point once) of (Y~ - Y)^2,
+ *   sums[n_leaves + 1] = sum over Omega of Y^2,
+ * FP64, in the fixed order of pc_estimate_sums, whose outputs follow as
+ * eta_C = sqrt(sums[c] / q), eta_abs = sqrt(sums[L] / q), eta_rel =
+ * sqrt(sums[L] / sums[L + 1]).  sums: device double[n_leaves + 2], caller
+ * owned.  Does not synchronise; capturable once the operator's estimator
+ * buffer exists (after one estimator call outside the capture). */
+pc_status pc_estimate_sums_device(pc_op* op, int64_t q, const void* Yt, int64_t ldt,
+                                  const void* Y, int64_t ldy, double* sums, hipStream_t s);
+
+/* Plan statistics (for measurement and admission). */
 typedef struct {
     int64_t n;              /* N = |Omega|                                          */
     int64_t r;              /* number of sample points                              */
@@ -301,8 +318,12 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
  *  PC_TUNE_SCRATCH  3-D operators: bytes of plane-spectrum scratch per item
  *                   group (0 = library default, 512 MiB); one item group runs
  *                   its three kernels before the next group starts
+ *  PC_TUNE_BUDGET   cap, in bytes, on the work buffers the operator may hold
+ *                   (staging, scratch, estimator and block buffers; 0 = no
+ *                   cap): a call that would grow them beyond it returns
+ *                   PC_ERR_BUDGET before anything is enqueued
  * Results are bitwise identical for every setting. */
-enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3 };
+enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 /* pc_device_bytes -- device bytes the operator holds now: its resident data

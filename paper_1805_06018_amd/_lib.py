@@ -62,6 +62,8 @@ _lib.pc_entries.argtypes = [_P, _I64, _P, _P, _P, _P]
 _lib.pc_entries.restype = ctypes.c_int
 _lib.pc_estimate_sums.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P]
 _lib.pc_estimate_sums.restype = ctypes.c_int
+_lib.pc_estimate_sums_device.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P]
+_lib.pc_estimate_sums_device.restype = ctypes.c_int
 _lib.pc_error_estimate.argtypes = [_P, _I64, _P, _I64, _P, _I64, MATVEC_FN, _P, _P, _P, _P, _P]
 _lib.pc_error_estimate.restype = ctypes.c_int
 _lib.pc_get_stats.argtypes = [_P, ctypes.POINTER(PcStats)]
@@ -72,7 +74,7 @@ _lib.pc_set_profiling.argtypes = [_P, ctypes.c_int]
 _lib.pc_set_profiling.restype = ctypes.c_int
 _lib.pc_set_tuning.argtypes = [_P, ctypes.c_int, _I64]
 _lib.pc_set_tuning.restype = ctypes.c_int
-PC_TUNE_CHUNK, PC_TUNE_OVERLAP, PC_TUNE_SCRATCH = 1, 2, 3
+PC_TUNE_CHUNK, PC_TUNE_OVERLAP, PC_TUNE_SCRATCH, PC_TUNE_BUDGET = 1, 2, 3, 4
 _lib.pc_read_profile.argtypes = [_P, ctypes.POINTER(PcProfile)]
 _lib.pc_read_profile.restype = ctypes.c_int
 _lib.pc_device_bytes.argtypes = [_P]
@@ -86,7 +88,7 @@ _lib.pc_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["pc_create", "pc_create_patches", "pc_apply", "pc_apply_batch", "pc_apply_adjoint_batch",
             "pc_apply_batch_plain", "pc_apply_batch_noalloc", "pc_apply_batch_axpy", "pc_apply_adjoint_batch_axpy", "pc_apply_block", "pc_entries",
-            "pc_estimate_sums",
+            "pc_estimate_sums", "pc_estimate_sums_device",
             "pc_error_estimate", "pc_get_stats", "pc_debug_fail_launches", "pc_set_profiling", "pc_set_tuning", "pc_read_profile", "pc_device_bytes",
             "pc_destroy", "pc_status_string", "pc_last_error"]
 
@@ -256,6 +258,25 @@ class PcOperator:
                                      _dev(Y, self.torch_dtype, "Y"), _ld(Y, "Y"), eta.ctypes.data,
                                      ctypes.byref(ea), ctypes.byref(er), _stream(stream)))
         return eta, ea.value, er.value
+
+    def estimate_sums_device(self, Yt, Y, sums, stream=None):
+        """pc_estimate_sums_device: the estimator's FP64 sums into the device
+        tensor sums (float64, n_leaves + 2), without synchronising."""
+        q = 1 if Yt.dim() == 1 else Yt.shape[0]
+        if sums.numel() < self.n_leaves + 2:
+            raise ValueError("sums needs n_leaves + 2 elements")
+        _check(_lib.pc_estimate_sums_device(self._h, q, _dev(Yt, self.torch_dtype, "Yt"), _ld(Yt, "Yt"),
+                                            _dev(Y, self.torch_dtype, "Y"), _ld(Y, "Y"),
+                                            _dev(sums, torch.float64, "sums"), _stream(stream)))
+        return sums
+
+    @staticmethod
+    def eta_from_sums(sums, q):
+        """(eta_leaf, eta_abs, eta_rel) from host sums of estimate_sums_device."""
+        s = np.asarray(sums, dtype=np.float64)
+        L = s.size - 2
+        eta_rel = float(np.sqrt(s[L]) / np.sqrt(s[L + 1])) if s[L + 1] > 0 else float("inf")
+        return np.sqrt(s[:L] / q), float(np.sqrt(s[L] / q)), eta_rel
 
     def error_estimate(self, Z, Y=None, exact_adjoint=None, stream=None):
         """Returns (eta_leaf[n_leaves], eta_abs, eta_rel).  exact_adjoint, if

@@ -66,6 +66,11 @@ struct pc_op {
     void* blk = nullptr;
     size_t blk_bytes = 0;
     hipEvent_t blk_done = nullptr;
+    // the end of the last call that used the work buffers above (stream order
+    // for releasing a buffer that has to grow); budget: cap on their bytes
+    hipEvent_t last_use = nullptr;
+    bool last_use_set = false;
+    size_t budget = 0;
     // matrix entries: tables uploaded on the first pc_entries call
     bool ent_ready = false;
     pc::EntryTables ent{};
@@ -97,6 +102,7 @@ struct pc_op {
         if (scratch) hipFree(scratch);
         if (blk) hipFree(blk);
         if (blk_done) hipEventDestroy(blk_done);
+        if (last_use) hipEventDestroy(last_use);
         if (work) hipFree(work);
         if (est) hipFree(est);
     }
@@ -104,8 +110,10 @@ struct pc_op {
 
 namespace {
 
+// Operator data: allocated once, copied on stream s (finished before the
+// host array may go away).
 template <class V>
-pc_status upload(pc_op* op, const V& host, void** dptr) {
+pc_status upload(pc_op* op, const V& host, void** dptr, hipStream_t s) {
     size_t bytes = host.size() * sizeof(host[0]);
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(dptr, bytes);
@@ -113,17 +121,18 @@ pc_status upload(pc_op* op, const V& host, void** dptr) {
     op->allocs.push_back(*dptr);
     op->resident += bytes;
     if (!host.empty()) {
-        e = hipMemcpy(*dptr, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (operator data)");
+        e = hipMemcpyAsync(*dptr, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (operator data)");
     }
     return PC_OK;
 }
 
-pc_status upload_real(pc_op* op, const std::vector<double>& v, void** dptr) {
-    if (op->plan.dtype == PC_F64) return upload(op, v, dptr);
+pc_status upload_real(pc_op* op, const std::vector<double>& v, void** dptr, hipStream_t s) {
+    if (op->plan.dtype == PC_F64) return upload(op, v, dptr, s);
     std::vector<float> f(v.size());
     for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
-    return upload(op, f, dptr);
+    return upload(op, f, dptr, s);
 }
 
 // True while s records a graph (stream capture).
@@ -132,21 +141,57 @@ bool capturing(hipStream_t s) {
     return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
-pc_status ensure(void** buf, size_t* have, size_t need, const char* what, bool in_capture = false) {
+// Bytes of the work buffers the operator holds (grown by calls, kept until
+// pc_destroy).
+size_t work_buffer_bytes(const pc_op* op) {
+    return op->slots_bytes + op->scratch_bytes + op->work_bytes + op->est_bytes + op->blk_bytes;
+}
+
+// Grows one of the operator's work buffers to at least 'need' bytes, in
+// stream order on s: the old buffer is released on s after the end of the
+// last call that used the work buffers (an event, so neither the host nor
+// other streams wait) and the new one is allocated on s.  Refused under
+// stream capture (PC_ERR_ARG) and beyond the operator's work-buffer budget
+// (PC_ERR_BUDGET), in both cases before anything is enqueued.
+pc_status ensure(pc_op* op, void** buf, size_t* have, size_t need, const char* what, hipStream_t s) {
     if (*have >= need) return PC_OK;
-    if (in_capture)   // growing would synchronise the device and allocate inside the capture
+    if (capturing(s))   // growing would allocate inside the capture
         return fail(PC_ERR_ARG, std::string(what) + ": the buffer is smaller than this call needs; make one call "
                                                     "of at least this size before the stream capture");
+    if (op->budget > 0 && work_buffer_bytes(op) - *have + need > op->budget)
+        return fail(PC_ERR_BUDGET, std::string(what) + ": " + std::to_string(need) +
+                                       " bytes would take the operator's work buffers to " +
+                                       std::to_string(work_buffer_bytes(op) - *have + need) + " bytes, above its budget of " +
+                                       std::to_string(op->budget));
+    hipError_t e;
     if (*buf) {
-        hipError_t e = hipDeviceSynchronize();   // a previous call may still use it
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        hipFree(*buf);
+        if (op->last_use_set) {
+            e = hipStreamWaitEvent(s, op->last_use, 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        }
+        e = hipFreeAsync(*buf, s);
+        if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
         *buf = nullptr;
         *have = 0;
     }
-    hipError_t e = hipMalloc(buf, need);
+    e = hipMallocAsync(buf, need, s);
     if (e != hipSuccess) return hip_fail(e, what);
     *have = need;
+    return PC_OK;
+}
+
+// Records the end of a call that used the work buffers (not under capture:
+// a replayed graph is ordered by its caller, as the header states).
+pc_status mark_used(pc_op* op, hipStream_t s) {
+    if (capturing(s)) return PC_OK;
+    hipError_t e;
+    if (!op->last_use) {
+        e = hipEventCreateWithFlags(&op->last_use, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    e = hipEventRecord(op->last_use, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    op->last_use_set = true;
     return PC_OK;
 }
 
@@ -274,11 +319,10 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
         slots = ext->slots;
         scratch = ext->scratch;
     } else {
-        const bool cap = capturing(s);
-        pc_status st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)", cap);
+        pc_status st = ensure(op, &op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMallocAsync (staging)", s);
         if (st != PC_OK) return st;
-        st = ensure(&op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16), "hipMalloc (3-D scratch)",
-                    cap);
+        st = ensure(op, &op->scratch, &op->scratch_bytes, std::max<size_t>(scratch_need, 16),
+                    "hipMallocAsync (3-D scratch)", s);
         if (st != PC_OK) return st;
         slots = op->slots;
         scratch = op->scratch;
@@ -329,7 +373,10 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     if (!U || !OUT) return fail(PC_ERR_ARG, "null vector pointer");
     if (ldu < N || ldo < N) return fail(PC_ERR_ARG, "leading dimension smaller than N");
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
-    if (op->plan.d == 3) return run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
+    if (op->plan.d == 3) {
+        st = run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
+        return st == PC_OK ? mark_used(op, s) : st;
+    }
     const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     int64_t chunk = 1;
@@ -344,7 +391,7 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     const bool overlap = !plain && op->tune_overlap && nchunks > 1;
     const size_t buf_bytes = (size_t)chunk * per_bytes;
     const bool cap = capturing(s);
-    st = ensure(&op->slots, &op->slots_bytes, (overlap ? 2 : 1) * buf_bytes, "hipMalloc (staging)", cap);
+    st = ensure(op, &op->slots, &op->slots_bytes, (overlap ? 2 : 1) * buf_bytes, "hipMallocAsync (staging)", s);
     if (st != PC_OK) return st;
     if (overlap && cap && !op->aux) return fail(PC_ERR_ARG, "make one overlapped call before the stream capture");
     if (overlap && (st = ensure_aux(op)) != PC_OK) return st;
@@ -399,13 +446,13 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
         hipError_t e = hipStreamWaitEvent(s, op->ev_red[(nchunks - 1) & 1], 0);
         if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
-    return PC_OK;
+    return mark_used(op, s);
 }
 
 pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
                       int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
                       const int64_t* phi_off, pc_dtype dtype, uint32_t flags, int64_t n_sel, const int64_t* sel,
-                      pc_op** out) {
+                      hipStream_t s, pc_op** out) {
     if (!out) return fail(PC_ERR_ARG, "null output handle");
     *out = nullptr;
     pc_op* op = new (std::nothrow) pc_op();
@@ -457,15 +504,15 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     op->esz = (dtype == PC_F64) ? 8 : 4;
     pc::Plan& P = op->plan;
     void *d_items, *d_spec, *d_wts, *d_tw, *d_tf, *d_ta, *d_bf, *d_ba;
-    if ((st = upload(op, P.items, &d_items)) != PC_OK || (st = upload_real(op, P.spec, &d_spec)) != PC_OK ||
-        (st = upload_real(op, P.wts, &d_wts)) != PC_OK || (st = upload_real(op, P.tw, &d_tw)) != PC_OK ||
-        (st = upload(op, P.tiles_fwd, &d_tf)) != PC_OK || (st = upload(op, P.tiles_adj, &d_ta)) != PC_OK ||
-        (st = upload(op, P.cboxes_fwd, &d_bf)) != PC_OK || (st = upload(op, P.cboxes_adj, &d_ba)) != PC_OK) {
+    if ((st = upload(op, P.items, &d_items, s)) != PC_OK || (st = upload_real(op, P.spec, &d_spec, s)) != PC_OK ||
+        (st = upload_real(op, P.wts, &d_wts, s)) != PC_OK || (st = upload_real(op, P.tw, &d_tw, s)) != PC_OK ||
+        (st = upload(op, P.tiles_fwd, &d_tf, s)) != PC_OK || (st = upload(op, P.tiles_adj, &d_ta, s)) != PC_OK ||
+        (st = upload(op, P.cboxes_fwd, &d_bf, s)) != PC_OK || (st = upload(op, P.cboxes_adj, &d_ba, s)) != PC_OK) {
         delete op;
         return st;
     }
     void *d_leaf, *d_items3;
-    if ((st = upload(op, P.leaf_box, &d_leaf)) != PC_OK || (st = upload(op, P.items3, &d_items3)) != PC_OK) {
+    if ((st = upload(op, P.leaf_box, &d_leaf, s)) != PC_OK || (st = upload(op, P.items3, &d_items3, s)) != PC_OK) {
         delete op;
         return st;
     }
@@ -495,10 +542,10 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     D.dtype = (int)dtype;
     op->leaf_box = static_cast<int32_t*>(d_leaf);
     op->d_wts = d_wts;
-    e = hipDeviceSynchronize();
+    e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete op;
-        return hip_fail(e, "hipDeviceSynchronize after upload");
+        return hip_fail(e, "hipStreamSynchronize after upload");
     }
     // spectra are only needed on the device from now on
     std::vector<double>().swap(P.spec);
@@ -514,7 +561,7 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
 }
 
 // Uploads the matrix-entry tables (once per operator).
-pc_status ensure_entries(pc_op* op) {
+pc_status ensure_entries(pc_op* op, hipStream_t s) {
     if (op->ent_ready) return PC_OK;
     const pc::Plan& P = op->plan;
     std::vector<int32_t> leaf_of((size_t)P.N, -1);
@@ -529,10 +576,10 @@ pc_status ensure_entries(pc_op* op) {
     }
     void *d_leaf, *d_off, *d_lp, *d_wb, *d_ub, *d_eo, *d_eb, *d_phi;
     pc_status st;
-    if ((st = upload(op, leaf_of, &d_leaf)) != PC_OK || (st = upload(op, P.leaf_pts_off, &d_off)) != PC_OK ||
-        (st = upload(op, P.leaf_pts, &d_lp)) != PC_OK || (st = upload(op, P.pt_wbase, &d_wb)) != PC_OK ||
-        (st = upload(op, P.pt_ubox, &d_ub)) != PC_OK || (st = upload(op, P.pt_eoff, &d_eo)) != PC_OK ||
-        (st = upload(op, P.pt_ebox, &d_eb)) != PC_OK || (st = upload_real(op, P.phiE, &d_phi)) != PC_OK)
+    if ((st = upload(op, leaf_of, &d_leaf, s)) != PC_OK || (st = upload(op, P.leaf_pts_off, &d_off, s)) != PC_OK ||
+        (st = upload(op, P.leaf_pts, &d_lp, s)) != PC_OK || (st = upload(op, P.pt_wbase, &d_wb, s)) != PC_OK ||
+        (st = upload(op, P.pt_ubox, &d_ub, s)) != PC_OK || (st = upload(op, P.pt_eoff, &d_eo, s)) != PC_OK ||
+        (st = upload(op, P.pt_ebox, &d_eb, s)) != PC_OK || (st = upload_real(op, P.phiE, &d_phi, s)) != PC_OK)
         return st;
     pc::EntryTables& E = op->ent;
     E.d = P.d;
@@ -551,28 +598,39 @@ pc_status ensure_entries(pc_op* op) {
     return PC_OK;
 }
 
-// Estimator sums (Sec. 2.6) of Yt - Y over the operator's leaves.
+constexpr int kEstParts = 512;   // row-block partials of the estimator totals
+
+// Estimator sums (Sec. 2.6) of Yt - Y over the operator's leaves, left on
+// the device in stream order: sums[c] per leaf, sums[L] over Omega, sums[L+1]
+// = sum Y^2.  The row-block partials live in the operator's estimator buffer.
+pc_status est_sums_device(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
+                          double* sums, hipStream_t s) {
+    const int L = (int)op->plan.L;
+    void* est = op->est;
+    pc_status st = ensure(op, &est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 + 2 * kEstParts),
+                          "hipMallocAsync (estimator sums)", s);
+    op->est = static_cast<double*>(est);
+    if (st != PC_OK) return st;
+    double* leaf = sums ? sums : op->est;
+    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, ldt, Y, ldy, op->plan.planes,
+                                  op->plan.prow, op->plan.cols, leaf, op->est + L + 2, kEstParts, leaf + L, s);
+    if (e != hipSuccess) return hip_fail(e, "estimator launch");
+    return mark_used(op, s);
+}
+
+// The same sums read back (synchronises s) and turned into eta_leaf, eta_abs
+// and eta_rel.
 pc_status est_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy, double* eta_leaf,
                    double* eta_abs, double* eta_rel, hipStream_t s) {
     const int L = (int)op->plan.L;
-    const int n_part = 512;
-    void* est = op->est;
-    pc_status st = ensure(&est, &op->est_bytes, sizeof(double) * (size_t)(L + 2 * n_part), "hipMalloc (estimator sums)");
-    op->est = static_cast<double*>(est);
+    pc_status st = est_sums_device(op, q, Yt, ldt, Y, ldy, nullptr, s);
     if (st != PC_OK) return st;
-    hipError_t e = pc::launch_est(op->plan.dtype, op->leaf_box, L, (int)q, Yt, ldt, Y, ldy, op->plan.planes,
-                                  op->plan.prow, op->plan.cols, op->est, op->est + L, n_part, s);
-    if (e != hipSuccess) return hip_fail(e, "estimator launch");
-    std::vector<double> h((size_t)L + 2 * n_part);
-    e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    std::vector<double> h((size_t)L + 2);
+    hipError_t e = hipMemcpyAsync(h.data(), op->est, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (estimator sums)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (estimator)");
-    double dd = 0.0, yy = 0.0;
-    for (int i = 0; i < n_part; ++i) {
-        dd += h[(size_t)L + 2 * i];
-        yy += h[(size_t)L + 2 * i + 1];
-    }
+    const double dd = h[(size_t)L], yy = h[(size_t)L + 1];
     if (eta_leaf)
         for (int c = 0; c < L; ++c) eta_leaf[c] = std::sqrt(h[(size_t)c] / (double)q);
     *eta_abs = std::sqrt(dd / (double)q);
@@ -587,22 +645,20 @@ extern "C" {
 pc_status pc_create(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo, const int64_t* leaf_hi,
                     int64_t r, const int64_t* points, const int64_t* radius, const double* phi,
                     const int64_t* phi_off, pc_dtype dtype, uint32_t flags, hipStream_t s, pc_op** out) {
-    (void)s;
     return create_impl(d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags, -1,
-                       nullptr, out);
+                       nullptr, s, out);
 }
 
 pc_status pc_create_patches(int d, const int64_t* shape, int64_t n_leaves, const int64_t* leaf_lo,
                             const int64_t* leaf_hi, int64_t r, const int64_t* points, const int64_t* radius,
                             const double* phi, const int64_t* phi_off, pc_dtype dtype, uint32_t flags,
                             int64_t n_sel, const int64_t* sel, hipStream_t s, pc_op** out) {
-    (void)s;
     if (n_sel < 0) {
         if (out) *out = nullptr;
         return fail(PC_ERR_ARG, "negative selection size");
     }
     return create_impl(d, shape, n_leaves, leaf_lo, leaf_hi, r, points, radius, phi, phi_off, dtype, flags, n_sel,
-                       sel, out);
+                       sel, s, out);
 }
 
 pc_status pc_apply(pc_op* op, const void* u, void* out, hipStream_t s) {
@@ -709,7 +765,7 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
         e = hipEventCreateWithFlags(&op->blk_done, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
     }
-    st = ensure(&op->blk, &op->blk_bytes, std::max<size_t>(bi + bt + bc, 256), "hipMalloc (block tables)");
+    st = ensure(op, &op->blk, &op->blk_bytes, std::max<size_t>(bi + bt + bc, 256), "hipMallocAsync (block tables)", s);
     if (st != PC_OK) return st;
     char* base = static_cast<char*>(op->blk);
     if (!bp.items.empty()) e = hipMemcpy(base, bp.items.data(), bp.items.size() * sizeof(pc::Item), hipMemcpyHostToDevice);
@@ -738,11 +794,11 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
         if (st != PC_OK) return st;
         e = hipEventRecord(op->blk_done, s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        return PC_OK;
+        return mark_used(op, s);
     }
     const size_t per_bytes = (size_t)std::max<int64_t>(bp.per, 1) * op->esz;
     const int64_t chunk = std::min<int64_t>(B, std::max<int64_t>(1, (int64_t)(kSlotCapBytes / per_bytes)));
-    st = ensure(&op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMalloc (staging)");
+    st = ensure(op, &op->slots, &op->slots_bytes, (size_t)chunk * per_bytes, "hipMallocAsync (staging)", s);
     if (st != PC_OK) return st;
     const char* u = static_cast<const char*>(U);
     char* o = static_cast<char*>(OUT);
@@ -757,7 +813,7 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     }
     e = hipEventRecord(op->blk_done, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    return PC_OK;
+    return mark_used(op, s);
 }
 
 pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs, void* out, hipStream_t s) {
@@ -767,7 +823,7 @@ pc_status pc_entries(pc_op* op, int64_t n, const int64_t* ys, const int64_t* xs,
     if (n == 0) return PC_OK;
     if (!ys || !xs || !out) return fail(PC_ERR_ARG, "null coordinate or output pointer");
     if (!op->ent_phiE && capturing(s)) return fail(PC_ERR_ARG, "make one pc_entries call before the stream capture");
-    if ((st = ensure_entries(op)) != PC_OK) return st;
+    if ((st = ensure_entries(op, s)) != PC_OK) return st;
     hipError_t e = pc::launch_entries(op->ent, op->plan.dtype, op->d_wts, op->ent_phiE, n, ys, xs, out, s);
     if (e != hipSuccess) return hip_fail(e, "entries launch");
     return PC_OK;
@@ -784,6 +840,16 @@ pc_status pc_estimate_sums(pc_op* op, int64_t q, const void* Yt, int64_t ldt, co
     return est_sums(op, q, Yt, ldt, Y, ldy, eta_leaf, eta_abs, eta_rel, s);
 }
 
+pc_status pc_estimate_sums_device(pc_op* op, int64_t q, const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
+                                  double* sums, hipStream_t s) {
+    pc_status st = check_op(op);
+    if (st != PC_OK) return st;
+    const int64_t N = op->plan.N;
+    if (q < 1 || !Yt || !Y || ldt < N || ldy < N) return fail(PC_ERR_ARG, "invalid estimator blocks");
+    if (!sums) return fail(PC_ERR_ARG, "null sums pointer");
+    return est_sums_device(op, q, Yt, ldt, Y, ldy, sums, s);
+}
+
 pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, const void* Y_or_null, int64_t ldy,
                             pc_matvec_fn exact_adjoint, void* user, double* eta_leaf, double* eta_abs,
                             double* eta_rel, hipStream_t s) {
@@ -797,7 +863,7 @@ pc_status pc_error_estimate(pc_op* op, int64_t q, const void* Z, int64_t ldz, co
     if (capturing(s)) return fail(PC_ERR_ARG, "the estimator returns host scalars: not capturable");
     const size_t vec = (size_t)N * op->esz;
     const size_t need = (size_t)q * vec * (Y_or_null ? 1 : 2);
-    st = ensure(&op->work, &op->work_bytes, need, "hipMalloc (estimator work)");
+    st = ensure(op, &op->work, &op->work_bytes, need, "hipMallocAsync (estimator work)", s);
     if (st != PC_OK) return st;
     char* Yt = static_cast<char*>(op->work);
     const void* Y = Y_or_null;
@@ -876,6 +942,10 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
             if (value < 0) return fail(PC_ERR_ARG, "scratch size out of range");
             op->tune_scratch = value;
             return PC_OK;
+        case PC_TUNE_BUDGET:
+            if (value < 0) return fail(PC_ERR_ARG, "budget out of range");
+            op->budget = (size_t)value;
+            return PC_OK;
         default:
             return fail(PC_ERR_ARG, "unknown tuning key");
     }
@@ -907,12 +977,14 @@ pc_status pc_read_profile(pc_op* op, pc_profile* out) {
 
 size_t pc_device_bytes(const pc_op* op) {
     if (!op) return 0;
-    return op->resident + op->slots_bytes + op->scratch_bytes + op->work_bytes + op->est_bytes;
+    return op->resident + work_buffer_bytes(op);
 }
 
 pc_status pc_destroy(pc_op* op) {
     if (!op) return PC_OK;
-    hipDeviceSynchronize();
+    // the operator's last calls end before its memory is released
+    if (op->last_use_set) hipEventSynchronize(op->last_use);
+    if (op->blk_done) hipEventSynchronize(op->blk_done);
     delete op;
     return PC_OK;
 }

@@ -59,12 +59,13 @@ hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s);
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride,
                          void* out, int64_t ldo, hipStream_t s, bool accumulate = false, double alpha = 1.0);
 
-// Estimator: per-leaf (leaf_box [L][6]) FP64 sums of squares of (Yt - Y) over q vectors and
-// the totals sum (Yt - Y)^2 and sum Y^2 (per row-block partials).
+// Estimator: per-leaf (leaf_box [L][6]) FP64 sums of squares of (Yt - Y) over q vectors into
+// leaf_sq, and the totals sum (Yt - Y)^2 and sum Y^2 into totals[2] (through n_part
+// row-block partials, summed in order).
 hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q,
                       const void* Yt, int64_t ldt, const void* Y, int64_t ldy,
                       int planes, int prow, int cols, double* leaf_sq, double* partials, int n_part,
-                      hipStream_t s);
+                      double* totals, hipStream_t s);
 
 // Matrix entries out[i] = A~[ys[i], xs[i]] (device int64 [n][d] coordinates).
 hipError_t launch_entries(const EntryTables& E, int dtype, const void* wts, const void* phiE, int64_t n,

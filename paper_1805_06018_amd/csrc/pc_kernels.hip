@@ -362,6 +362,19 @@ __global__ __launch_bounds__(kEstThreads) void est_total_kernel(int q, const T* 
     }
 }
 
+// The totals from the row-block partials, one thread, partials in index
+// order (FP64): totals[0] = sum (Yt - Y)^2, totals[1] = sum Y^2.
+__global__ __launch_bounds__(64) void est_final_kernel(const double* partials, int n_part, double* totals) {
+    if (threadIdx.x != 0) return;
+    double dd = 0.0, yy = 0.0;
+    for (int i = 0; i < n_part; ++i) {
+        dd += partials[2 * i];
+        yy += partials[2 * i + 1];
+    }
+    totals[0] = dd;
+    totals[1] = yy;
+}
+
 // ---------------------------------------------------------------- launchers
 template <class T>
 static hipError_t conv_t(const DevPlan& P, bool adj, int item_lo, int item_hi, int B, const void* in, int64_t ld_in,
@@ -421,7 +434,7 @@ hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slot
 
 hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, const void* Yt, int64_t ldt,
                       const void* Y, int64_t ldy, int planes, int prow, int cols, double* leaf_sq, double* partials,
-                      int n_part, hipStream_t s) {
+                      int n_part, double* totals, hipStream_t s) {
     const int64_t n_total = (int64_t)planes * prow * cols;
     if (dtype == 1) {
         hipLaunchKernelGGL(est_leaf_kernel<double>, dim3(n_leaves), dim3(kEstThreads), 0, s, leaf_box, q,
@@ -438,6 +451,7 @@ hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, c
                            static_cast<const float*>(Yt), ldt, static_cast<const float*>(Y), ldy, n_total, n_part,
                            partials);
     }
+    hipLaunchKernelGGL(est_final_kernel, dim3(1), dim3(64), 0, s, partials, n_part, totals);
     return hipGetLastError();
 }
 

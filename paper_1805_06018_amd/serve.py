@@ -10,11 +10,16 @@ operator's spectra on the device and runs a loop that
     queued apply requests for the operator with the oldest waiting request are
     merged into one fused pc_apply_batch launch (continuous batching across
     requests; the apply of each vector is independent of the batch, so every
-    result is bitwise the same alone and in the mix); an estimate request runs
-    pc_error_estimate.
+    result is bitwise the same alone and in the mix); an estimate request is
+    stream-ordered too: the adjoint apply of its probes and the estimator
+    sums (pc_estimate_sums_device) are enqueued with a copy of the sums to
+    pinned host memory, and eta is formed once its event has fired, so the
+    loop never blocks on the device.
 Batches for different operators run on different streams and overlap on the
 device; one operator has at most one batch in flight (its work buffers are
-shared).  Modes: "batched" (the above), "sequential" (one request at a time,
+shared).  Each request reads its own rows of the operator's input pool (an
+offset that depends on its id), so a result handed to the wrong request
+shows.  Modes: "batched" (the above), "sequential" (one request at a time,
 fused kernels) and "plain" (one request at a time, one launch per patch and
 vector).  Latency = completion time observed by the loop - arrival time.
 """
@@ -48,10 +53,18 @@ class Resident:
     name: str
     pc: object           # _lib.PcOperator
     N: int
-    U: torch.Tensor      # (32, N) input pool: request j uses the first B rows
+    U: torch.Tensor      # (POOL_ROWS, N) input pool: a request reads B rows from its own offset
     Z: torch.Tensor      # (q, N) probes for estimate requests
     Y: torch.Tensor      # (q, N) exact adjoint of Z
     work_bytes: int = 0  # resident operator data + staging estimate
+
+
+POOL_ROWS = 64
+
+
+def input_rows(q):
+    """First pool row of request q's input (its B rows follow)."""
+    return (q.rid * 13) % (POOL_ROWS - q.B + 1)
 
 
 def poisson_requests(n_req, n_ops, rate, seed=104, max_b=32, p_estimate=0.2, q=8):
@@ -68,13 +81,14 @@ def poisson_requests(n_req, n_ops, rate, seed=104, max_b=32, p_estimate=0.2, q=8
 
 
 class _Batch:
-    def __init__(self, op, reqs, stream, nbytes):
+    def __init__(self, op, reqs, stream, nbytes, finish=None):
         self.op, self.reqs, self.stream, self.nbytes = op, reqs, stream, nbytes
+        self.finish = finish          # called once the event has fired
         self.event = torch.cuda.Event()
 
 
 class Server:
-    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=2):
+    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=4):
         self.ops = residents
         self.budget = hbm_budget
         self.max_batch = max_batch
@@ -104,10 +118,11 @@ class Server:
         r = self.ops[op]
         Bt = sum(q.B for q in reqs)
         with torch.cuda.stream(stream):
+            rows = [(input_rows(q), q.B) for q in reqs]
             if len(reqs) == 1:
-                inp = r.U[:Bt]
+                inp = r.U[rows[0][0]:rows[0][0] + Bt]
             else:
-                inp = torch.cat([r.U[:q.B] for q in reqs], dim=0)
+                inp = torch.cat([r.U[a:a + b] for a, b in rows], dim=0)
             out = torch.empty((Bt, r.N), dtype=torch.float32, device="cuda")
             (r.pc.apply_batch_plain if plain else r.pc.apply_batch)(inp, out, stream=stream)
         o = 0
@@ -118,10 +133,24 @@ class Server:
         b.event.record(stream)
         return b
 
-    def _run_estimate(self, q, stream):
+    def _launch_estimate(self, q, stream):
+        """Enqueues Y~ = A~* Z, the estimator sums and their copy to pinned
+        host memory on the stream; eta is formed after the event."""
         r = self.ops[q.op]
         with torch.cuda.stream(stream):
-            q.result = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B], stream=stream)
+            Yt = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
+            r.pc.apply_adjoint_batch(r.Z[:q.B], Yt, stream=stream)
+            sums = torch.empty(r.pc.n_leaves + 2, dtype=torch.float64, device="cuda")
+            r.pc.estimate_sums_device(Yt, r.Y[:q.B], sums, stream=stream)
+            host = torch.empty(sums.shape, dtype=torch.float64, pin_memory=True)
+            host.copy_(sums, non_blocking=True)
+
+        def finish():
+            q.result = r.pc.eta_from_sums(host.numpy(), q.B)
+
+        b = _Batch(q.op, [q], stream, q.B * r.N * 4, finish)
+        b.event.record(stream)
+        return b
 
     def run(self, requests, mode="batched"):
         reqs = sorted(requests, key=lambda q: q.arrival)
@@ -144,6 +173,8 @@ class Server:
                 i += 1
             for b in list(inflight):
                 if b.event.query():
+                    if b.finish:
+                        b.finish()
                     td = now()
                     for q in b.reqs:
                         q.t_done = td
@@ -164,11 +195,9 @@ class Server:
                 q = pending.popleft()
                 try:
                     if q.kind == "estimate":
-                        self._run_estimate(q, stream)
-                        q.t_done = now()
-                        batches.append(1)
-                        continue
-                    b = self._launch_apply(q.op, [q], stream, plain=(mode == "plain"))
+                        b = self._launch_estimate(q, stream)
+                    else:
+                        b = self._launch_apply(q.op, [q], stream, plain=(mode == "plain"))
                 except _lib.PcError as e:
                     self._failed([q], e, pending, now())
                     continue
@@ -179,17 +208,27 @@ class Server:
             head = next((q for q in pending if q.op not in busy_ops), None)
             if head is None:
                 continue
+            r = self.ops[head.op]
             if head.kind == "estimate":
+                nb = head.B * r.N * 4
+                if self.resident_bytes + inflight_bytes + nb > self.budget:
+                    if not inflight:
+                        pending.remove(head)
+                        head.result = "rejected: exceeds the HBM budget"
+                        head.t_done = now()
+                    continue
                 pending.remove(head)
                 try:
-                    self._run_estimate(head, stream)
+                    b = self._launch_estimate(head, stream)
                 except _lib.PcError as e:
                     self._failed([head], e, pending, now())
                     continue
-                head.t_done = now()
+                inflight.append(b)
+                busy_ops.add(head.op)
+                inflight_bytes += b.nbytes
+                peak = max(peak, self.resident_bytes + inflight_bytes)
                 batches.append(1)
                 continue
-            r = self.ops[head.op]
             take, vecs = [], 0
             for q in pending:
                 if q.op != head.op or q.kind != "apply":
@@ -261,12 +300,13 @@ def build_residents(workloads, q=8, dtype=_lib.PC_F32, max_batch=64, log=None):
     res = []
     for w in workloads:
         op = _lib.PcOperator.from_workload(w, dtype=dtype)
-        U = torch.from_numpy(w.vectors(32, dtype=np.float32)).cuda()
+        U = torch.from_numpy(w.vectors(POOL_ROWS, dtype=np.float32)).cuda()
         Z = torch.from_numpy(w.rademacher(q, w.vec_seed + 1000).astype(np.float32)).cuda()
         Y = GpuBlurAdjoint(w.op)(Z)
         tmp = torch.zeros((max_batch, w.N), dtype=torch.float32, device="cuda")
         op.apply_batch(tmp, tmp.clone())
         op.error_estimate(Z, Y)
+        op.estimate_sums_device(Z, Y, torch.empty(op.n_leaves + 2, dtype=torch.float64, device="cuda"))
         torch.cuda.synchronize()
         del tmp
         res.append(Resident(w.name, op, w.N, U, Z, Y, op.device_bytes()))

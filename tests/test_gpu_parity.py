@@ -253,6 +253,43 @@ def test_apply_argument_errors(lib):
                        torch.zeros((1, w.N), dtype=torch.float32, device="cuda"))
 
 
+def test_work_buffer_budget_and_device_sums(lib):
+    """PC_TUNE_BUDGET: a call whose staging would take the operator's work
+    buffers beyond the budget returns PC_ERR_BUDGET and leaves its output
+    untouched; within the budget it runs, and buffers grow in stream order
+    (a larger batch after a smaller one on another stream).  The estimator
+    sums left on the device give the same numbers as pc_estimate_sums."""
+    w = make_config(1, scale=0.25)
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    per = op.stats()["slot_elems_fwd"] * 4
+    op.set_tuning(lib.PC_TUNE_BUDGET, 2 * per)
+    U = torch.from_numpy(w.vectors(6, dtype=np.float32)).cuda()
+    out = torch.full_like(U, 5.0)
+    with pytest.raises(lib.PcError) as ei:
+        op.apply_batch(U, out)
+    assert ei.value.status == lib.PC_ERR_BUDGET
+    torch.cuda.synchronize()
+    assert torch.all(out == 5.0)
+    op.apply_batch(U[:2], out[:2])                       # fits: 2 vectors of staging
+    op.set_tuning(lib.PC_TUNE_BUDGET, 0)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        op.apply_batch(U, out, stream=side)              # grows the staging on another stream
+    torch.cuda.synchronize()
+    ref = torch.zeros_like(U)
+    op.apply_batch_plain(U, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    Y = torch.from_numpy(w.vectors(4, dtype=np.float32, seed=9)).cuda()
+    eta, ea, er = op.estimate_sums(U[:4], Y)
+    sums = torch.full((op.n_leaves + 2,), float("nan"), dtype=torch.float64, device="cuda")
+    op.estimate_sums_device(U[:4], Y, sums)
+    torch.cuda.synchronize()
+    eta2, ea2, er2 = op.eta_from_sums(sums.cpu().numpy(), 4)
+    assert np.array_equal(eta, eta2) and ea == ea2 and er == er2
+    op.close()
+
+
 def test_large_pieces_blur2048_start_grid(lib):
     """2048^2 start grid (16 points, cells 683 wide, kernels up to 129^2): every
     patch is cut into a grid of row x column pieces.  Forward and adjoint of

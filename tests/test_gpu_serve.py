@@ -12,23 +12,36 @@ def served():
         pytest.fail("GPU test run without a visible HIP device")
     from paper_1805_06018_amd import serve
     from workloads import make_serving_ops
-    res = serve.build_residents(make_serving_ops(sizes=(256, 512, 768)))
+    # three 2-D operators and the smallest 3-D one (64^3, 27 points)
+    res = serve.build_residents(make_serving_ops(sizes=(256, 512, 768), with_3d=True, sizes3=(64,)))
     return serve, res
 
 
+def _alone(serve, r, q):
+    """The request's result computed alone, from its own rows of the pool."""
+    a = serve.input_rows(q)
+    out = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
+    r.pc.apply_batch(r.U[a:a + q.B], out)
+    torch.cuda.synchronize()
+    return out
+
+
 def test_results_same_alone_and_in_the_mix(served):
+    """Every request reads its own rows of its operator's pool; merged into
+    batches with other requests (2-D and 3-D operators, four streams) each
+    result equals the request's alone result bit for bit, and a stream-ordered
+    estimate equals the synchronous pc_error_estimate."""
     serve, res = served
-    srv = serve.Server(res, hbm_budget=16 << 30)
+    srv = serve.Server(res, hbm_budget=24 << 30)
     reqs = serve.poisson_requests(60, len(res), 0.0, seed=5)
     out = srv.run(reqs, mode="batched")
     assert out["mean_batch_requests"] > 1.0          # requests were merged
+    assert len({serve.input_rows(q) for q in reqs}) > 10
+    assert {res[q.op].pc.d for q in reqs} == {2, 3}
     for q in reqs:
         r = res[q.op]
         if q.kind == "apply":
-            alone = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
-            r.pc.apply_batch(r.U[:q.B], alone)
-            torch.cuda.synchronize()
-            assert torch.equal(alone, q.result), q.rid
+            assert torch.equal(_alone(serve, r, q), q.result), q.rid
         else:
             eta, ea, er = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B])
             assert np.array_equal(eta, q.result[0]) and ea == q.result[1] and er == q.result[2]
@@ -48,10 +61,7 @@ def test_hbm_budget_admission(served):
     assert out["peak_admitted_bytes"] <= resident + room
     for q in reqs:
         if q.kind == "apply":
-            alone = torch.empty((q.B, res[q.op].N), dtype=torch.float32, device="cuda")
-            res[q.op].pc.apply_batch(res[q.op].U[:q.B], alone)
-            torch.cuda.synchronize()
-            assert torch.equal(alone, q.result)
+            assert torch.equal(_alone(serve, res[q.op], q), q.result)
 
 
 def test_failed_launch_is_isolated(served):
@@ -61,7 +71,7 @@ def test_failed_launch_is_isolated(served):
     every other request completes with its alone result, and the operator
     keeps working."""
     serve, res = served
-    srv = serve.Server(res, hbm_budget=16 << 30)
+    srv = serve.Server(res, hbm_budget=24 << 30)
     reqs = serve.poisson_requests(40, len(res), 0.0, seed=8)
     target = next(q.op for q in reqs if q.kind == "apply")
     res[target].pc.debug_fail_launches(1, 2)
@@ -77,10 +87,7 @@ def test_failed_launch_is_isolated(served):
             continue
         r = res[q.op]
         if q.kind == "apply":
-            alone = torch.empty((q.B, r.N), dtype=torch.float32, device="cuda")
-            r.pc.apply_batch(r.U[:q.B], alone)
-            torch.cuda.synchronize()
-            assert torch.equal(alone, q.result), q.rid
+            assert torch.equal(_alone(serve, r, q), q.result), q.rid
         else:
             eta, ea, er = r.pc.error_estimate(r.Z[:q.B], r.Y[:q.B])
             assert np.array_equal(eta, q.result[0]) and ea == q.result[1] and er == q.result[2]
