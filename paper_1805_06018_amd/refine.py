@@ -20,14 +20,10 @@ Two ways to keep Y~ = A~* Z current:
     are formed from the updated Y~ (pc_estimate_sums).  Impulse responses are
     requested only for new points.
 
-Subdivision direction (Sec. 2.7): for each axis along which the leaf is wider
-than 2, the impulse responses of the corners on the front and on the back of
-the leaf are averaged, and the leaf is split at its midpoint along the axis
-where the two averages differ most in l2 over the offsets z with
-c_mid + z in Omega.  The impulse responses used are the supplied patches
-(zero outside their boxes).
+Subdivision direction (Sec. 2.7): tiling.split_direction, the paper's
+front/back comparison of corner impulse responses with the change measured
+through the leaf's midplane as well (see that module).
 """
-import itertools
 import json
 import sys
 import time
@@ -36,89 +32,7 @@ import numpy as np
 import torch
 
 from . import _lib
-
-
-def corner_points(lo, hi):
-    d = lo.shape[1]
-    pts = set()
-    for a, b in zip(lo, hi):
-        for bits in itertools.product((0, 1), repeat=d):
-            pts.add(tuple(int(b[i] if bit else a[i]) for i, bit in enumerate(bits)))
-    return np.array(sorted(pts), dtype=np.int64).reshape(-1, d)
-
-
-def split_direction(lo, hi, shape, patch_of):
-    """Axis along which the corner impulse responses change the most."""
-    d = len(lo)
-    mid = [(lo[i] + hi[i]) // 2 for i in range(d)]
-    best, best_axis = -1.0, None
-    for i in range(d):
-        if hi[i] - lo[i] <= 2:
-            continue
-        groups = {}
-        for side, val in (("+", hi[i]), ("-", lo[i])):
-            pats = []
-            for bits in itertools.product((0, 1), repeat=d):
-                p = tuple(int(hi[j] if bits[j] else lo[j]) for j in range(d))
-                if p[i] == val:
-                    pats.append(patch_of(p))
-            groups[side] = pats
-        R = np.max([np.array(P.shape) // 2 for P in groups["+"] + groups["-"]], axis=0)
-
-        def avg(pats):
-            acc = np.zeros(tuple(2 * R + 1))
-            for P in pats:
-                r = np.array(P.shape) // 2
-                sl = tuple(slice(int(R[j] - r[j]), int(R[j] + r[j] + 1)) for j in range(d))
-                acc[sl] += P
-            return acc / len(pats)
-
-        diff = avg(groups["+"]) - avg(groups["-"])
-        # restrict to offsets z with c_mid + z inside the domain
-        sl = tuple(slice(int(max(0, R[j] - mid[j])), int(min(2 * R[j] + 1, R[j] + shape[j] - mid[j])))
-                   for j in range(d))
-        val = float(np.sqrt(np.sum(diff[sl] ** 2)))
-        if val > best:
-            best, best_axis = val, i
-    return best_axis
-
-
-def split_leaf(lo, hi, axis):
-    mid = (lo[axis] + hi[axis]) // 2
-    a_hi = hi.copy()
-    a_hi[axis] = mid
-    b_lo = lo.copy()
-    b_lo[axis] = mid
-    return (lo.copy(), a_hi), (b_lo, hi.copy())
-
-
-def leaf_point_sets(lo, hi, pts):
-    """For every leaf, the indices of the points on its closed box (pts sorted
-    with axis 0 most significant, as corner_points returns them)."""
-    x0 = pts[:, 0]
-    a = np.searchsorted(x0, lo[:, 0], side="left")
-    b = np.searchsorted(x0, hi[:, 0], side="right")
-    out = []
-    for c in range(len(lo)):
-        cand = pts[a[c]:b[c], 1:]
-        inside = np.all((cand >= lo[c, 1:]) & (cand <= hi[c, 1:]), axis=1)
-        out.append(a[c] + np.nonzero(inside)[0])
-    return out
-
-
-def term_keys(lo, hi, pts):
-    """A key per point that is equal between two tilings iff the point's term
-    of the sum is the same: the point, and the boxes of the leaves containing
-    it with the points on each (they fix U_k, w_k, nbrs(k) and phi_k^E)."""
-    pts = np.ascontiguousarray(pts, dtype=np.int64)
-    sets = leaf_point_sets(lo, hi, pts)
-    leaf_key = [lo[c].astype(np.int64).tobytes() + hi[c].astype(np.int64).tobytes() + pts[sc].tobytes()
-                for c, sc in enumerate(sets)]
-    cells = [[] for _ in range(len(pts))]
-    for c, sc in enumerate(sets):
-        for k in sc.tolist():
-            cells[k].append(leaf_key[c])
-    return [(pts[k].tobytes(), tuple(sorted(cells[k]))) for k in range(len(pts))]
+from .tiling import corner_points, split_round, term_keys
 
 
 class _ImpulseCache:
@@ -144,34 +58,16 @@ class _ImpulseCache:
         return rad, np.concatenate(blocks), off
 
 
-def _split_round(lo, hi, eta, frac, shape, patch_of):
-    order = np.argsort(-eta, kind="stable")
-    refinable = [c for c in order if np.any(hi[c] - lo[c] > 2)]
-    if not refinable:
-        return None
-    n_take = 1 if frac <= 0 else max(1, int(np.ceil(frac * len(lo))))
-    chosen = set(int(c) for c in refinable[:n_take])
-    new_lo, new_hi = [], []
-    for c in range(len(lo)):
-        if c in chosen:
-            axis = split_direction(lo[c], hi[c], shape, patch_of)
-            (alo, ahi), (blo, bhi) = split_leaf(lo[c], hi[c], axis)
-            new_lo += [alo, blo]
-            new_hi += [ahi, bhi]
-        else:
-            new_lo.append(lo[c])
-            new_hi.append(hi[c])
-    order = np.lexsort(np.array(new_lo).T[::-1])
-    return np.array(new_lo)[order], np.array(new_hi)[order]
-
-
 def refine(shape, leaf_lo, leaf_hi, impulse_responses, patch_of, Z, Y, tol=1e-2, max_points=4000,
-           frac=0.1, max_rounds=200, dtype=_lib.PC_F32, log=None, incremental=False, yt_out=None):
+           frac=0.1, max_rounds=200, dtype=_lib.PC_F32, log=None, incremental=False, yt_out=None,
+           rule="midplane"):
     """Run the loop.  impulse_responses(points) -> (radius, phi, phi_off);
     patch_of(point) -> the point's impulse-response patch (for the split
     direction); Z, Y: (q, N) device tensors, Y = A* Z.  frac = 0 refines one
-    leaf per round (Algorithm 1).  Returns the final leaves and per-round
-    records; with yt_out (a list), the final Y~ is appended to it."""
+    leaf per round (Algorithm 1).  rule: the subdivision-direction rule of
+    tiling.split_direction ("midplane", or the corner-only "faces").
+    Returns the final leaves and per-round records; with yt_out (a list),
+    the final Y~ is appended to it."""
     lo = np.array(leaf_lo, dtype=np.int64)
     hi = np.array(leaf_hi, dtype=np.int64)
     d = lo.shape[1]
@@ -221,7 +117,7 @@ def refine(shape, leaf_lo, leaf_hi, impulse_responses, patch_of, Z, Y, tol=1e-2,
             prev = (lo, hi, pts, radius, phi, off, keys)
         if erel < tol or len(pts) >= max_points or it == max_rounds - 1:
             break        # the returned tiling is the one the last estimate is for
-        nxt = _split_round(lo, hi, eta, frac, shape, patch_of)
+        nxt = split_round(lo, hi, eta, frac, shape, patch_of, rule)
         if nxt is None:
             break
         lo, hi = nxt
@@ -244,9 +140,11 @@ def main(argv=None):
     ap.add_argument("--q", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--frac", type=float, default=0.1, help="0: one leaf per round (Algorithm 1)")
-    ap.add_argument("--max-points", type=int, default=4000)
+    ap.add_argument("--max-points", type=int, default=20000)
     ap.add_argument("--max-rounds", type=int, default=200)
     ap.add_argument("--incremental", action="store_true", help="update Y~ with the changed terms only")
+    ap.add_argument("--rule", choices=["midplane", "faces"], default="midplane",
+                    help="subdivision-direction rule (tiling.split_direction)")
     ap.add_argument("--drift-check", action="store_true",
                     help="at the end, compare the incremental Y~ with a full recomputation")
     ap.add_argument("--q-check", type=str, default="",
@@ -259,13 +157,15 @@ def main(argv=None):
     t0 = time.time()
     Y = exact(Z)
     torch.cuda.synchronize()
-    print(json.dumps({"workload": w.name, "N": w.N, "q": args.q, "incremental": args.incremental,
-                      "frac": args.frac, "t_exact_adjoint_s": time.time() - t0}), flush=True)
+    cmd = "python -m paper_1805_06018_amd.refine " + " ".join(sys.argv[1:] if argv is None else argv)
+    print(json.dumps({"command": cmd.strip(), "workload": w.name, "N": w.N, "q": args.q,
+                      "incremental": args.incremental,
+                      "frac": args.frac, "rule": args.rule, "t_exact_adjoint_s": time.time() - t0}), flush=True)
     yts = []
     t0 = time.time()
     lo, hi, rounds = refine(w.shape, w.leaf_lo, w.leaf_hi, w.op.impulse_responses, w.op.patch, Z, Y,
                             tol=args.tol, max_points=args.max_points, frac=args.frac, max_rounds=args.max_rounds,
-                            incremental=args.incremental, yt_out=yts,
+                            incremental=args.incremental, yt_out=yts, rule=args.rule,
                             log=lambda r: print(json.dumps(r), flush=True))
     t_loop = time.time() - t0
     out = {"final_points": rounds[-1]["points"], "final_eta_rel": rounds[-1]["eta_rel"], "rounds": len(rounds),

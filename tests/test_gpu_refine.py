@@ -75,6 +75,18 @@ def test_refinement_loop_converges_and_matches_oracle(mods):
     radius, phi, off = w.op.impulse_responses(pts)
     op = _lib.PcOperator(2, w.shape, lo, hi, pts, radius, phi, off, dtype=_lib.PC_F32)
     eta, eabs, erel = op.error_estimate(Z, Y)
+    # against the uniform tiling with at least as many points, on fresh probes
+    m = int(np.ceil(np.sqrt(len(pts))))
+    ulo, uhi = tensor_leaves([uniform_nodes(n, m), uniform_nodes(n, m)])
+    upts = corner_points(ulo, uhi)
+    urad, uphi, uoff = w.op.impulse_responses(upts)
+    uop = _lib.PcOperator(2, w.shape, ulo, uhi, upts, urad, uphi, uoff, dtype=_lib.PC_F32)
+    Zf = torch.from_numpy(w.rademacher(16, 77).astype(np.float32)).cuda()
+    Yf = GpuBlurAdjoint(w.op)(Zf)
+    _, _, e_adapt = op.error_estimate(Zf, Yf)
+    _, _, e_unif = uop.error_estimate(Zf, Yf)
+    print("fresh probes: adaptive", len(pts), e_adapt, "uniform", len(upts), e_unif, flush=True)
+    assert len(upts) >= len(pts) and e_adapt < e_unif
     ora = OracleOperator(w.shape, lo, hi, pts, radius, phi, off)
     eta_o, eabs_o, erel_o, _ = estimate(ora, Zh, Y.cpu().numpy().astype(np.float64))
     assert abs(erel - erel_o) <= 1e-3 * erel_o, (erel, erel_o)
@@ -125,8 +137,10 @@ def test_term_subset_operators_and_axpy(mods):
 def test_incremental_refinement_tracks_full_recompute(mods):
     """Sec. 2.8: Y~ updated with the changed terms only stays equal (to FP32
     rounding) to a full recomputation on the final tiling, and so does the
-    estimate; far fewer terms are convolved than by rebuilding every round.
-    Then three rounds of one leaf each (Algorithm 1)."""
+    estimate.  With 15 % of the leaves split per round an update convolves
+    old and new terms of most points (about as many as a rebuild); with one
+    leaf per round (Algorithm 1, six rounds) each update convolves a handful
+    of terms against hundreds for a rebuild."""
     _lib, refine, GpuBlurAdjoint = mods
     from workloads import cosine_field, uniform_nodes, tensor_leaves
     n = 256
@@ -154,7 +168,6 @@ def test_incremental_refinement_tracks_full_recompute(mods):
     eta_e, _, erel_e = op.error_estimate(Z, Y)
     assert np.array_equal(eta_f, eta_e) and erel_f == erel_e     # same Y~ bits, same sums
     assert abs(rounds[-1]["eta_rel"] - erel_f) <= 1e-4 * erel_f
-    assert sum(r["terms_convolved"] for r in rounds) <= sum(r["points"] for r in rounds)
     # Algorithm 1: one leaf per round; each round convolves a few terms only
     yts1 = []
     lo1, hi1, r1 = refine.refine(w.shape, lo, hi, w.op.impulse_responses, w.op.patch, Z, Y, tol=1e-9,
@@ -162,6 +175,7 @@ def test_incremental_refinement_tracks_full_recompute(mods):
     print("one-leaf terms", [r["terms_convolved"] for r in r1], flush=True)
     assert [r["leaves"] for r in r1] == [len(lo) + i for i in range(6)]
     assert all(r["terms_convolved"] <= 40 for r in r1[1:])
+    assert all(r["terms_convolved"] < r["points"] / 10 for r in r1[1:])
     pts1 = corner_points(lo1, hi1)
     radius1, phi1, off1 = w.op.impulse_responses(pts1)
     op1 = _lib.PcOperator(2, w.shape, lo1, hi1, pts1, radius1, phi1, off1, dtype=_lib.PC_F32)
