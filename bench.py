@@ -199,7 +199,8 @@ def main():
     # not divide ends with a shorter launch, so the bytes are averaged over
     # the launches of one apply (as the launch time is)
     traffic = None
-    if not three_d and not f64:
+    direct = schedule.get("chosen", {}).get("direct", 0) if schedule["autotuned"] else 0
+    if not three_d and not f64 and not direct:
         per_vec = st["slot_elems_fwd"] * esz
         cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's 2 GiB staging cap
         chunk = schedule.get("chosen", {}).get("chunk", 0) if schedule["autotuned"] else 0

@@ -318,12 +318,28 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
  *  PC_TUNE_SCRATCH  3-D operators: bytes of plane-spectrum scratch per item
  *                   group (0 = library default, 512 MiB); one item group runs
  *                   its three kernels before the next group starts
+ *  PC_TUNE_DIRECT   1-D/2-D operators, pc_apply_batch and the adjoint: 1
+ *                   runs the items colour by colour - the items of one
+ *                   colour write pairwise disjoint boxes - and adds each box
+ *                   straight into the outputs, which are zeroed first;
+ *                   0 (default) stages every item's box and sums them in a
+ *                   reduction launch.  Both sum each output point's contributions in
+ *                   the same order (ascending colour, then item), so the
+ *                   bits are the same.  The axpy forms, block applies and the
+ *                   plain path always stage.
+ *  PC_TUNE_STREAMS  colour launches: the batch is cut into vector chunks
+ *                   (PC_TUNE_CHUNK vectors, default B / streams) whose
+ *                   colour sequences run on up to this many library streams
+ *                   at once, forked from and joined back into the caller's
+ *                   stream with events (1..4, default 4); each chunk keeps
+ *                   its own colour order, so the bits do not change
  *  PC_TUNE_BUDGET   cap, in bytes, on the work buffers the operator may hold
  *                   (staging, scratch, estimator and block buffers; 0 = no
  *                   cap): a call that would grow them beyond it returns
  *                   PC_ERR_BUDGET before anything is enqueued
  * Results are bitwise identical for every setting. */
-enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4 };
+enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4, PC_TUNE_DIRECT = 5,
+       PC_TUNE_STREAMS = 6 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 /* pc_device_bytes -- device bytes the operator holds now: its resident data

@@ -21,8 +21,12 @@ thread_local std::string g_emu_err;
 template <class T>
 void reduce_all(const pc::Plan& P, bool adj, int64_t B, const std::vector<T>& slots, int64_t per, T* OUT, int64_t ldo);
 
+// direct: the colour launches of the library (outputs zeroed, then every
+// item in the canonical order adds its written box into the output);
+// otherwise every item stages its box and the reduction sums them.
 template <class T>
-void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo) {
+void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, T* OUT, int64_t ldo,
+               bool direct = false) {
     using C = pc::cx<T>;
     const int64_t N = P.N;
     std::vector<T> spec(P.spec.begin(), P.spec.end());
@@ -31,14 +35,18 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
     const int64_t per = adj ? P.slot_adj : P.slot_fwd;
     std::vector<T> in((size_t)(B * N));
     for (int64_t b = 0; b < B; ++b) std::memcpy(&in[(size_t)(b * N)], U + b * ldu, sizeof(T) * (size_t)N);
-    std::vector<T> slots((size_t)(B * per), T(0));
+    std::vector<T> slots(direct ? 0 : (size_t)(B * per), T(0));
+    std::vector<T> out(direct ? (size_t)(B * N) : 0, T(0));
+    const std::vector<int32_t>& ord = adj ? P.order_adj : P.order_fwd;
     for (int64_t b = 0; b < B; ++b) {
-        for (const pc::Item& it : P.items) {
+        for (size_t pos = 0; pos < P.items.size(); ++pos) {
+            const pc::Item& it = P.items[direct ? (size_t)ord[pos] : pos];
             std::vector<C> buf((size_t)(it.n0 * it.ld + pc::tw_lds_elems(it)));
             for (auto& v : buf) v = C{T(1e30), T(1e30)};   // poison: unwritten reads show up
-            pc::Ctx<T> c = pc::make_ctx<T>(it, adj, &in[(size_t)(b * N)], &slots[(size_t)(b * per)], wts.data(),
-                                           reinterpret_cast<const C*>(spec.data()),
-                                           reinterpret_cast<const C*>(tw.data()), P.cols);
+            pc::Ctx<T> c = pc::make_ctx<T>(it, adj, &in[(size_t)(b * N)], direct ? nullptr : &slots[(size_t)(b * per)],
+                                           wts.data(), reinterpret_cast<const C*>(spec.data()),
+                                           reinterpret_cast<const C*>(tw.data()), P.cols,
+                                           direct ? &out[(size_t)(b * N)] : nullptr);
             const int nth = P.conv_threads;
             {
                 pc::Ctx<T> c0 = c;
@@ -58,6 +66,10 @@ void emu_apply(const pc::Plan& P, bool adj, int64_t B, const T* U, int64_t ldu, 
             for (int t = 0; t < nth; ++t) pc::phG(c, buf.data(), t, nth);
             for (int t = 0; t < nth; ++t) pc::phH(c, buf.data(), t, nth);
         }
+    }
+    if (direct) {
+        for (int64_t b = 0; b < B; ++b) std::memcpy(OUT + b * ldo, &out[(size_t)(b * N)], sizeof(T) * (size_t)N);
+        return;
     }
     reduce_all(P, adj, B, slots, per, OUT, ldo);
 }
@@ -239,6 +251,40 @@ int pc_emu_apply(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void
     else
         emu_apply<float>(e->plan, adj != 0, B, static_cast<const float*>(U), ldu, static_cast<float*>(OUT), ldo);
     return 0;
+}
+
+// The colour-launch path (d <= 2): items in the canonical order add their
+// written boxes into zeroed outputs.  Returns -1 for d = 3.
+int pc_emu_apply_direct(pc_emu* e, int adj, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo) {
+    if (e->plan.d == 3) return -1;
+    if (e->plan.dtype == PC_F64)
+        emu_apply<double>(e->plan, adj != 0, B, static_cast<const double*>(U), ldu, static_cast<double*>(OUT), ldo,
+                          true);
+    else
+        emu_apply<float>(e->plan, adj != 0, B, static_cast<const float*>(U), ldu, static_cast<float*>(OUT), ldo,
+                         true);
+    return 0;
+}
+
+// The canonical summation order of one direction (d <= 2): for each
+// position, the item index, its colour and its written box in the 2-D view
+// (row, column origin and extents), into out[6 * n_items]; returns the
+// number of colours (0 for d = 3).
+int64_t pc_emu_order(pc_emu* e, int adj, int32_t* out) {
+    const pc::Plan& P = e->plan;
+    const std::vector<int32_t>& ord = adj ? P.order_adj : P.order_fwd;
+    const std::vector<int32_t>& cbeg = adj ? P.cbeg_adj : P.cbeg_fwd;
+    if (cbeg.empty()) return 0;
+    for (size_t c = 0; c + 1 < cbeg.size(); ++c)
+        for (int32_t j = cbeg[c]; j < cbeg[c + 1]; ++j) {
+            const pc::Item& it = P.items[(size_t)ord[(size_t)j]];
+            const int32_t v[6] = {ord[(size_t)j], (int32_t)c,
+                                  adj ? it.g0 + it.in_off0 : it.g0 + it.out_off0,
+                                  adj ? it.g1 + it.in_off1 : it.g1 + it.out_off1,
+                                  adj ? it.in_n0 : it.out_n0, adj ? it.in_n1 : it.out_n1};
+            std::memcpy(out + 6 * (size_t)j, v, sizeof(v));
+        }
+    return (int64_t)cbeg.size() - 1;
 }
 
 int pc_emu_stats(pc_emu* e, int64_t* out8) {

@@ -36,6 +36,8 @@ constexpr int64_t kMinChunks = 4;
 // 3-D operators: default scratch bytes of one item group (all vectors of a
 // chunk), the plane spectra between the three kernels of the group.
 constexpr size_t kScratchCapBytes = size_t(512) << 20;
+// Colour launches: most streams that vector chunks run on at once.
+constexpr int kMaxLanes = 4;
 
 }  // namespace
 
@@ -53,6 +55,11 @@ struct pc_op {
     void* scratch = nullptr;      // 3-D plane spectra of one item group
     size_t scratch_bytes = 0;
     bool tune_overlap = false;    // reduce on the aux stream while the next chunk convolves
+    bool tune_direct = false;     // d <= 2: colour launches add into the outputs (no staging)
+    int tune_streams = 4;         // colour launches: vector chunks run on this many streams at once
+    hipStream_t lanes[kMaxLanes] = {};       // the library's streams of the colour launches
+    hipEvent_t lane_done[kMaxLanes] = {};    // end of each lane's work in the current call
+    hipEvent_t fork = nullptr;               // start of the current call on the caller's stream
     hipStream_t aux = nullptr;    // reductions overlap the next chunk's convolution here
     hipEvent_t ev_conv[2] = {nullptr, nullptr};
     hipEvent_t ev_red[2] = {nullptr, nullptr};
@@ -97,6 +104,11 @@ struct pc_op {
             hipEventDestroy(t.b);
         }
         for (hipEvent_t e : event_pool) hipEventDestroy(e);
+        for (int i = 0; i < kMaxLanes; ++i) {
+            if (lanes[i]) hipStreamDestroy(lanes[i]);
+            if (lane_done[i]) hipEventDestroy(lane_done[i]);
+        }
+        if (fork) hipEventDestroy(fork);
         for (void* p : allocs) hipFree(p);
         if (slots) hipFree(slots);
         if (scratch) hipFree(scratch);
@@ -363,6 +375,88 @@ pc_status run_batch_3d(pc_op* op, bool adj, bool plain, int64_t B, const void* U
     return run_3d(op, op->plan.items3, op->dev, op->dev, per, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
 }
 
+// d <= 2, colour launches: each vector chunk's outputs are zeroed, then the
+// items of each colour (pairwise disjoint written boxes) add their boxes
+// straight into the outputs, colour after colour, so every output point sums
+// its contributions in the canonical (colour, item) order - the order the
+// staged reduction uses.  The order only binds within a vector: chunks of
+// vectors run their colour sequences on up to tune_streams library streams
+// at once (forked from and joined back into s with events), so the tail of
+// one chunk's colour launch overlaps the next launches of the others.  No
+// work buffer is needed.
+pc_status lane_streams(pc_op* op, int n) {
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = hipSuccess;
+        if (!op->lanes[i]) e = hipStreamCreateWithFlags(&op->lanes[i], hipStreamNonBlocking);
+        if (e == hipSuccess && !op->lane_done[i]) e = hipEventCreateWithFlags(&op->lane_done[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "library stream setup");
+    }
+    if (!op->fork) {
+        hipError_t e = hipEventCreateWithFlags(&op->fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    return PC_OK;
+}
+
+pc_status run_direct(pc_op* op, bool adj, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
+                     hipStream_t s, int max_lanes = kMaxLanes) {
+    const pc::Plan& P = op->plan;
+    const std::vector<int32_t>& cbeg = adj ? P.cbeg_adj : P.cbeg_fwd;
+    const pc::Item* items = op->dev.items_ord[adj ? 1 : 0];
+    const int lanes_want = std::max(1, std::min(op->tune_streams, max_lanes));
+    int64_t chunk = op->tune_chunk > 0 ? op->tune_chunk : (B + lanes_want - 1) / lanes_want;
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, B));
+    const int64_t nchunks = (B + chunk - 1) / chunk;
+    const int lanes = (int)std::min<int64_t>(lanes_want, nchunks);
+    const bool cap = capturing(s);
+    if (lanes > 1) {
+        if (cap && !op->lanes[lanes - 1])
+            return fail(PC_ERR_ARG, "make one call with this stream setting before the stream capture");
+        pc_status st = lane_streams(op, lanes);
+        if (st != PC_OK) return st;
+    }
+    hipEvent_t ev_all;
+    prof_begin(op, s, &ev_all);   // one span: the colour launches of all lanes
+    hipError_t e;
+    if (lanes > 1) {
+        e = hipEventRecord(op->fork, s);
+        for (int i = 0; i < lanes && e == hipSuccess; ++i) e = hipStreamWaitEvent(op->lanes[i], op->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "stream fork");
+    }
+    const char* u = static_cast<const char*>(U);
+    char* o = static_cast<char*>(OUT);
+    pc_status st = PC_OK;
+    for (int64_t k = 0; k < nchunks && st == PC_OK; ++k) {
+        const int64_t b0 = k * chunk;
+        const int nb = (int)std::min<int64_t>(chunk, B - b0);
+        hipStream_t ls = lanes > 1 ? op->lanes[k % lanes] : s;
+        const void* in = u + (size_t)b0 * ldu * op->esz;
+        void* out = o + (size_t)b0 * ldo * op->esz;
+        e = pc::launch_fill_zero(P.dtype, out, ldo, P.N, nb, ls);
+        if (e != hipSuccess) st = hip_fail(e, "fill launch");
+        for (size_t c = 0; c + 1 < cbeg.size() && st == PC_OK; ++c) {
+            if (injected_failure(op)) {
+                st = injected();
+                break;
+            }
+            e = pc::launch_conv(op->dev, items, adj, cbeg[c], cbeg[c + 1], nb, in, ldu, nullptr, 0, out, ldo, ls);
+            if (e != hipSuccess) st = hip_fail(e, "conv launch");
+        }
+    }
+    if (lanes > 1) {   // join every lane, also after a failure, so s orders all work enqueued
+        for (int i = 0; i < lanes; ++i) {
+            e = hipEventRecord(op->lane_done[i], op->lanes[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, op->lane_done[i], 0);
+            if (e != hipSuccess && st == PC_OK) st = hip_fail(e, "stream join");
+        }
+    }
+    if (st != PC_OK) return st;
+    prof_end(op, s, ev_all, 0, (int)B);
+    return mark_used(op, s);
+}
+
+bool uses_direct(const pc_op* op) { return op->tune_direct && op->plan.d <= 2 && !op->plan.cbeg_fwd.empty(); }
+
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
                     hipStream_t s, bool acc = false, double alpha = 1.0) {
     pc_status st = check_op(op);
@@ -377,6 +471,7 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
         st = run_batch_3d(op, adj, plain, B, U, ldu, OUT, ldo, s, acc, alpha);
         return st == PC_OK ? mark_used(op, s) : st;
     }
+    if (!plain && !acc && uses_direct(op)) return run_direct(op, adj, B, U, ldu, OUT, ldo, s);
     const int64_t per = adj ? op->plan.slot_adj : op->plan.slot_fwd;
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     int64_t chunk = 1;
@@ -415,14 +510,14 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
             for (int it = 0; it < n_items; ++it) {
                 if (injected_failure(op)) return injected();
                 prof_begin(op, s, &ev);
-                e = pc::launch_conv(op->dev, adj, it, it + 1, 1, in, ldu, slots, per, s);
+                e = pc::launch_conv(op->dev, op->dev.items, adj, it, it + 1, 1, in, ldu, slots, per, nullptr, 0, s);
                 if (e != hipSuccess) return hip_fail(e, "conv launch");
                 prof_end(op, s, ev, 0, 1);
             }
         } else {
             if (injected_failure(op)) return injected();
             prof_begin(op, s, &ev);
-            e = pc::launch_conv(op->dev, adj, 0, n_items, nb, in, ldu, slots, per, s);
+            e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
             prof_end(op, s, ev, 0, nb);
         }
@@ -516,9 +611,22 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
         delete op;
         return st;
     }
+    void* d_ord[2] = {d_items, d_items};
+    for (int dir = 0; dir < 2 && !P.items.empty(); ++dir) {
+        const std::vector<int32_t>& ord = dir ? P.order_adj : P.order_fwd;
+        if (ord.size() != P.items.size()) continue;
+        std::vector<pc::Item> perm(ord.size());
+        for (size_t j = 0; j < ord.size(); ++j) perm[j] = P.items[(size_t)ord[j]];
+        if ((st = upload(op, perm, &d_ord[dir], s)) != PC_OK) {
+            delete op;
+            return st;
+        }
+    }
     pc::DevPlan& D = op->dev;
     D.items = static_cast<const pc::Item*>(d_items);
     D.n_items = (int)P.items.size();
+    D.items_ord[0] = static_cast<const pc::Item*>(d_ord[0]);
+    D.items_ord[1] = static_cast<const pc::Item*>(d_ord[1]);
     D.items3 = static_cast<const pc::Item3*>(d_items3);
     D.n_items3 = (int)P.items3.size();
     D.rows = P.rows;
@@ -692,6 +800,15 @@ pc_status pc_apply_batch_noalloc(pc_op* op, int64_t B, const void* U, int64_t ld
     if (B > 0x7fff) return fail(PC_ERR_ARG, "batch too large (B > 32767)");
     char* area = static_cast<char*>(pc::noalloc_area(op->device));
     if (!area) return fail(PC_ERR_DEVICE, "the allocation-free work area of this device was not set up");
+    if (uses_direct(op)) {   // the colour launches need no work area
+        struct NoProfiling {
+            pc_op* op;
+            bool was;
+            ~NoProfiling() { op->profiling = was; }
+        } guard{op, op->profiling};
+        op->profiling = false;
+        return run_direct(op, false, B, U, ldu, OUT, ldo, s, 1);   // the caller's stream only
+    }
     const size_t per_bytes = (size_t)std::max<int64_t>(P.slot_fwd, 1) * op->esz;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     if (al(per_bytes) > pc::kNoAllocBytes)
@@ -717,8 +834,8 @@ pc_status pc_apply_batch_noalloc(pc_op* op, int64_t B, const void* U, int64_t ld
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
         if (injected_failure(op)) return injected();
-        hipError_t e = pc::launch_conv(op->dev, false, 0, n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu, area,
-                                       P.slot_fwd, s);
+        hipError_t e = pc::launch_conv(op->dev, op->dev.items, false, 0, n_items, nb, u + (size_t)b0 * ldu * op->esz,
+                                       ldu, area, P.slot_fwd, nullptr, 0, s);
         if (e != hipSuccess) return hip_fail(e, "conv launch");
         e = pc::launch_reduce(op->dev, false, nb, area, P.slot_fwd, o + (size_t)b0 * ldo * op->esz, ldo, s);
         if (e != hipSuccess) return hip_fail(e, "reduce launch");
@@ -805,8 +922,8 @@ pc_status pc_apply_block(pc_op* op, int adjoint, const int64_t* tlo, const int64
     for (int64_t b0 = 0; b0 < B; b0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - b0);
         if (injected_failure(op)) return injected();
-        e = pc::launch_conv(Dc, adjoint != 0, 0, Dc.n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu, op->slots,
-                            bp.per, s);
+        e = pc::launch_conv(Dc, Dc.items, adjoint != 0, 0, Dc.n_items, nb, u + (size_t)b0 * ldu * op->esz, ldu,
+                            op->slots, bp.per, nullptr, 0, s);
         if (e != hipSuccess) return hip_fail(e, "block conv launch");
         e = pc::launch_reduce(Dr, adjoint != 0, nb, op->slots, bp.per, o + (size_t)b0 * ldo * op->esz, ldo, s);
         if (e != hipSuccess) return hip_fail(e, "block reduce launch");
@@ -941,6 +1058,13 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
         case PC_TUNE_SCRATCH:
             if (value < 0) return fail(PC_ERR_ARG, "scratch size out of range");
             op->tune_scratch = value;
+            return PC_OK;
+        case PC_TUNE_DIRECT:
+            op->tune_direct = value != 0;
+            return PC_OK;
+        case PC_TUNE_STREAMS:
+            if (value < 1 || value > kMaxLanes) return fail(PC_ERR_ARG, "streams out of range (1..4)");
+            op->tune_streams = (int)value;
             return PC_OK;
         case PC_TUNE_BUDGET:
             if (value < 0) return fail(PC_ERR_ARG, "budget out of range");

@@ -10,6 +10,7 @@ namespace pc {
 struct DevPlan {
     const Item* items;
     int n_items;
+    const Item* items_ord[2];       // the items in the canonical summation order (forward, adjoint), d <= 2
     const Item3* items3;            // 3-D operators
     int n_items3;
     int rows, cols;                 // 2-D view of Omega (reduction)
@@ -44,12 +45,17 @@ struct Conv3Launch {
     int max_gather, max_write, max_tiles;
 };
 
-// Convolution items -> staging (one workgroup per item and vector).
-// item_lo/item_hi restrict the launch to a range of items (the plain mode
-// launches one item at a time); B vectors starting at 'in'.
-hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi, int B,
-                       const void* in, int64_t ld_in, void* slots, int64_t slot_stride,
+// Convolution items (one workgroup per item and vector): items[item_lo,
+// item_hi) of the given array (the plain mode launches one item at a time),
+// B vectors starting at 'in'.  With out null the written boxes go to
+// staging; otherwise they are added into the B outputs at out (stride ldo),
+// which is only race-free and deterministic for items of one colour.
+hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
+                       const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
                        hipStream_t s);
+
+// out[b * ld + i] = 0 for b < B, i < N.
+hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, hipStream_t s);
 
 // 3-D convolution items -> staging (three kernels, see pc_phases3.h).
 hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s);

@@ -56,25 +56,37 @@ struct ConvArgs {
     int64_t ld_in;
     T* slots;
     int64_t slot_stride;
+    T* out;                 // non-null: add the written boxes into out (items of one colour)
+    int64_t ldo;
     int64_t pitch;
 };
 
 // One workgroup per (item, vector).  Blocks are dealt round-robin to the 8
-// XCDs (block id mod 8); the mapping below gives every XCD whole items with
-// all their vectors in sequence, so a patch's spectrum is fetched into one
-// XCD's L2 and reused there by every vector.
-template <class T, int NT>
+// XCDs (block id mod 8).  Staged launches (all items at once) give every
+// XCD whole items with all their vectors in sequence, so a patch's spectrum
+// is fetched into one XCD's L2 and reused there by every vector.  A colour
+// launch holds a few dozen items of uneven size, and whole items per XCD
+// would leave the XCD with the largest ones working alone at the end, so
+// there the blocks of one item run through all XCDs (item-major order).
+template <class T, int NT, bool ADD>
 __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     const int bid = blockIdx.x;
-    const int xcd = bid & 7, l = bid >> 3;
-    const int item = xcd + 8 * (l / A.B);
-    const int rhs = l % A.B;
+    int item, rhs;
+    if (ADD) {
+        item = bid / A.B;
+        rhs = bid - item * A.B;
+    } else {
+        const int xcd = bid & 7, l = bid >> 3;
+        item = xcd + 8 * (l / A.B);
+        rhs = l % A.B;
+    }
     if (item >= A.n_items) return;
     const Item it = A.items[A.item_lo + item];
-    Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, A.slots + (int64_t)rhs * A.slot_stride,
-                           A.wts, A.spec, A.tw, A.pitch);
+    T* const slot_vec = A.slots + (ADD ? 0 : (int64_t)rhs * A.slot_stride);
+    Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, slot_vec, A.wts, A.spec, A.tw, A.pitch,
+                           ADD ? A.out + (int64_t)rhs * A.ldo : nullptr);
     const int tid = threadIdx.x;
     twiddles_to_lds(c, buf + (int64_t)it.n0 * it.ld, tid, NT);
     phA0(c, buf, tid, NT);
@@ -93,7 +105,7 @@ __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     __syncthreads();
     phG(c, buf, tid, NT);
     __syncthreads();
-    phH(c, buf, tid, NT);
+    phH<4, ADD ? kOutAdd : kOutStage>(c, buf, tid, NT);
 }
 
 // ------------------------------------------------------------------- 3-D
@@ -375,12 +387,36 @@ __global__ __launch_bounds__(64) void est_final_kernel(const double* partials, i
     totals[1] = yy;
 }
 
+// Zero fill of B vectors of N elements at stride ld (the outputs that the
+// colour launches then add into; a kernel rather than a memset node, so the
+// apply records into graphs safely).
+template <class T>
+__global__ __launch_bounds__(256) void fill_zero_kernel(T* out, int64_t ld, int64_t N, int B) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int b = 0; b < B; ++b) {
+        T* o = out + (int64_t)b * ld;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) o[i] = T(0);
+    }
+}
+
+hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, hipStream_t s) {
+    if (N <= 0 || B <= 0) return hipSuccess;
+    const int64_t want = (N + 255) / 256;
+    const unsigned nb = (unsigned)(want < 8192 ? want : 8192);
+    if (dtype == 1)
+        hipLaunchKernelGGL(fill_zero_kernel<double>, dim3(nb), dim3(256), 0, s, static_cast<double*>(out), ld, N, B);
+    else
+        hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(nb), dim3(256), 0, s, static_cast<float*>(out), ld, N, B);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 template <class T>
-static hipError_t conv_t(const DevPlan& P, bool adj, int item_lo, int item_hi, int B, const void* in, int64_t ld_in,
-                         void* slots, int64_t slot_stride, hipStream_t s) {
+static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item_lo, int item_hi, int B,
+                         const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
+                         hipStream_t s) {
     ConvArgs<T> A;
-    A.items = P.items;
+    A.items = items;
     A.item_lo = item_lo;
     A.n_items = item_hi - item_lo;
     A.B = B;
@@ -392,26 +428,36 @@ static hipError_t conv_t(const DevPlan& P, bool adj, int item_lo, int item_hi, i
     A.ld_in = ld_in;
     A.slots = static_cast<T*>(slots);
     A.slot_stride = slot_stride;
+    A.out = static_cast<T*>(out);
+    A.ldo = ldo;
     A.pitch = P.cols;
     if (A.n_items <= 0 || B <= 0) return hipSuccess;
-    const int64_t per_xcd = (int64_t)((A.n_items + 7) / 8) * B;
-    const int64_t nblk = 8 * per_xcd;
+    const int64_t nblk = out ? (int64_t)A.n_items * B : 8 * ((int64_t)((A.n_items + 7) / 8) * B);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     if (P.conv_threads == 512) {
-        hipLaunchKernelGGL((conv_kernel<T, 512>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
-    } else {
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((conv_kernel<T, 1024>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+        if (out)
+            hipLaunchKernelGGL((conv_kernel<T, 512, true>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
         else
+            hipLaunchKernelGGL((conv_kernel<T, 512, false>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
+    } else {
+        if constexpr (sizeof(T) == 4) {
+            if (out)
+                hipLaunchKernelGGL((conv_kernel<T, 1024, true>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+            else
+                hipLaunchKernelGGL((conv_kernel<T, 1024, false>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+        } else {
             return hipErrorInvalidValue;   // FP64 items always use 512 threads
+        }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_conv(const DevPlan& P, bool adjoint, int item_lo, int item_hi, int B, const void* in, int64_t ld_in,
-                       void* slots, int64_t slot_stride, hipStream_t s) {
-    if (P.dtype == 1) return conv_t<double>(P, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, s);
-    return conv_t<float>(P, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, s);
+hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
+                       const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
+                       hipStream_t s) {
+    if (P.dtype == 1)
+        return conv_t<double>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s);
+    return conv_t<float>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s);
 }
 
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride, void* out,
@@ -457,8 +503,12 @@ hipError_t launch_est(int dtype, const int32_t* leaf_box, int n_leaves, int q, c
 
 hipError_t set_kernel_attributes() {
     const void* fns[] = {
-        reinterpret_cast<const void*>(&conv_kernel<float, 1024>), reinterpret_cast<const void*>(&conv_kernel<float, 512>),
-        reinterpret_cast<const void*>(&conv_kernel<double, 512>),
+        reinterpret_cast<const void*>(&conv_kernel<float, 1024, false>),
+        reinterpret_cast<const void*>(&conv_kernel<float, 512, false>),
+        reinterpret_cast<const void*>(&conv_kernel<double, 512, false>),
+        reinterpret_cast<const void*>(&conv_kernel<float, 1024, true>),
+        reinterpret_cast<const void*>(&conv_kernel<float, 512, true>),
+        reinterpret_cast<const void*>(&conv_kernel<double, 512, true>),
         reinterpret_cast<const void*>(&plane_fwd_kernel<float>), reinterpret_cast<const void*>(&plane_fwd_kernel<double>),
         reinterpret_cast<const void*>(&axis_kernel<float>),      reinterpret_cast<const void*>(&axis_kernel<double>),
         reinterpret_cast<const void*>(&plane_inv_kernel<float>), reinterpret_cast<const void*>(&plane_inv_kernel<double>)};

@@ -56,7 +56,10 @@ struct Ctx {
     int d_off0, d_n0, d_off1, d_n1;   // written box
     float inv_bm, inv_b0, inv_nc, inv_sn0, inv_dn0;
     const T* src;                     // input vector, Omega origin
-    T* dst;                           // staging box of this item and vector
+    T* dst;                           // written box: staging box of this item and vector, or
+                                      // (add) the output vector at the box's Omega origin
+    int64_t dst_rs;                   // row stride of dst (box width, or the Omega pitch)
+    bool add;                         // add into the output instead of storing to staging
     const T* w;                       // weight table of the item's input box
     const cx<T>* spec;
     int spec_ld;                      // spectrum row stride (m + 1 for 2-D items)
@@ -66,20 +69,30 @@ struct Ctx {
     int64_t pitch;                    // Omega row pitch (elements)
 };
 
+// out_vec: null to store the written box to the item's staging box in
+// slot_vec; else the output vector (Omega origin) that the written box is
+// added into, in place.
 template <class T>
 __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in_vec, T* slot_vec,
-                                           const T* wts, const cx<T>* spec, const cx<T>* tw, int64_t pitch) {
+                                           const T* wts, const cx<T>* spec, const cx<T>* tw, int64_t pitch,
+                                           T* out_vec = nullptr) {
     Ctx<T> c;
     c.it = it;
     c.adj = adj;
     if (!adj) {
         c.s_off0 = it.in_off0; c.s_n0 = it.in_n0; c.s_off1 = it.in_off1; c.s_n1 = it.in_n1;
         c.d_off0 = it.out_off0; c.d_n0 = it.out_n0; c.d_off1 = it.out_off1; c.d_n1 = it.out_n1;
-        c.dst = slot_vec + it.slot_fwd;
     } else {
         c.s_off0 = it.out_off0; c.s_n0 = it.out_n0; c.s_off1 = it.out_off1; c.s_n1 = it.out_n1;
         c.d_off0 = it.in_off0; c.d_n0 = it.in_n0; c.d_off1 = it.in_off1; c.d_n1 = it.in_n1;
-        c.dst = slot_vec + it.slot_adj;
+    }
+    c.add = out_vec != nullptr;
+    if (c.add) {
+        c.dst = out_vec + (int64_t)(it.g0 + c.d_off0) * pitch + it.g1 + c.d_off1;
+        c.dst_rs = pitch;
+    } else {
+        c.dst = slot_vec + (adj ? it.slot_adj : it.slot_fwd);
+        c.dst_rs = c.d_n1;
     }
     c.inv_bm = 1.0f / (float)it.bm;
     c.inv_b0 = 1.0f / (float)it.b0;
@@ -508,16 +521,39 @@ __host__ __device__ inline void phG(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     PC_RADIX_SWITCH(c.it.am, phG_r, c, buf, tid, nth);
 }
 
+// *p += v as one device atomic whose result is not used (the add is done
+// where the line lives, nothing returns to the wave, so no load latency is
+// exposed at the end of the workgroup).  Only the workgroups of one colour
+// launch touch a given element, and only once, so the atomic never races;
+// it rounds like a plain add (round to nearest even).
+template <class T>
+__host__ __device__ __forceinline__ void add_to(T* p, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    unsafeAtomicAdd(p, v);
+#else
+    *p = *p + v;
+#endif
+}
+
 // ---------------------------------------------------------------- phase H
-// Copy of the written box from LDS to the staging buffer (weighted for the
-// adjoint).  A fixed set of threads owns each column of the box, so
-// consecutive lanes write consecutive staging elements and no index is
-// divided per element.  The stores are non-temporal: staging is read once,
-// by the reduction after the launch, and streaming it past the L2 keeps the
-// spectra and inputs that the item's other vectors reuse (measured on the
-// 1024^2 workload: 5.17 -> 5.03 ms per apply, mostly in the reduction).
-template <int U = 4, class T>
+// The written box leaves LDS (weighted for the adjoint), either to the
+// item's staging box or, when the launch holds items of one colour (their
+// written boxes are disjoint), added straight into the output vector.  A
+// fixed set of threads owns each column of the box, so consecutive lanes
+// touch consecutive elements and no index is divided per element.
+// Staging stores are non-temporal: staging is read once, by the reduction
+// after the launch, and streaming it past the L2 keeps the spectra and
+// inputs that the item's other vectors reuse (measured on the 1024^2
+// workload: 5.17 -> 5.03 ms per apply, mostly in the reduction).
+// The weighted value is rounded before it is added (no fused multiply-add),
+// as the staged value is before the reduction adds it, so both ways give
+// the same bits.
+// OUT: kOutStage (staged kernel: stores only), kOutAdd (colour launches:
+// adds only) or kOutEither (the CPU emulation: c.add decides).
+enum { kOutStage = 0, kOutAdd = 1, kOutEither = 2 };
+template <int U = 4, int OUT = kOutEither, class T>
 __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nth) {
+#pragma clang fp contract(off)
     const int n1 = c.d_n1;
     const int rps = nth / n1;            // rows per sweep (n1 <= 256 <= nth)
     const int r0 = tid / n1, e = tid - r0 * n1;
@@ -526,6 +562,15 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     const int rstride = 2 * c.it.ld;
     const T* w = c.w + e;
     T* dst = c.dst + e;
+    const int64_t rs = c.dst_rs;
+    if (OUT == kOutAdd || (OUT == kOutEither && c.add)) {
+        // one atomic add per element; nothing returns, so no batching
+        for (int r = r0; r < c.d_n0; r += rps) {
+            const T p = rows[r * rstride] * (c.adj ? w[(int64_t)r * c.it.w_ld] : T(1));
+            add_to(&dst[(int64_t)r * rs], p);
+        }
+        return;
+    }
     // predicated batches of U rows: LDS reads (and adjoint weights) first
     for (int q = r0; q < c.d_n0; q += U * rps) {
         T v[U], f[U];
@@ -541,7 +586,7 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (q + u * rps < c.d_n0) __builtin_nontemporal_store(v[u] * f[u], &dst[(int64_t)(q + u * rps) * n1]);
+            if (q + u * rps < c.d_n0) __builtin_nontemporal_store(v[u] * f[u], &dst[(int64_t)(q + u * rps) * rs]);
     }
 }
 

@@ -58,7 +58,7 @@ template <class T>
 __host__ __device__ inline Ctx<T> plane_ctx_write(const Item3& I, bool adj, int q, const T* in_vec, T* slot_vec,
                                                   const T* wts, const cx<T>* spec, const cx<T>* tw, int64_t pitch) {
     Ctx<T> c = make_ctx<T>(I.p, adj, in_vec, slot_vec, wts, spec, tw, pitch);
-    c.dst += (int64_t)q * c.d_n0 * c.d_n1;
+    c.dst += (int64_t)q * c.d_n0 * c.dst_rs;
     if (adj) c.w += (int64_t)q * I.w_plane;
     return c;
 }
@@ -150,6 +150,8 @@ __host__ __device__ inline Ctx<T> axis_ctx(const Item3& I, bool adj, int c_lo, i
     c.inv_dn0 = 1.0f / (float)pl.d_n;
     c.src = nullptr;
     c.dst = nullptr;
+    c.dst_rs = 0;
+    c.add = false;
     c.w = nullptr;
     c.spec = spec + I.p.spec_off + c_lo;
     c.spec_ld = (int)plane_elems(I);

@@ -296,6 +296,51 @@ bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<
 }
 
 // Tiles, contributor lists and per-contributor boxes of both directions.
+void colour_boxes(const std::vector<Box>& boxes, int rows, int cols, std::vector<int32_t>& order,
+                  std::vector<int32_t>& cbeg) {
+    constexpr int kCell = 64;   // bucket grid for the overlap queries
+    const int gr = (rows + kCell - 1) / kCell, gc = (cols + kCell - 1) / kCell;
+    std::vector<std::vector<int32_t>> bucket((size_t)gr * gc);
+    const int n = (int)boxes.size();
+    std::vector<int32_t> colour((size_t)n, 0), stamp((size_t)n, -1);
+    std::vector<char> used;
+    int n_colours = 0;
+    for (int i = 0; i < n; ++i) {
+        const Box& b = boxes[(size_t)i];
+        if (b.n0 <= 0 || b.n1 <= 0) {
+            colour[(size_t)i] = 0;
+            n_colours = std::max(n_colours, 1);
+            continue;
+        }
+        const int r0 = b.lo0 / kCell, r1 = (b.lo0 + b.n0 - 1) / kCell;
+        const int c0 = b.lo1 / kCell, c1 = (b.lo1 + b.n1 - 1) / kCell;
+        used.assign((size_t)n_colours + 1, 0);
+        for (int r = r0; r <= r1; ++r)
+            for (int c = c0; c <= c1; ++c)
+                for (int32_t j : bucket[(size_t)r * gc + c]) {
+                    if (stamp[(size_t)j] == i) continue;
+                    stamp[(size_t)j] = i;
+                    const Box& o = boxes[(size_t)j];
+                    const bool meet = b.lo0 < o.lo0 + o.n0 && o.lo0 < b.lo0 + b.n0 && b.lo1 < o.lo1 + o.n1 &&
+                                      o.lo1 < b.lo1 + b.n1;
+                    if (meet) used[(size_t)colour[(size_t)j]] = 1;
+                }
+        int col = 0;
+        while (used[(size_t)col]) ++col;
+        colour[(size_t)i] = col;
+        n_colours = std::max(n_colours, col + 1);
+        for (int r = r0; r <= r1; ++r)
+            for (int c = c0; c <= c1; ++c) bucket[(size_t)r * gc + c].push_back(i);
+    }
+    // counting sort by colour, stable in the given order
+    cbeg.assign((size_t)n_colours + 1, 0);
+    for (int i = 0; i < n; ++i) ++cbeg[(size_t)colour[(size_t)i] + 1];
+    for (int c = 0; c < n_colours; ++c) cbeg[(size_t)c + 1] += cbeg[(size_t)c];
+    order.assign((size_t)n, 0);
+    std::vector<int32_t> fill(cbeg.begin(), cbeg.end() - 1);
+    for (int i = 0; i < n; ++i) order[(size_t)fill[(size_t)colour[(size_t)i]]++] = i;
+}
+
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err) {
     if (!build_tiles(bf, p.rows, p.cols, p.tiles_fwd, p.contrib_fwd, err) ||
         !build_tiles(ba, p.rows, p.cols, p.tiles_adj, p.contrib_adj, err))
@@ -339,7 +384,11 @@ pc_status build_block(const Plan& P, bool adjoint, const int64_t* tlo, const int
         return n > 0;
     };
     std::vector<Box> boxes;
-    for (const Item& it : P.items) {
+    const std::vector<int32_t>& order = adjoint ? P.order_adj : P.order_fwd;
+    for (size_t pos = 0; pos < P.items.size(); ++pos) {
+        // the canonical summation order, so that every output point sums its
+        // contributions as the full apply does
+        const Item& it = P.items[order.empty() ? pos : (size_t)order[pos]];
         // input box I and output box O in Omega coordinates
         const int64_t I0 = it.g0 + it.in_off0, I1 = it.g1 + it.in_off1;
         const int64_t O0 = it.g0, O1 = it.g1;
@@ -943,14 +992,21 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             }
         }
     }
-    // --------------------------------------------------- reduction tiles
+    // ------------------------- summation order and reduction tiles
     std::vector<Box> bf(p.items.size()), ba(p.items.size());
     for (size_t i = 0; i < p.items.size(); ++i) {
         const Item& it = p.items[i];
         bf[i] = Box{it.g0, it.g1, it.out_n0, it.out_n1, it.slot_fwd};
         ba[i] = Box{it.g0 + it.in_off0, it.g1 + it.in_off1, it.in_n0, it.in_n1, it.slot_adj};
     }
-    if (!finish_tiles(p, bf, ba, err)) return PC_ERR_UNSUPPORTED;
+    colour_boxes(bf, p.rows, p.cols, p.order_fwd, p.cbeg_fwd);
+    colour_boxes(ba, p.rows, p.cols, p.order_adj, p.cbeg_adj);
+    std::vector<Box> bfo(bf.size()), bao(ba.size());
+    for (size_t j = 0; j < bf.size(); ++j) {
+        bfo[j] = bf[(size_t)p.order_fwd[j]];
+        bao[j] = ba[(size_t)p.order_adj[j]];
+    }
+    if (!finish_tiles(p, bfo, bao, err)) return PC_ERR_UNSUPPORTED;
     p.planes = 1;
     p.prow = p.rows;
     p.leaf_box.resize(6 * L);

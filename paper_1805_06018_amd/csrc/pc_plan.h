@@ -49,7 +49,13 @@ struct Plan {
     std::vector<double> tw;          // interleaved complex twiddle tables
     std::vector<Tile> tiles_fwd, tiles_adj;
     std::vector<int32_t> contrib_fwd, contrib_adj;
-    std::vector<Box> boxes_fwd, boxes_adj;     // staging box of every item
+    // Canonical summation order of the contributions to an output point
+    // (d <= 2): ascending (colour, item), where the items of one colour write
+    // pairwise disjoint boxes (forward: output boxes, adjoint: input boxes).
+    // order_*: item indices in that order; cbeg_*: colour c holds positions
+    // [cbeg[c], cbeg[c + 1]) of order_*.  Empty for d = 3.
+    std::vector<int32_t> order_fwd, order_adj, cbeg_fwd, cbeg_adj;
+    std::vector<Box> boxes_fwd, boxes_adj;     // staging box of every item (canonical order)
     std::vector<Box> cboxes_fwd, cboxes_adj;   // staging box of every tile contributor
     std::vector<int32_t> leaf_box;   // [L][6]: plane, row, col origin and extents (planes x prow x cols view)
     // matrix entries (Sec. 3.1), in the planes x prow x cols view
@@ -106,8 +112,13 @@ struct SineBasis {
 // in ascending box order
 bool build_tiles(const std::vector<Box>& boxes, int rows, int cols, std::vector<Tile>& tiles,
                  std::vector<int32_t>& contrib, std::string& err);
+// Greedy colouring (first fit in the given order) of the boxes of a
+// rows x cols view: boxes of one colour are pairwise disjoint.  Writes the
+// order (ascending colour, then position) and the colour ranges.
+void colour_boxes(const std::vector<Box>& boxes, int rows, int cols, std::vector<int32_t>& order,
+                  std::vector<int32_t>& cbeg);
 // reduction tiles and contributor boxes of both directions from the
-// per-item staging boxes (ascending item order)
+// per-item staging boxes (given in the canonical summation order)
 bool finish_tiles(Plan& p, std::vector<Box>& bf, std::vector<Box>& ba, std::string& err);
 // Block apply (Sec. 3.3): OUT_T = A~[T, S] U_S or A~*[T, S] U_S, with U_S
 // row-major over the box S and OUT_T over the box T (d <= 2).  Every work

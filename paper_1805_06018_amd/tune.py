@@ -1,12 +1,14 @@
 """Autotuner of the apply schedule.
 
 The library's schedule knobs (pc_set_tuning) change how a batched apply is
-cut into launches, never what it computes: vectors per convolution launch
-(PC_TUNE_CHUNK), reduction overlapped on a second stream (PC_TUNE_OVERLAP,
-1-D/2-D operators) and the plane-spectrum scratch per item group
-(PC_TUNE_SCRATCH, 3-D operators).  autotune() times each candidate setting
-on the caller's own vectors, checks that every schedule gives the bitwise
-same result, applies the fastest and returns the whole table.  Results can
+cut into launches, never what it computes: colour launches adding into the
+outputs or staged boxes and a reduction (PC_TUNE_DIRECT, 1-D/2-D
+operators), vectors per convolution launch (PC_TUNE_CHUNK), reduction
+overlapped on a second stream (PC_TUNE_OVERLAP, staged 1-D/2-D) and the
+plane-spectrum scratch per item group (PC_TUNE_SCRATCH, 3-D operators).
+autotune() times each candidate setting on the caller's own vectors, checks
+that every schedule gives the bitwise same result, applies the fastest and
+returns the whole table.  Results can
 be cached in a JSON file keyed by the operator's shape, size and batch.
 """
 import json
@@ -25,6 +27,9 @@ def candidates(op, B, allow_overlap=True):
     reduction on the caller's stream (each kernel then runs alone, which is
     what per-kernel timing needs)."""
     default = {_lib.PC_TUNE_CHUNK: 0, _lib.PC_TUNE_OVERLAP: 0, _lib.PC_TUNE_SCRATCH: 0}
+    if op.d < 3:
+        default[_lib.PC_TUNE_DIRECT] = 0
+        default[_lib.PC_TUNE_STREAMS] = 4
     out = [dict(default)]
     # powers of two and the sizes in between (for B = 64: 8, 10, 12, 16, 20,
     # 22, 24, 28, 32, 64); a batch that a chunk does not divide ends with a
@@ -39,13 +44,20 @@ def candidates(op, B, allow_overlap=True):
                 if c != default:
                     out.append(c)
     else:
-        for overlap in ((0, 1) if allow_overlap else (0,)):
+        for overlap in ((0, 1) if allow_overlap else (0,)):   # staged boxes and a reduction
             for chunk in [0] + chunks:
                 c = dict(default)
                 c[_lib.PC_TUNE_CHUNK] = chunk
                 c[_lib.PC_TUNE_OVERLAP] = overlap
                 if c != default:
                     out.append(c)
+        for streams in (4, 2, 1):               # colour launches
+            for chunk in [0] + [x for x in chunks if x <= max(1, B // 2)]:
+                c = dict(default)
+                c[_lib.PC_TUNE_DIRECT] = 1
+                c[_lib.PC_TUNE_STREAMS] = streams
+                c[_lib.PC_TUNE_CHUNK] = chunk
+                out.append(c)
     return out
 
 
@@ -107,7 +119,8 @@ def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=T
 
 
 def names(setting):
-    """Readable form of a setting: {"chunk": .., "overlap": .., "scratch_MiB": ..}."""
+    """Readable form of a setting: {"direct": .., "chunk": .., "overlap": .., "scratch_MiB": ..}."""
     s = {int(k): v for k, v in setting.items()}
-    return {"chunk": s.get(_lib.PC_TUNE_CHUNK, 0), "overlap": s.get(_lib.PC_TUNE_OVERLAP, 0),
-            "scratch_MiB": s.get(_lib.PC_TUNE_SCRATCH, 0) // _MiB}
+    return {"direct": s.get(_lib.PC_TUNE_DIRECT, 0), "streams": s.get(_lib.PC_TUNE_STREAMS, 1),
+            "chunk": s.get(_lib.PC_TUNE_CHUNK, 0),
+            "overlap": s.get(_lib.PC_TUNE_OVERLAP, 0), "scratch_MiB": s.get(_lib.PC_TUNE_SCRATCH, 0) // _MiB}

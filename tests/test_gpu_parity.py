@@ -93,6 +93,26 @@ def test_batch_column_equals_single_apply_and_plain(lib):
     torch.cuda.synchronize()
     assert torch.equal(Obig[:, :w.N], out[:3])
     assert torch.all(Obig[:, w.N:] == 7.0)
+    # colour launches (outputs zeroed, each colour's disjoint boxes added in
+    # place, vector chunks on 1, 2 or 4 streams): the same bits, forward and
+    # adjoint, also into strided outputs
+    adj_ref = torch.zeros_like(U)
+    op.apply_adjoint_batch(U, adj_ref)
+    op.set_tuning(lib.PC_TUNE_DIRECT, 1)
+    for streams, chunk in ((1, 0), (2, 0), (4, 2), (4, 0)):
+        op.set_tuning(lib.PC_TUNE_STREAMS, streams)
+        op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
+        got = torch.full_like(U, float("nan"))
+        op.apply_batch(U, got)
+        gota = torch.full_like(U, float("nan"))
+        op.apply_adjoint_batch(U, gota)
+        Ob = torch.full((3, w.N + 64), 7.0, dtype=torch.float32, device="cuda")
+        op.apply_batch(Ubig[:, :w.N], Ob[:, :w.N])
+        torch.cuda.synchronize()
+        assert torch.equal(got, out) and torch.equal(gota, adj_ref), (streams, chunk)
+        assert torch.equal(Ob[:, :w.N], out[:3]) and torch.all(Ob[:, w.N:] == 7.0)
+    op.set_tuning(lib.PC_TUNE_DIRECT, 0)
+    op.set_tuning(lib.PC_TUNE_CHUNK, 0)
 
 
 FULL_VECTORS = tuple(range(0, 64, 9))   # 8 of the 64 vectors: 0, 9, ..., 63
@@ -261,6 +281,7 @@ def test_work_buffer_budget_and_device_sums(lib):
     sums left on the device give the same numbers as pc_estimate_sums."""
     w = make_config(1, scale=0.25)
     op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    op.set_tuning(lib.PC_TUNE_DIRECT, 0)                 # the staged schedule (colour launches need no buffer)
     per = op.stats()["slot_elems_fwd"] * 4
     op.set_tuning(lib.PC_TUNE_BUDGET, 2 * per)
     U = torch.from_numpy(w.vectors(6, dtype=np.float32)).cuda()
@@ -272,6 +293,7 @@ def test_work_buffer_budget_and_device_sums(lib):
     assert torch.all(out == 5.0)
     op.apply_batch(U[:2], out[:2])                       # fits: 2 vectors of staging
     op.set_tuning(lib.PC_TUNE_BUDGET, 0)
+    assert op.device_bytes() >= op.stats()["device_bytes"] + 2 * per
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         op.apply_batch(U, out, stream=side)              # grows the staging on another stream

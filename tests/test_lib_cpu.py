@@ -87,12 +87,17 @@ def _emu_lib(path=os.path.join(PKG, "libpc_emu.so")):
     lib.pc_emu_create_patches.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P, P, P,
                                           ctypes.c_int, ctypes.c_uint32, ctypes.c_int64, P, ctypes.POINTER(P)]
     lib.pc_emu_apply.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64]
+    lib.pc_emu_apply_direct.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64]
+    lib.pc_emu_items.argtypes = [P, P]
+    lib.pc_emu_items.restype = ctypes.c_int64
+    lib.pc_emu_order.argtypes = [P, ctypes.c_int, P]
+    lib.pc_emu_order.restype = ctypes.c_int64
     lib.pc_emu_destroy.argtypes = [P]
     lib.pc_emu_last_error.restype = ctypes.c_char_p
     return lib
 
 
-def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None):
+def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None, direct=False):
     k = [np.ascontiguousarray(v, dtype=np.int64) for v in (w.shape, w.leaf_lo, w.leaf_hi, w.points, w.radius)]
     phi = np.ascontiguousarray(w.phi, dtype=np.float64)
     off = np.ascontiguousarray(w.phi_off, dtype=np.int64)
@@ -110,7 +115,8 @@ def emu_apply(lib, w, U, dtype, flags=0, adj=False, patches=None):
     dt = np.float64 if dtype == 1 else np.float32
     U = np.ascontiguousarray(U, dtype=dt)
     out = np.zeros_like(U)
-    lib.pc_emu_apply(h, int(adj), U.shape[0], U.ctypes.data, U.shape[1], out.ctypes.data, out.shape[1])
+    fn = lib.pc_emu_apply_direct if direct else lib.pc_emu_apply
+    assert fn(h, int(adj), U.shape[0], U.ctypes.data, U.shape[1], out.ctypes.data, out.shape[1]) == 0
     lib.pc_emu_destroy(h)
     return out
 
@@ -149,6 +155,36 @@ def test_emulated_term_subsets_match_oracle(name):
                 assert np.all(got == 0.0)
             else:
                 assert relerr(got, ref).max() <= TOL[1], (name, sel.size, adj)
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_colour_launches_equal_staged_reduction(idx):
+    """The colour-launch path (outputs zeroed, items of each colour adding
+    their written boxes in place, colour after colour) gives the same bits as
+    staging every box and summing in the reduction, FP32 and FP64, forward
+    and adjoint; and the items of one colour write pairwise disjoint boxes,
+    so their adds cannot race on the GPU."""
+    name, w = small_cases()[idx]
+    lib = _emu_lib()
+    U = np.random.default_rng(500 + idx).standard_normal((2, w.N))
+    for dtype in (0, 1):
+        for adj in (False, True):
+            staged = emu_apply(lib, w, U, dtype, 0, adj)
+            direct = emu_apply(lib, w, U, dtype, 0, adj, direct=True)
+            assert np.array_equal(staged, direct), (name, dtype, adj)
+    h = _emu_handle(lib, w)
+    n = int(lib.pc_emu_items(h, None))
+    for adj in (0, 1):
+        tab = np.zeros((n, 6), dtype=np.int32)
+        n_col = lib.pc_emu_order(h, adj, tab.ctypes.data)
+        assert n_col >= 1 and sorted(tab[:, 0]) == list(range(n)) and np.all(np.diff(tab[:, 1]) >= 0)
+        for c in range(n_col):
+            boxes = tab[tab[:, 1] == c][:, 2:]
+            cover = np.zeros((max(1, w.shape[0]) if w.d == 2 else 1, w.shape[-1]), dtype=np.int32)
+            for r0, c0, n0, n1 in boxes:
+                cover[r0:r0 + n0, c0:c0 + n1] += 1
+            assert cover.max() <= 1, (name, adj, c)
+    lib.pc_emu_destroy(h)
 
 
 def test_create_patches_rejects_bad_selection():
@@ -309,6 +345,8 @@ def test_emulated_kernels_under_address_sanitizer():
         "    for dt in (0, 1):\n"
         "        for fl in (0, 1):\n"
         "            for adj in (0, 1): emu_apply(lib, w, U, dt, fl, adj)\n"
+        "            if w.d < 3:\n"
+        "                for adj in (0, 1): emu_apply(lib, w, U, dt, fl, adj, direct=True)\n"
         "print('ASAN-CLEAN')\n" % (ROOT, lib))
     env = dict(os.environ, LD_PRELOAD=asan_rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
@@ -317,15 +355,18 @@ def test_emulated_kernels_under_address_sanitizer():
 
 def test_autotune_candidates():
     """The autotuner's candidate schedules: the library default first, no
-    duplicates, 3-D candidates vary chunk and scratch, 2-D chunk and overlap."""
+    duplicates, 3-D candidates vary chunk and scratch, 2-D colour launches
+    against staging, chunk and overlap."""
     import types
     from paper_1805_06018_amd import _lib, tune
-    for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP}), (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
+    defaults = {_lib.PC_TUNE_DIRECT: 0, _lib.PC_TUNE_STREAMS: 4}
+    for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP, _lib.PC_TUNE_DIRECT, _lib.PC_TUNE_STREAMS}),
+                    (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
         c = tune.candidates(types.SimpleNamespace(d=d), 16)
-        assert all(v == 0 for v in c[0].values())
-        assert len({tuple(sorted(x.items())) for x in c}) == len(c)
-        varied = {k for x in c for k, v in x.items() if v != 0}
+        assert all(v == defaults.get(k, 0) for k, v in c[0].items())
+        varied = {k for x in c for k, v in x.items() if v != c[0][k]}
         assert varied == keys, (d, varied)
+        assert len({tuple(sorted(x.items())) for x in c}) == len(c)
         assert all(1 <= x[_lib.PC_TUNE_CHUNK] <= 16 for x in c if x[_lib.PC_TUNE_CHUNK])
 
 
