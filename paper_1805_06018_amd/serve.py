@@ -84,19 +84,34 @@ class _Batch:
     def __init__(self, op, reqs, stream, nbytes, finish=None):
         self.op, self.reqs, self.stream, self.nbytes = op, reqs, stream, nbytes
         self.finish = finish          # called once the event has fired
+        self.large = False
         self.event = torch.cuda.Event()
 
 
 class Server:
-    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=4):
+    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=4, large_work=256 << 20):
+        """max_batch: vectors merged into one launch; large_work: requests
+        whose work (_work) exceeds it run alone, and merged batches stay
+        below it."""
         self.ops = residents
         self.budget = hbm_budget
         self.max_batch = max_batch
+        self.large_work = large_work
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.resident_bytes = sum(r.work_bytes for r in residents)
         if self.resident_bytes > self.budget:
             raise ValueError("resident operators exceed the HBM budget")
         self.launch_failures = 0
+
+    def _work(self, B, op):
+        """Relative cost of B vectors on an operator: grid points, a 3-D
+        point weighted 10 (the 3-D apply runs about ten times fewer grid
+        points per second than the 2-D one)."""
+        r = self.ops[op]
+        return B * r.N * (10 if r.pc.d == 3 else 1)
+
+    def _large(self, q):
+        return self._work(q.B, q.op) > self.large_work
 
     def _failed(self, reqs, err, pending, t):
         """A launch failed: nothing of it was enqueued and the operator stays
@@ -130,6 +145,7 @@ class Server:
             q.result = out[o:o + q.B]
             o += q.B
         b = _Batch(op, reqs, stream, 2 * Bt * r.N * 4)
+        b.large = self._work(Bt, op) > self.large_work
         b.event.record(stream)
         return b
 
@@ -149,6 +165,7 @@ class Server:
             q.result = r.pc.eta_from_sums(host.numpy(), q.B)
 
         b = _Batch(q.op, [q], stream, q.B * r.N * 4, finish)
+        b.large = self._large(q)
         b.event.record(stream)
         return b
 
@@ -204,9 +221,32 @@ class Server:
                 inflight.append(b)
                 batches.append(1)
                 continue
-            # batched: the operator of the oldest waiting request that is free
+            # batched: the oldest waiting request whose operator is free.  A
+            # large request (work above large_work) is served as in the
+            # sequential loop - it waits for the device to drain, then runs
+            # alone - so the requests that set the latency tail are never
+            # slowed by sharing the device; small requests are merged and
+            # overlapped, and do not overtake a large request at the head
+            if any(b.large for b in inflight):
+                continue
             head = next((q for q in pending if q.op not in busy_ops), None)
             if head is None:
+                continue
+            if self._large(head):
+                if inflight:
+                    continue
+                pending.remove(head)
+                try:
+                    b = (self._launch_estimate(head, stream) if head.kind == "estimate"
+                         else self._launch_apply(head.op, [head], stream))
+                except _lib.PcError as e:
+                    self._failed([head], e, pending, now())
+                    continue
+                inflight.append(b)
+                busy_ops.add(head.op)
+                inflight_bytes += b.nbytes
+                peak = max(peak, self.resident_bytes + inflight_bytes)
+                batches.append(1)
                 continue
             r = self.ops[head.op]
             if head.kind == "estimate":
@@ -236,6 +276,8 @@ class Server:
                 if take and (q.solo or head.solo):   # a retried request runs alone
                     break
                 nb = 2 * (vecs + q.B) * r.N * 4
+                if take and self._work(vecs + q.B, head.op) > self.large_work:
+                    break
                 if vecs + q.B > self.max_batch or self.resident_bytes + inflight_bytes + nb > self.budget:
                     break
                 take.append(q)
@@ -330,7 +372,12 @@ def main(argv=None):
     ap.add_argument("--ops", choices=["2d", "all"], default="all")
     ap.add_argument("--plain-requests", type=int, default=40)
     ap.add_argument("--loads", type=str, default="0.5,0.8,1.0")
+    ap.add_argument("--large-mwork", type=float, default=256.0,
+                    help="requests whose work (vectors x grid points, 3-D points x 10) exceeds this many "
+                         "million run alone in the batched loop")
     args = ap.parse_args(argv)
+    cmd = "python -m paper_1805_06018_amd.serve " + " ".join(sys.argv[1:] if argv is None else argv)
+    print(json.dumps({"command": cmd.strip()}), flush=True)
     t0 = time.time()
     res = build_residents(make_serving_ops(with_3d=(args.ops == "all")),
                           log=lambda r: print(json.dumps(r), flush=True))
@@ -338,7 +385,7 @@ def main(argv=None):
     budget = int(args.budget_gib * 2**30) if args.budget_gib > 0 else resident + (4 << 30)
     print(json.dumps({"ops": [r.name for r in res], "setup_s": time.time() - t0,
                       "resident_gib": resident / 2**30, "budget_gib": budget / 2**30}), flush=True)
-    srv = Server(res, hbm_budget=budget)
+    srv = Server(res, hbm_budget=budget, large_work=int(args.large_mwork * 2**20))
     # warm-up, then the saturated rate of one-request-at-a-time fused applies
     srv.run(poisson_requests(24, len(res), 0.0), mode="sequential")
     sat = srv.run(poisson_requests(args.requests // 4, len(res), 0.0), mode="sequential")
