@@ -785,6 +785,41 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 }
                 E[(size_t)((z0 - zlo[0]) * K[1] + (z1 - zlo[1]))] = v;
             }
+        // The box above allows for the largest neighbour radius, but phi_k^E
+        // is zero wherever p_k + z lies in Omega and z is outside phi_k's own
+        // box (the extension only fills offsets that leave Omega), so away
+        // from the boundary most of that margin is zero.  The kernel box is
+        // cut to the bounding box of the non-zero entries: the same sum,
+        // with shorter FFTs and smaller output boxes.
+        {
+            int64_t lo0 = K[0], hi0 = -1, lo1 = K[1], hi1 = -1;
+            for (int64_t i0 = 0; i0 < K[0]; ++i0)
+                for (int64_t i1 = 0; i1 < K[1]; ++i1)
+                    if (E[(size_t)(i0 * K[1] + i1)] != 0.0) {
+                        lo0 = std::min(lo0, i0);
+                        hi0 = std::max(hi0, i0);
+                        lo1 = std::min(lo1, i1);
+                        hi1 = std::max(hi1, i1);
+                    }
+            if (hi0 < 0) {   // an all-zero kernel: keep one (zero) entry at the smallest |z| in the box
+                lo0 = hi0 = std::min(std::max<int64_t>(-zlo[0], 0), K[0] - 1);
+                lo1 = hi1 = std::min(std::max<int64_t>(-zlo[1], 0), K[1] - 1);
+            }
+            if (lo0 > 0 || hi0 < K[0] - 1 || lo1 > 0 || hi1 < K[1] - 1) {
+                const int64_t K0 = hi0 - lo0 + 1, K1 = hi1 - lo1 + 1;
+                std::vector<double> T((size_t)(K0 * K1));
+                for (int64_t i0 = 0; i0 < K0; ++i0)
+                    for (int64_t i1 = 0; i1 < K1; ++i1)
+                        T[(size_t)(i0 * K1 + i1)] = E[(size_t)((i0 + lo0) * K[1] + (i1 + lo1))];
+                E.swap(T);
+                zlo[0] += lo0;
+                zlo[1] += lo1;
+                zhi[0] = zlo[0] + K0 - 1;
+                zhi[1] = zlo[1] + K1 - 1;
+                K[0] = K0;
+                K[1] = K1;
+            }
+        }
         // algorithmic flops by the unsplit 7-smooth convention
         {
             int64_t nn = (int64_t)smallest_7smooth(m[0] + K[0] - 1) * smallest_7smooth(m[1] + K[1] - 1);

@@ -349,9 +349,19 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
             g.m[i] = Uhi[3 * k + i] - Ulo[3 * k + i] + 1;
             Rm[i] = Rd[k * 3 + i];
         }
-        if (extend)
+        if (extend) {
             for (int64_t j : nbrs[k])
                 for (int i = 0; i < 3; ++i) Rm[i] = std::max(Rm[i], Rd[j * 3 + i]);
+            // phi_k^E differs from phi_k only at offsets z with p_k + z
+            // outside Omega; if the neighbour-radius box around p_k stays in
+            // Omega, phi_k^E is zero outside phi_k's own box, which is then
+            // the kernel box (shorter FFTs, smaller output boxes, same sum)
+            bool inside = true;
+            for (int i = 0; i < 3; ++i)
+                inside = inside && Pt[k * 3 + i] - Rm[i] >= 0 && Pt[k * 3 + i] + Rm[i] <= n[i] - 1;
+            if (inside)
+                for (int i = 0; i < 3; ++i) Rm[i] = Rd[k * 3 + i];
+        }
         g.kel = 1;
         for (int i = 0; i < 3; ++i) {
             g.zlo[i] = std::max(-Rm[i], -(Uhi[3 * k + i]));
