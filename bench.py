@@ -1,7 +1,8 @@
 """Benchmark of the product-convolution apply on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--workload blur1024|blur3d] [--dtype f32|f64] [--no-graph] [--no-autotune]
+                [--workload blur1024|blur3d] [--dtype f32|f64] [--plan auto|cost|smallest]
+                [--no-graph] [--no-autotune]
 
 A step is one pc_apply_batch of the whole hot path (gather with weights,
 forward FFT, spectral product, inverse FFT, deterministic scatter-add) with
@@ -34,7 +35,7 @@ TRAFFIC_SOURCES = ["paper_1805_06018_amd/csrc/" + f
                    for f in ("pc_kernels.hip", "pc_phases.h", "pc_fft.h", "pc_internal.h", "pc_plan.cpp")]
 
 
-def measured_traffic(vectors_per_launch):
+def measured_traffic(vectors_per_launch, plan_flags=0):
     import hashlib
     import re
     try:
@@ -45,10 +46,10 @@ def measured_traffic(vectors_per_launch):
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    for m in re.finditer(r"traffic vectors_per_launch=(\d+) bytes_per_launch=([0-9.eE+]+) "
+    for m in re.finditer(r"traffic plan_flags=(\d+) vectors_per_launch=(\d+) bytes_per_launch=([0-9.eE+]+) "
                          r"sources_sha256=([0-9a-f]{64})", text):
-        if int(m.group(1)) == vectors_per_launch and m.group(3) == h.hexdigest():
-            return float(m.group(2))
+        if (int(m.group(1)), int(m.group(2))) == (plan_flags, vectors_per_launch) and m.group(4) == h.hexdigest():
+            return float(m.group(3))
     return None
 
 
@@ -61,6 +62,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--workload", choices=["blur1024", "blur3d"], default="blur1024")
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--plan", choices=["auto", "cost", "smallest"], default="auto",
+                    help="FFT lengths of the 2-D plan: the autotuner's pick of the two (auto), the "
+                         "planner's cost model (cost) or the smallest supported lengths (smallest)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default schedule instead of the autotuner's choice")
     ap.add_argument("--no-graph", action="store_true",
@@ -89,8 +93,9 @@ def main():
     f64 = args.dtype == "f64"
     ndt = np.float64 if f64 else np.float32
     esz = 8 if f64 else 4
+    plan_flags = _lib.PC_PLAN_SMALLEST_FFT if args.plan == "smallest" else 0
     t0 = time.time()
-    op = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F64 if f64 else _lib.PC_F32)
+    op = _lib.PcOperator.from_workload(w, dtype=_lib.PC_F64 if f64 else _lib.PC_F32, flags=plan_flags)
     t_create = time.time() - t0
     st = op.stats()
     U = torch.from_numpy(w.vectors(B, dtype=ndt)).to(dev)
@@ -98,14 +103,24 @@ def main():
     print(f"# workload {w.name}: N={w.N} r={w.r} B={B} items={st['n_items']} create={t_create:.2f}s",
           file=sys.stderr, flush=True)
 
-    schedule = {"autotuned": False}
+    schedule = {"autotuned": False, "plan_flags": plan_flags}
     if not args.no_autotune:
         from paper_1805_06018_amd import tune
         t_tune = time.time()
         # reductions stay on the launch stream: the convolution kernel then
         # runs alone and its per-launch time is its own
-        res = tune.autotune(op, U, OUT, allow_overlap=False)
-        schedule = {"autotuned": True, "chosen": tune.names(res["best"]), "best_ms": res["best_ms"],
+        if three_d or args.plan != "auto":
+            res = tune.autotune(op, U, OUT, allow_overlap=False)
+            res["plan_flags"], res["plans"] = plan_flags, []
+        else:
+            op.close()
+            op, res = tune.autotune_plan(
+                lambda fl: _lib.PcOperator.from_workload(w, dtype=_lib.PC_F64 if f64 else _lib.PC_F32, flags=fl),
+                U, OUT, allow_overlap=False)
+            st = op.stats()
+            plan_flags = res["plan_flags"]
+        schedule = {"autotuned": True, "plan_flags": res["plan_flags"], "plans": res["plans"],
+                    "chosen": tune.names(res["best"]), "best_ms": res["best_ms"],
                     "default_ms": res["default_ms"], "candidates": len(res["table"]),
                     "tune_s": time.time() - t_tune}
         print(f"# autotune: {schedule}", file=sys.stderr, flush=True)
@@ -209,7 +224,7 @@ def main():
         chunk = min(cap, chunk if chunk > 0 else B)
         sizes = [chunk] * (B // chunk) + ([B % chunk] if B % chunk else [])
         if len(sizes) == prof["conv_launches"] / args.steps:
-            per = [measured_traffic(v) for v in sizes]
+            per = [measured_traffic(v, plan_flags) for v in sizes]
             if all(x is not None for x in per):
                 traffic = sum(per) / len(per)
 

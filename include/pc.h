@@ -79,6 +79,13 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  * rounding; a scheduling choice. */
 #define PC_PLAN_HALF_LDS (1u << 1)
 
+/* 1-D/2-D plans: the smallest supported FFT lengths, pieces by the least
+ * n log n.  By default the planner picks lengths up to 35 % longer where a
+ * cheaper radix factorisation and the staged output volume give a lower
+ * estimated time (instruction counts of the compiled codelets).  Same
+ * results to rounding; a scheduling choice. */
+#define PC_PLAN_SMALLEST_FFT (1u << 2)
+
 /* pc_create -- build the operator (Sec. 2.2, 2.4, 2.5) and its device data.
  *
  *  d, shape[d]          : Omega.
@@ -98,7 +105,7 @@ typedef enum { PC_F32 = 0, PC_F64 = 1 } pc_dtype;
  *                         phi_k is taken as 0 outside the supplied box.
  *  dtype                : arithmetic of the apply (FP32 or FP64).  Setup is
  *                         FP64; the spectra are rounded once to dtype.
- *  flags                : PC_NO_EXTEND, PC_PLAN_HALF_LDS, or 0.
+ *  flags                : PC_NO_EXTEND, PC_PLAN_HALF_LDS, PC_PLAN_SMALLEST_FFT, or 0.
  *  s                    : stream of the uploads (synchronised before return;
  *                         no device-wide synchronisation).
  *  out                  : receives the operator.

@@ -18,6 +18,7 @@ PC_OK, PC_ERR_ARG, PC_ERR_GRID, PC_ERR_OOM, PC_ERR_BUDGET, PC_ERR_DEVICE, PC_ERR
 PC_F32, PC_F64 = 0, 1
 PC_NO_EXTEND = 1
 PC_PLAN_HALF_LDS = 2
+PC_PLAN_SMALLEST_FFT = 4
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "

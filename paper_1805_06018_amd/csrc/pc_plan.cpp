@@ -49,6 +49,23 @@ int next_fft_size(int need) {
 
 int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
 
+// FP32 vector instructions per complex point of one codelet pass, counted in
+// the compiled codelets (adds, multiplies, fused multiply-adds) for radix
+// 1, 2, ..., 16 (0 where there is no codelet).
+double radix_cost(int r) {
+    static const double c[17] = {0, 0, 2.0, 4.67, 4.0, 7.2, 8.0, 9.43, 6.75, 11.11, 10.8, 0, 10.0, 0, 13.14, 14.0, 9.75};
+    return (r >= 0 && r <= 16) ? c[r] : 1e9;
+}
+
+// Instructions per complex point of a two-pass length-n transform: both
+// codelets, the twiddle between the passes and the index work of the two
+// LDS sweeps.
+double fft_point_cost(int n) {
+    int a, b;
+    if (!fft_factor(n, &a, &b)) return 1e9;
+    return radix_cost(a) + radix_cost(b) + ((a > 1 && b > 1) ? 6.0 : 0.0) + 4.0;
+}
+
 int smallest_7smooth(int64_t need) {
     for (int64_t n = std::max<int64_t>(need, 1);; ++n) {
         int64_t m = n;
@@ -456,7 +473,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         err = "dtype must be PC_F32 or PC_F64";
         return PC_ERR_ARG;
     }
-    if (a.flags & ~(uint32_t)(PC_NO_EXTEND | PC_PLAN_HALF_LDS)) {
+    if (a.flags & ~(uint32_t)(PC_NO_EXTEND | PC_PLAN_HALF_LDS | PC_PLAN_SMALLEST_FFT)) {
         err = "unknown flag bits";
         return PC_ERR_ARG;
     }
@@ -831,35 +848,71 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         const int64_t need1 = m[1] + K[1] - 1;
         (void)need1;
         int M = 0, ldr = 0;
-        // smallest total work over P0 x P1 pieces (rows x columns) that fit LDS
+        // P0 x P1 pieces (rows x columns) and FFT lengths that fit LDS.
+        // Default: the least estimated time, in vector instructions per
+        // piece - the row FFTs of the gathered and written rows (with the
+        // real-row post-processing), the column FFTs both ways and the
+        // spectral product, at lengths up to 35 % above the needed ones
+        // (a longer length with cheaper radices can win), plus the staged
+        // output box (written and read back once: about as long as 45
+        // instructions per element at the measured rates).  With
+        // PC_PLAN_SMALLEST_FFT: the smallest supported lengths and the least
+        // n log n over the pieces.
+        const bool smallest = (a.flags & PC_PLAN_SMALLEST_FFT) != 0;
+        constexpr double kStageCost = 45.0;
         int best_P0 = -1, best_P1 = -1, best_n0 = 0, best_M = 0;
         double best_cost = 1e300;
         const int maxP0 = (int)std::min<int64_t>(m[0], 64), maxP1 = (int)std::min<int64_t>(m[1], 64);
         for (int P1 = 1; P1 <= maxP1; ++P1) {
             const int64_t h1 = (m[1] + P1 - 1) / P1;
-            const int Mp = next_fft_size((int)((h1 + K[1] - 1 + 1) / 2));
-            if (Mp < 0 || Mp > 128) continue;
-            int ap, bp;
-            fft_factor(Mp, &ap, &bp);
-            if (bp > 10) continue;
-            int ld_p = Mp + 1;
-            if (ld_p % 2 == 0) ++ld_p;
-            for (int P0 = 1; P0 <= maxP0; ++P0) {
-                const int64_t h0 = (m[0] + P0 - 1) / P0;
-                const int n0p = (d == 1) ? 1 : next_fft_size((int)(h0 + K[0] - 1));
-                if (n0p < 0) continue;
-                if (((int64_t)n0p * ld_p + n0p + 3 * Mp) * (int64_t)csz > lds_cap) continue;   // box + twiddles
-                const double nn = (double)n0p * 2.0 * Mp;
-                const double cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
-                if (cost < best_cost) {
-                    best_cost = cost;
-                    best_P0 = P0;
-                    best_P1 = P1;
-                    best_n0 = n0p;
-                    best_M = Mp;
+            const int need_m = (int)((h1 + K[1] - 1 + 1) / 2);
+            const int Mlo = next_fft_size(need_m);
+            if (Mlo < 0 || Mlo > 128) continue;
+            const int Mhi = smallest ? Mlo : std::min(128, (int)std::ceil(need_m * 1.35));
+            bool fit_any = false;
+            for (int Mp = Mlo; Mp <= Mhi; ++Mp) {
+                int ap, bp;
+                if (!fft_factor(Mp, &ap, &bp) || bp > 10) continue;
+                int ld_p = Mp + 1;
+                if (ld_p % 2 == 0) ++ld_p;
+                for (int P0 = 1; P0 <= maxP0; ++P0) {
+                    const int64_t h0 = (m[0] + P0 - 1) / P0;
+                    const int need0 = (int)(h0 + K[0] - 1);
+                    const int nlo = (d == 1) ? 1 : next_fft_size(need0);
+                    if (nlo < 0) continue;
+                    const int nhi = (d == 1 || smallest) ? nlo : std::min(256, (int)std::ceil(need0 * 1.35));
+                    bool fit = false;
+                    for (int n0p = nlo; n0p <= nhi; ++n0p) {
+                        int a0p, b0p;
+                        if (d != 1 && !fft_factor(n0p, &a0p, &b0p)) continue;
+                        if (((int64_t)n0p * ld_p + n0p + 3 * Mp) * (int64_t)csz > lds_cap) continue;   // box + twiddles
+                        fit = true;
+                        double cost;
+                        if (smallest) {
+                            const double nn = (double)n0p * 2.0 * Mp;
+                            cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
+                        } else {
+                            const double rows = (double)(h0 + std::min<int64_t>(n0p, h0 + K[0] - 1)) * Mp *
+                                                (fft_point_cost(Mp) + 11.0);
+                            const double cols = (d == 1) ? 0.0 : (double)(Mp + 1) * n0p * (2.0 * fft_point_cost(n0p) + 6.0);
+                            const double stage = kStageCost * (double)(h0 + K[0] - 1) * (double)(h1 + K[1] - 1);
+                            cost = (double)P0 * P1 * (rows + cols + stage);
+                        }
+                        if (cost < best_cost) {
+                            best_cost = cost;
+                            best_P0 = P0;
+                            best_P1 = P1;
+                            best_n0 = n0p;
+                            best_M = Mp;
+                        }
+                    }
+                    if (fit) {
+                        fit_any = true;
+                        break;   // more row pieces only add work once the box fits
+                    }
                 }
-                break;   // more row pieces only add work once the box fits
             }
+            (void)fit_any;
         }
         if (best_P0 < 0) {
             po.err = "patch " + std::to_string(k) + " does not fit the LDS-resident FFT";

@@ -118,6 +118,45 @@ def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=T
     return res
 
 
+def autotune_plan(make_op, U, OUT, plan_flags=(0, None), adjoint=False, reps=3, allow_overlap=True):
+    """Plan-level choices, made at pc_create: make_op(flags) builds the
+    operator with the given plan flags.  For each candidate (0: the cost
+    model's FFT lengths; PC_PLAN_SMALLEST_FFT: the smallest supported
+    lengths) the schedule autotuner runs and the best time is kept.  The
+    plans differ in FFT lengths, so their results agree to rounding (each is
+    checked against the other within 1e-5 relative L2 per vector), not
+    bitwise.  Returns (op, {"plan_flags": f, "plans": [...], **autotune result})
+    with the fastest operator kept and the others closed."""
+    cands = [0, _lib.PC_PLAN_SMALLEST_FFT] if plan_flags == (0, None) else list(plan_flags)
+    best = None
+    plans = []
+    ref = None
+    for f in cands:
+        op = make_op(f)
+        res = autotune(op, U, OUT, adjoint=adjoint, reps=reps, allow_overlap=allow_overlap)
+        torch.cuda.synchronize()
+        out = OUT.double()
+        if ref is None:
+            ref = out.clone()
+        else:
+            rel = ((out - ref).norm(dim=-1) / ref.norm(dim=-1).clamp_min(1e-300)).max().item()
+            if rel > 1e-5:
+                raise RuntimeError(f"plan flags {f} changed the result by {rel:.3e}")
+        st = op.stats()
+        plans.append({"plan_flags": int(f), "items": int(st["n_items"]), "fft_points": int(st["sum_fft_points"]),
+                      "best_ms": res["best_ms"]})
+        if best is None or res["best_ms"] < best[1]["best_ms"]:
+            if best is not None:
+                best[0].close()
+            best = (op, dict(res, plan_flags=int(f)))
+        else:
+            op.close()
+    op, res = best
+    _apply_settings(op, {int(k): v for k, v in res["best"].items()})
+    res["plans"] = plans
+    return op, res
+
+
 def names(setting):
     """Readable form of a setting: {"direct": .., "chunk": .., "overlap": .., "scratch_MiB": ..}."""
     s = {int(k): v for k, v in setting.items()}

@@ -47,8 +47,8 @@ def test_small_cases_parity(lib, idx):
     name, w = small_cases()[idx]
     rng = np.random.default_rng(200 + idx)
     U = rng.standard_normal((5, w.N))
-    for flags in (0, lib.PC_NO_EXTEND):
-        ora = OracleOperator.from_workload(w, extend=(flags == 0))
+    for flags in (0, lib.PC_NO_EXTEND, lib.PC_PLAN_SMALLEST_FFT):
+        ora = OracleOperator.from_workload(w, extend=((flags & lib.PC_NO_EXTEND) == 0))
         for dtype in (lib.PC_F64, lib.PC_F32):
             _note(f"case={name} flags={flags} dtype={dtype}")
             tdt, ndt = _dt(dtype)
@@ -350,8 +350,8 @@ def test_small_cases_3d_parity(lib, idx):
     name, w = small_cases_3d()[idx]
     rng = np.random.default_rng(300 + idx)
     U = rng.standard_normal((3, w.N))
-    for flags in (0, lib.PC_NO_EXTEND):
-        ora = OracleOperator.from_workload(w, extend=(flags == 0))
+    for flags in (0, lib.PC_NO_EXTEND, lib.PC_PLAN_SMALLEST_FFT):
+        ora = OracleOperator.from_workload(w, extend=((flags & lib.PC_NO_EXTEND) == 0))
         for dtype in (lib.PC_F64, lib.PC_F32):
             _note(f"case={name} flags={flags} dtype={dtype}")
             tdt, ndt = _dt(dtype)

@@ -127,8 +127,8 @@ def test_emulated_kernels_match_oracle(idx):
     lib = _emu_lib()
     rng = np.random.default_rng(100 + idx)
     U = rng.standard_normal((3, w.N))
-    for flags in (0, 1):
-        op = OracleOperator.from_workload(w, extend=(flags == 0))
+    for flags in (0, 1, 4):     # default, PC_NO_EXTEND, PC_PLAN_SMALLEST_FFT
+        op = OracleOperator.from_workload(w, extend=((flags & 1) == 0))
         for dtype in (1, 0):
             Ur = U.astype(np.float32).astype(np.float64) if dtype == 0 else U
             for adj in (False, True):
