@@ -216,8 +216,9 @@ def main():
     # not divide ends with a shorter launch, so the bytes are averaged over
     # the launches of one apply (as the launch time is)
     traffic = None
-    direct = schedule.get("chosen", {}).get("direct", 0) if schedule["autotuned"] else 0
-    if not three_d and not f64 and not direct:
+    chosen = schedule.get("chosen", {}) if schedule["autotuned"] else {}
+    direct, persistent = chosen.get("direct", 0), chosen.get("persistent", 0)
+    if not three_d and not f64 and not direct and not persistent:
         per_vec = st["slot_elems_fwd"] * esz
         cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's 2 GiB staging cap
         chunk = schedule.get("chosen", {}).get("chunk", 0) if schedule["autotuned"] else 0

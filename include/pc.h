@@ -344,9 +344,17 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
  *                   (staging, scratch, estimator and block buffers; 0 = no
  *                   cap): a call that would grow them beyond it returns
  *                   PC_ERR_BUDGET before anything is enqueued
+ *  PC_TUNE_PERSISTENT  staged 1-D/2-D applies (pc_apply_batch and the
+ *                   adjoint): 1 runs each vector chunk's convolution as a
+ *                   fixed grid of workgroups that take (item, vector) units
+ *                   from per-XCD queues in device memory (cleared by a
+ *                   kernel before each launch) instead of one workgroup per
+ *                   unit; 0 (default) launches one workgroup per unit.
+ *                   Ignored where the item data leaves no room in LDS for
+ *                   the queue slot, and by the other entry points.
  * Results are bitwise identical for every setting. */
 enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4, PC_TUNE_DIRECT = 5,
-       PC_TUNE_STREAMS = 6 };
+       PC_TUNE_STREAMS = 6, PC_TUNE_PERSISTENT = 7 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 /* pc_device_bytes -- device bytes the operator holds now: its resident data

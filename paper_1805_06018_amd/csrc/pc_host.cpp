@@ -57,6 +57,7 @@ struct pc_op {
     bool tune_overlap = false;    // reduce on the aux stream while the next chunk convolves
     bool tune_direct = false;     // d <= 2: colour launches add into the outputs (no staging)
     int tune_streams = 4;         // colour launches: vector chunks run on this many streams at once
+    bool tune_persistent = false; // staged 1-D/2-D applies: persistent convolution launches
     hipStream_t lanes[kMaxLanes] = {};       // the library's streams of the colour launches
     hipEvent_t lane_done[kMaxLanes] = {};    // end of each lane's work in the current call
     hipEvent_t fork = nullptr;               // start of the current call on the caller's stream
@@ -517,7 +518,10 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
         } else {
             if (injected_failure(op)) return injected();
             prof_begin(op, s, &ev);
-            e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s);
+            if (op->tune_persistent && pc::persistent_fits(op->dev))
+                e = pc::launch_conv_persistent(op->dev, adj, nb, in, ldu, slots, per, s);
+            else
+                e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
             prof_end(op, s, ev, 0, nb);
         }
@@ -606,10 +610,17 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
         delete op;
         return st;
     }
-    void *d_leaf, *d_items3;
-    if ((st = upload(op, P.leaf_box, &d_leaf, s)) != PC_OK || (st = upload(op, P.items3, &d_items3, s)) != PC_OK) {
+    void *d_leaf, *d_items3, *d_queue;
+    if ((st = upload(op, P.leaf_box, &d_leaf, s)) != PC_OK || (st = upload(op, P.items3, &d_items3, s)) != PC_OK ||
+        (st = upload(op, std::vector<int32_t>(128, 0), &d_queue, s)) != PC_OK) {
         delete op;
         return st;
+    }
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, op->device);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_fail(e, "hipDeviceGetAttribute");
     }
     void* d_ord[2] = {d_items, d_items};
     for (int dir = 0; dir < 2 && !P.items.empty(); ++dir) {
@@ -648,6 +659,8 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
     D.conv_threads = P.conv_threads;
     D.max_lds_axis = P.max_lds_axis;
     D.dtype = (int)dtype;
+    D.queue = static_cast<int*>(d_queue);
+    D.n_cu = n_cu;
     op->leaf_box = static_cast<int32_t*>(d_leaf);
     op->d_wts = d_wts;
     e = hipStreamSynchronize(s);
@@ -1065,6 +1078,9 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
         case PC_TUNE_STREAMS:
             if (value < 1 || value > kMaxLanes) return fail(PC_ERR_ARG, "streams out of range (1..4)");
             op->tune_streams = (int)value;
+            return PC_OK;
+        case PC_TUNE_PERSISTENT:
+            op->tune_persistent = value != 0;
             return PC_OK;
         case PC_TUNE_BUDGET:
             if (value < 0) return fail(PC_ERR_ARG, "budget out of range");

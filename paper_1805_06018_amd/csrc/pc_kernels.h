@@ -28,6 +28,8 @@ struct DevPlan {
     int conv_threads;               // 1-D/2-D convolution workgroup size (1024 or 512)
     int max_lds_axis;               // 3-D axis-0 kernel
     int dtype;                      // 0 = f32, 1 = f64
+    int* queue;                     // persistent launches: 8 XCD counters, 16 ints apart
+    int n_cu;                       // compute units of the device
 };
 
 // One 3-D launch set (plane-forward, axis-0, plane-inverse) over items
@@ -53,6 +55,14 @@ struct Conv3Launch {
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
                        hipStream_t s);
+
+// Staged launch of all items in persistent form (fixed grid, per-XCD unit
+// queues at P.queue, cleared on s first): the same staging boxes as
+// launch_conv with out null.  persistent_fits: whether the item data leaves
+// room in LDS for the queue slot (else launch_conv_persistent refuses).
+bool persistent_fits(const DevPlan& P);
+hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
+                                  int64_t slot_stride, hipStream_t s);
 
 // out[b * ld + i] = 0 for b < B, i < N.
 hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, hipStream_t s);

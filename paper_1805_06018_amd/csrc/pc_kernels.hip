@@ -1,4 +1,5 @@
 // HIP kernels of the product-convolution apply for gfx950.
+#include <algorithm>
 #include <mutex>
 
 #include "pc_kernels.h"
@@ -61,6 +62,35 @@ struct ConvArgs {
     int64_t pitch;
 };
 
+// One (item, vector) unit of the convolution, phases A0 to H.  With
+// load_tw false the item's twiddle tables are already in LDS (the previous
+// unit of a persistent workgroup was the same item).
+template <class T, int NT, bool ADD>
+__device__ __forceinline__ void conv_unit(const ConvArgs<T>& A, cx<T>* buf, int item, int rhs, bool load_tw, int tid) {
+    const Item it = A.items[A.item_lo + item];
+    T* const slot_vec = A.slots + (ADD ? 0 : (int64_t)rhs * A.slot_stride);
+    Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, slot_vec, A.wts, A.spec, A.tw, A.pitch,
+                           ADD ? A.out + (int64_t)rhs * A.ldo : nullptr);
+    twiddles_to_lds(c, buf + (int64_t)it.n0 * it.ld, tid, NT, load_tw);
+    phA0(c, buf, tid, NT);
+    __syncthreads();
+    phA(c, buf, tid, NT);
+    __syncthreads();
+    phB(c, buf, tid, NT);
+    __syncthreads();
+    phC(c, buf, tid, NT);
+    __syncthreads();
+    phD(c, buf, tid, NT);
+    __syncthreads();
+    phE(c, buf, tid, NT);
+    __syncthreads();
+    phF(c, buf, tid, NT);
+    __syncthreads();
+    phG(c, buf, tid, NT);
+    __syncthreads();
+    phH<4, ADD ? kOutAdd : kOutStage>(c, buf, tid, NT);
+}
+
 // One workgroup per (item, vector).  Blocks are dealt round-robin to the 8
 // XCDs (block id mod 8).  Staged launches (all items at once) give every
 // XCD whole items with all their vectors in sequence, so a patch's spectrum
@@ -83,29 +113,41 @@ __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
         rhs = l % A.B;
     }
     if (item >= A.n_items) return;
-    const Item it = A.items[A.item_lo + item];
-    T* const slot_vec = A.slots + (ADD ? 0 : (int64_t)rhs * A.slot_stride);
-    Ctx<T> c = make_ctx<T>(it, A.adj != 0, A.in + (int64_t)rhs * A.ld_in, slot_vec, A.wts, A.spec, A.tw, A.pitch,
-                           ADD ? A.out + (int64_t)rhs * A.ldo : nullptr);
-    const int tid = threadIdx.x;
-    twiddles_to_lds(c, buf + (int64_t)it.n0 * it.ld, tid, NT);
-    phA0(c, buf, tid, NT);
-    __syncthreads();
-    phA(c, buf, tid, NT);
-    __syncthreads();
-    phB(c, buf, tid, NT);
-    __syncthreads();
-    phC(c, buf, tid, NT);
-    __syncthreads();
-    phD(c, buf, tid, NT);
-    __syncthreads();
-    phE(c, buf, tid, NT);
-    __syncthreads();
-    phF(c, buf, tid, NT);
-    __syncthreads();
-    phG(c, buf, tid, NT);
-    __syncthreads();
-    phH<4, ADD ? kOutAdd : kOutStage>(c, buf, tid, NT);
+    conv_unit<T, NT, ADD>(A, buf, item, rhs, true, threadIdx.x);
+}
+
+// Persistent form of the staged launch: a fixed grid of workgroups (one per
+// CU), each taking units from the queue of its XCD (block id mod 8).  Unit l
+// of XCD x is item x + 8 (l / B) with vector l mod B: the same units on the
+// same XCD as the block-per-unit launch, handed out as workgroups free up,
+// and a workgroup whose next unit is the same item keeps the item's twiddle
+// tables in LDS.  queue[16 x] counts the units handed out on XCD x (cleared
+// before the launch); the int at byte q_off of LDS (behind the item data)
+// passes a unit index to the workgroup.  Every workgroup leaves once its
+// XCD's queue is empty.
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void conv_persistent_kernel(ConvArgs<T> A, int* queue, int q_off) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    int* const next = reinterpret_cast<int*>(smem + q_off);
+    const int xcd = blockIdx.x & 7;
+    int prev = -1;
+    for (;;) {
+        // the barrier also ends the previous unit's LDS reads (phase H)
+        // before the next unit writes the box and the twiddle tables
+        if (threadIdx.x == 0) *next = atomicAdd(queue + 16 * xcd, 1);
+        __syncthreads();
+        const int l = *next;
+        const int item = xcd + 8 * (l / A.B);
+        if (item >= A.n_items) return;
+        // the thread index passes through an opaque move on every unit, so
+        // no per-thread offset of the phases is hoisted out of this loop
+        // (kept live across units, they would not fit in registers)
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        conv_unit<T, NT, false>(A, buf, item, l % A.B, item != prev, tid);
+        prev = item;
+    }
 }
 
 // ------------------------------------------------------------------- 3-D
@@ -452,6 +494,56 @@ static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item
     return hipGetLastError();
 }
 
+// LDS of a persistent launch: the item data, then the unit slot (16 B).
+static int persistent_q_off(const DevPlan& P) { return (P.max_lds + 15) & ~15; }
+
+bool persistent_fits(const DevPlan& P) {
+    return P.queue != nullptr && persistent_q_off(P) + 16 <= kLdsBytes && (P.conv_threads == 512 || P.dtype == 0);
+}
+
+template <class T>
+static hipError_t conv_persistent_t(const DevPlan& P, bool adj, int B, const void* in, int64_t ld_in, void* slots,
+                                    int64_t slot_stride, hipStream_t s) {
+    if (!persistent_fits(P)) return hipErrorInvalidValue;
+    if (P.n_items <= 0 || B <= 0) return hipSuccess;
+    ConvArgs<T> A;
+    A.items = P.items;
+    A.item_lo = 0;
+    A.n_items = P.n_items;
+    A.B = B;
+    A.adj = adj ? 1 : 0;
+    A.spec = static_cast<const cx<T>*>(P.spec);
+    A.wts = static_cast<const T*>(P.wts);
+    A.tw = static_cast<const cx<T>*>(P.tw);
+    A.in = static_cast<const T*>(in);
+    A.ld_in = ld_in;
+    A.slots = static_cast<T*>(slots);
+    A.slot_stride = slot_stride;
+    A.out = nullptr;
+    A.ldo = 0;
+    A.pitch = P.cols;
+    const int q_off = persistent_q_off(P), lds = q_off + 16;
+    // workgroups per CU that LDS and the 2048 threads of a CU allow
+    const int per_cu = std::max(1, std::min(kLdsBytes / lds, 2048 / P.conv_threads));
+    const int grid = std::max(8, (P.n_cu * per_cu) / 8 * 8);
+    hipError_t e = launch_fill_zero(0, P.queue, 128, 128, 1, s);   // 128 int counters = zero floats
+    if (e != hipSuccess) return e;
+    if (P.conv_threads == 512)
+        hipLaunchKernelGGL((conv_persistent_kernel<T, 512>), dim3((unsigned)grid), dim3(512), lds, s, A, P.queue, q_off);
+    else if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((conv_persistent_kernel<T, 1024>), dim3((unsigned)grid), dim3(1024), lds, s, A, P.queue,
+                           q_off);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
+                                  int64_t slot_stride, hipStream_t s) {
+    if (P.dtype == 1) return conv_persistent_t<double>(P, adjoint, B, in, ld_in, slots, slot_stride, s);
+    return conv_persistent_t<float>(P, adjoint, B, in, ld_in, slots, slot_stride, s);
+}
+
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
                        hipStream_t s) {
@@ -509,6 +601,9 @@ hipError_t set_kernel_attributes() {
         reinterpret_cast<const void*>(&conv_kernel<float, 1024, true>),
         reinterpret_cast<const void*>(&conv_kernel<float, 512, true>),
         reinterpret_cast<const void*>(&conv_kernel<double, 512, true>),
+        reinterpret_cast<const void*>(&conv_persistent_kernel<float, 1024>),
+        reinterpret_cast<const void*>(&conv_persistent_kernel<float, 512>),
+        reinterpret_cast<const void*>(&conv_persistent_kernel<double, 512>),
         reinterpret_cast<const void*>(&plane_fwd_kernel<float>), reinterpret_cast<const void*>(&plane_fwd_kernel<double>),
         reinterpret_cast<const void*>(&axis_kernel<float>),      reinterpret_cast<const void*>(&axis_kernel<double>),
         reinterpret_cast<const void*>(&plane_inv_kernel<float>), reinterpret_cast<const void*>(&plane_inv_kernel<double>)};

@@ -48,6 +48,20 @@ __host__ __device__ __forceinline__ int imul24(int a, int b) {
 // (x + 1/2) / d stays at least 1/(2d) away from an integer).
 __host__ __device__ inline int fdiv(int x, float inv) { return (int)(((float)x + 0.5f) * inv); }
 
+// w[k1] = tw[j0 k1] for 1 <= k1 < A (the twiddles of one pass-1 task;
+// w[0] = 1 is never read).  All of a task's twiddles are read before any of
+// its results is written back to LDS: the compiler cannot tell the twiddle
+// table from the box, so a read placed after a store would wait for it.
+template <int A, class T>
+__host__ __device__ __forceinline__ void twiddle_run(const cx<T>* tw, int j0, cx<T>* w) {
+    const cx<T>* q = tw;
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+        q += j0;
+        w[k1] = *q;
+    }
+}
+
 template <class T>
 struct Ctx {
     Item it;
@@ -115,9 +129,10 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
 // barrier; the phases then read their twiddles from LDS.
 __host__ __device__ inline int64_t tw_lds_elems(const Item& it) { return (int64_t)it.n0 + 3 * (int64_t)it.m; }
 
+// With copy false the tables are already there (only the pointers are set).
 template <class T>
-__host__ __device__ inline void twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth) {
-    const int n0 = c.it.n0, m = c.it.m, n = n0 + 3 * m;
+__host__ __device__ inline void twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth, bool copy = true) {
+    const int n0 = c.it.n0, m = c.it.m, n = copy ? n0 + 3 * m : 0;
     for (int t = tid; t < n; t += nth) {
         cx<T> v;
         if (t < n0)
@@ -217,13 +232,14 @@ __host__ __device__ inline void phA_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     for (int t = tid; t < ntask; t += nth) {
         const int q = fdiv(t, c.inv_bm), j0 = t - imul24(q, bm);
         cx<T>* p = buf + (imul24(c.s_off0 + q, ld) + j0);
-        cx<T> x[A];
+        cx<T> x[A], w[A];
 #pragma unroll
         for (int j1 = 0; j1 < A; ++j1) x[j1] = p[bm * j1];
+        twiddle_run<A>(c.twm, j0, w);
         Dft<A, -1>::run(x);
-        int e = 0;   // twiddle exponent j0 k1
+        p[0] = x[0];   // twiddle w^0 = 1
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1, e += j0) p[bm * k1] = cmul(x[k1], c.twm[e]);
+        for (int k1 = 1; k1 < A; ++k1) p[bm * k1] = cmul(x[k1], w[k1]);
     }
 }
 template <class T>
@@ -269,19 +285,23 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         const int k1b = (k1 == 0) ? 0 : am - k1;
         cx<T>* pa = p + imul24(Bm, k1);
         cx<T>* pb = p + imul24(Bm, k1b);
-        cx<T> za[Bm], zb[Bm];
+        cx<T> za[Bm], zb[Bm], w[Bm];
 #pragma unroll
         for (int k0 = 0; k0 < Bm; ++k0) za[k0] = pa[k0];
-        Dft<Bm, -1>::run(za);
         if (k1b != k1) {
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
+        }
+        // w[k0] = w_2m^(k1 + am k0): the twiddles of every branch below
+#pragma unroll
+        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = c.tw2m[k1 + am * k0];
+        Dft<Bm, -1>::run(za);
+        if (k1b != k1) {
             Dft<Bm, -1>::run(zb);
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) {
-                const int k = k1 + am * k0;
                 cx<T> Xk, Xm;
-                post_pair(za[k0], zb[Bm - 1 - k0], c.tw2m[k], Xk, Xm);
+                post_pair(za[k0], zb[Bm - 1 - k0], w[k0], Xk, Xm);
                 za[k0] = Xk;
                 zb[Bm - 1 - k0] = Xm;
             }
@@ -292,9 +312,8 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             const cx<T> z0 = za[0];
 #pragma unroll
             for (int k0 = 1; 2 * k0 <= Bm; ++k0) {
-                const int k = am * k0;
                 cx<T> Xk, Xm;
-                post_pair(za[k0], za[Bm - k0], c.tw2m[k], Xk, Xm);
+                post_pair(za[k0], za[Bm - k0], w[k0], Xk, Xm);
                 za[k0] = Xk;
                 if (2 * k0 != Bm) za[Bm - k0] = Xm;
             }
@@ -304,9 +323,8 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             // am even, k1 = am/2: k0 pairs with bm - 1 - k0
 #pragma unroll
             for (int k0 = 0; 2 * k0 < Bm; ++k0) {
-                const int k = k1 + am * k0;
                 cx<T> Xk, Xm;
-                post_pair(za[k0], za[Bm - 1 - k0], c.tw2m[k], Xk, Xm);
+                post_pair(za[k0], za[Bm - 1 - k0], w[k0], Xk, Xm);
                 za[k0] = Xk;
                 if (2 * k0 != Bm - 1) za[Bm - 1 - k0] = Xm;
             }
@@ -329,16 +347,17 @@ __host__ __device__ inline void phC_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         const int j0 = fdiv(t, c.inv_nc), col = t - imul24(j0, NC);
         cx<T>* p = buf + (imul24(j0, ld) + col);
         const int step = b0 * ld;
-        cx<T> x[A0];
+        cx<T> x[A0], w[A0];
 #pragma unroll
         for (int j1 = 0; j1 < A0; ++j1) {
             const int row = b0 * j1 + j0;
             x[j1] = ((unsigned)(row - c.s_off0) < (unsigned)c.s_n0) ? p[j1 * step] : cx<T>{T(0), T(0)};
         }
+        twiddle_run<A0>(c.tw0, j0, w);
         Dft<A0, -1>::run(x);
-        int e = 0;   // twiddle exponent j0 k1
+        p[0] = x[0];
 #pragma unroll
-        for (int k1 = 0; k1 < A0; ++k1, e += j0) p[k1 * step] = cmul(x[k1], c.tw0[e]);
+        for (int k1 = 1; k1 < A0; ++k1) p[k1 * step] = cmul(x[k1], w[k1]);
     }
 }
 template <class T>
@@ -415,10 +434,12 @@ __host__ __device__ inline void phE_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         const int j0 = fdiv(t, c.inv_nc), col = t - imul24(j0, NC);
         cx<T>* p = buf + (imul24(j0, ld) + col);
         const int step = b0 * ld;
-        cx<T> x[A0];
-        int e = 0;   // twiddle exponent j0 k1
+        cx<T> x[A0], w[A0];
 #pragma unroll
-        for (int k1 = 0; k1 < A0; ++k1, e += j0) x[k1] = cmulc(p[k1 * step], c.tw0[e]);
+        for (int k1 = 0; k1 < A0; ++k1) x[k1] = p[k1 * step];
+        twiddle_run<A0>(c.tw0, j0, w);
+#pragma unroll
+        for (int k1 = 1; k1 < A0; ++k1) x[k1] = cmulc(x[k1], w[k1]);
         Dft<A0, 1>::run(x);
 #pragma unroll
         for (int j1 = 0; j1 < A0; ++j1) {
@@ -446,17 +467,21 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         const int k1b = (k1 == 0) ? 0 : am - k1;
         cx<T>* pa = p + imul24(Bm, k1);
         cx<T>* pb = p + imul24(Bm, k1b);
-        cx<T> za[Bm], zb[Bm];
+        cx<T> za[Bm], zb[Bm], w[Bm];
 #pragma unroll
         for (int k0 = 0; k0 < Bm; ++k0) za[k0] = pa[k0];
         if (k1b != k1) {
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
+        }
+        // w[k0] = w_2m^(k1 + am k0): the twiddles of every branch below
+#pragma unroll
+        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = c.tw2m[k1 + am * k0];
+        if (k1b != k1) {
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) {
-                const int k = k1 + am * k0;
                 cx<T> Zk, Zm;
-                pre_pair(za[k0], zb[Bm - 1 - k0], c.tw2m[k], Zk, Zm);
+                pre_pair(za[k0], zb[Bm - 1 - k0], w[k0], Zk, Zm);
                 za[k0] = Zk;
                 zb[Bm - 1 - k0] = Zm;
             }
@@ -467,9 +492,8 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             const cx<T> X0 = za[0], XM = p[M];
 #pragma unroll
             for (int k0 = 1; 2 * k0 <= Bm; ++k0) {
-                const int k = am * k0;
                 cx<T> Zk, Zm;
-                pre_pair(za[k0], za[Bm - k0], c.tw2m[k], Zk, Zm);
+                pre_pair(za[k0], za[Bm - k0], w[k0], Zk, Zm);
                 za[k0] = Zk;
                 if (2 * k0 != Bm) za[Bm - k0] = Zm;
             }
@@ -479,9 +503,8 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         } else {
 #pragma unroll
             for (int k0 = 0; 2 * k0 < Bm; ++k0) {
-                const int k = k1 + am * k0;
                 cx<T> Zk, Zm;
-                pre_pair(za[k0], za[Bm - 1 - k0], c.tw2m[k], Zk, Zm);
+                pre_pair(za[k0], za[Bm - 1 - k0], w[k0], Zk, Zm);
                 za[k0] = Zk;
                 if (2 * k0 != Bm - 1) za[Bm - 1 - k0] = Zm;
             }
@@ -507,10 +530,12 @@ __host__ __device__ inline void phG_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
     for (int t = tid; t < ntask; t += nth) {
         const int q = fdiv(t, c.inv_bm), j0 = t - imul24(q, bm);
         cx<T>* p = buf + (imul24(c.d_off0 + q, ld) + j0);
-        cx<T> x[A];
-        int e = 0;   // twiddle exponent j0 k1
+        cx<T> x[A], w[A];
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1, e += j0) x[k1] = cmulc(p[bm * k1], c.twm[e]);
+        for (int k1 = 0; k1 < A; ++k1) x[k1] = p[bm * k1];
+        twiddle_run<A>(c.twm, j0, w);
+#pragma unroll
+        for (int k1 = 1; k1 < A; ++k1) x[k1] = cmulc(x[k1], w[k1]);
         Dft<A, 1>::run(x);
 #pragma unroll
         for (int j1 = 0; j1 < A; ++j1) p[bm * j1] = x[j1];

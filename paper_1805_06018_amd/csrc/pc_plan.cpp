@@ -49,21 +49,44 @@ int next_fft_size(int need) {
 
 int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
 
-// FP32 vector instructions per complex point of one codelet pass, counted in
-// the compiled codelets (adds, multiplies, fused multiply-adds) for radix
-// 1, 2, ..., 16 (0 where there is no codelet).
-double radix_cost(int r) {
-    static const double c[17] = {0, 0, 2.0, 4.67, 4.0, 7.2, 8.0, 9.43, 6.75, 11.11, 10.8, 0, 10.0, 0, 13.14, 14.0, 9.75};
-    return (r >= 0 && r <= 16) ? c[r] : 1e9;
+// Estimated time of one convolution unit (one piece, one vector) on a CU,
+// in cycles.  Each phase runs its tasks (t = thread, thread + NT, ...) on
+// NT threads; waves go round-robin to the 4 SIMDs, a SIMD issues one wave64
+// VALU instruction per 4 cycles, and a barrier ends every phase, so a phase
+// costs 4 x (waves on the busiest SIMD) x (instructions per task).  The
+// per-task counts are the vector instructions of each phase's task loop in
+// the compiled gfx950 kernel, by radix (0 where the radix does not occur):
+//   kRow: row passes 1 (phases A and G) and column inverse pass 1 (E),
+//   kCol1: column pass 1 (C), kCol2: column pass 2, spectral product and
+//   inverse column pass 2 (D), kPair: row pass 2 with the real-row post- or
+//   pre-processing of two frequency groups (B and F).
+// Gather (A0) and copy-out (H) take 120 and 59 instructions per batch of 8
+// and 4 rows, and the reduction costs about 0.56 CU-cycles per staged
+// element (measured on the 1024^2 blur: 7.9e8 elements in 0.72 ms on 256
+// CUs).
+double simd_rounds(int64_t ntask, int NT) {
+    const int64_t full = ntask / NT, rem = ntask % NT;
+    double r = (double)full * (NT / 256);
+    if (rem) r += std::ceil(std::ceil(rem / 64.0) / 4.0);
+    return r;
 }
 
-// Instructions per complex point of a two-pass length-n transform: both
-// codelets, the twiddle between the passes and the index work of the two
-// LDS sweeps.
-double fft_point_cost(int n) {
-    int a, b;
-    if (!fft_factor(n, &a, &b)) return 1e9;
-    return radix_cost(a) + radix_cost(b) + ((a > 1 && b > 1) ? 6.0 : 0.0) + 4.0;
+double unit_cycles(int NT, int n0, int a0, int b0, int M, int am, int bm, int64_t in0, int64_t out0, int64_t out1) {
+    static const double kRow[17] = {0, 11, 25, 48, 59, 89, 110, 137, 134, 190, 207, 0, 237, 0, 319, 354, 309};
+    static const double kCol1[17] = {0, 11, 34, 55, 67, 97, 119, 147, 145, 201, 219, 0, 251, 0, 335, 371, 327};
+    static const double kCol2[17] = {0, 11, 45, 76, 93, 143, 179, 226, 214, 316, 344, 0, 392, 0, 546, 611, 517};
+    static const double kPair[11] = {0, 56, 95, 144, 179, 248, 302, 368, 375, 496, 542};
+    if (a0 > 16 || b0 > 16 || am > 16 || bm > 10) return 1e30;
+    const int64_t NC = M + 1, H = am / 2 + 1;
+    double c = simd_rounds(in0 * bm, NT) * kRow[am] + simd_rounds(in0 * H, NT) * kPair[bm] +
+               simd_rounds(NC * b0, NT) * kCol1[a0] + simd_rounds(NC * a0, NT) * kCol2[b0] +
+               simd_rounds(NC * b0, NT) * kRow[a0] + simd_rounds(out0 * H, NT) * kPair[bm] +
+               simd_rounds(out0 * bm, NT) * kRow[am];
+    (void)n0;
+    const int64_t rps_in = std::max<int64_t>(1, NT / (2 * M)), rps_out = std::max<int64_t>(1, NT / std::max<int64_t>(out1, 1));
+    c += (NT / 256) * (double)((in0 + 8 * rps_in - 1) / (8 * rps_in)) * 120.0;
+    c += (NT / 256) * (double)((out0 + 4 * rps_out - 1) / (4 * rps_out)) * 59.0;
+    return 4.0 * c + 0.56 * (double)(out0 * out1);
 }
 
 int smallest_7smooth(int64_t need) {
@@ -849,17 +872,16 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         (void)need1;
         int M = 0, ldr = 0;
         // P0 x P1 pieces (rows x columns) and FFT lengths that fit LDS.
-        // Default: the least estimated time, in vector instructions per
-        // piece - the row FFTs of the gathered and written rows (with the
-        // real-row post-processing), the column FFTs both ways and the
-        // spectral product, at lengths up to 35 % above the needed ones
-        // (a longer length with cheaper radices can win), plus the staged
-        // output box (written and read back once: about as long as 45
-        // instructions per element at the measured rates).  With
-        // PC_PLAN_SMALLEST_FFT: the smallest supported lengths and the least
-        // n log n over the pieces.
+        // Default: the least estimated time over the pieces (unit_cycles:
+        // whole SIMD rounds per phase at the measured per-task instruction
+        // counts, the gather and copy-out, and the staged output box read
+        // back by the reduction), at lengths up to 35 % above the needed
+        // ones (a longer length with cheaper radices or fewer rounds can
+        // win) and up to two more row pieces than the fewest that fit.
+        // With PC_PLAN_SMALLEST_FFT: the smallest supported lengths, the
+        // fewest row pieces that fit and the least n log n over the pieces.
         const bool smallest = (a.flags & PC_PLAN_SMALLEST_FFT) != 0;
-        constexpr double kStageCost = 45.0;
+        const int NT = p.conv_threads;
         int best_P0 = -1, best_P1 = -1, best_n0 = 0, best_M = 0;
         double best_cost = 1e300;
         const int maxP0 = (int)std::min<int64_t>(m[0], 64), maxP1 = (int)std::min<int64_t>(m[1], 64);
@@ -875,7 +897,9 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                 if (!fft_factor(Mp, &ap, &bp) || bp > 10) continue;
                 int ld_p = Mp + 1;
                 if (ld_p % 2 == 0) ++ld_p;
+                int first_fit = -1;
                 for (int P0 = 1; P0 <= maxP0; ++P0) {
+                    if (first_fit > 0 && (smallest || P0 > first_fit + 2)) break;
                     const int64_t h0 = (m[0] + P0 - 1) / P0;
                     const int need0 = (int)(h0 + K[0] - 1);
                     const int nlo = (d == 1) ? 1 : next_fft_size(need0);
@@ -883,7 +907,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                     const int nhi = (d == 1 || smallest) ? nlo : std::min(256, (int)std::ceil(need0 * 1.35));
                     bool fit = false;
                     for (int n0p = nlo; n0p <= nhi; ++n0p) {
-                        int a0p, b0p;
+                        int a0p = 1, b0p = 1;
                         if (d != 1 && !fft_factor(n0p, &a0p, &b0p)) continue;
                         if (((int64_t)n0p * ld_p + n0p + 3 * Mp) * (int64_t)csz > lds_cap) continue;   // box + twiddles
                         fit = true;
@@ -892,11 +916,9 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                             const double nn = (double)n0p * 2.0 * Mp;
                             cost = (double)P0 * P1 * nn * std::log2(std::max(nn, 2.0));
                         } else {
-                            const double rows = (double)(h0 + std::min<int64_t>(n0p, h0 + K[0] - 1)) * Mp *
-                                                (fft_point_cost(Mp) + 11.0);
-                            const double cols = (d == 1) ? 0.0 : (double)(Mp + 1) * n0p * (2.0 * fft_point_cost(n0p) + 6.0);
-                            const double stage = kStageCost * (double)(h0 + K[0] - 1) * (double)(h1 + K[1] - 1);
-                            cost = (double)P0 * P1 * (rows + cols + stage);
+                            const int64_t out0 = std::min<int64_t>(n0p, h0 + K[0] - 1);
+                            cost = (double)P0 * P1 *
+                                   unit_cycles(NT, n0p, a0p, b0p, Mp, ap, bp, h0, out0, std::min<int64_t>(2 * Mp, h1 + K[1] - 1));
                         }
                         if (cost < best_cost) {
                             best_cost = cost;
@@ -908,7 +930,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                     }
                     if (fit) {
                         fit_any = true;
-                        break;   // more row pieces only add work once the box fits
+                        if (first_fit < 0) first_fit = P0;
                     }
                 }
             }

@@ -113,6 +113,18 @@ def test_batch_column_equals_single_apply_and_plain(lib):
         assert torch.equal(Ob[:, :w.N], out[:3]) and torch.all(Ob[:, w.N:] == 7.0)
     op.set_tuning(lib.PC_TUNE_DIRECT, 0)
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
+    # persistent convolution launches (units from per-XCD queues): the same bits
+    op.set_tuning(lib.PC_TUNE_PERSISTENT, 1)
+    for chunk in (0, 3):
+        op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
+        got = torch.full_like(U, float("nan"))
+        op.apply_batch(U, got)
+        gota = torch.full_like(U, float("nan"))
+        op.apply_adjoint_batch(U, gota)
+        torch.cuda.synchronize()
+        assert torch.equal(got, out) and torch.equal(gota, adj_ref), chunk
+    op.set_tuning(lib.PC_TUNE_PERSISTENT, 0)
+    op.set_tuning(lib.PC_TUNE_CHUNK, 0)
 
 
 FULL_VECTORS = tuple(range(0, 64, 9))   # 8 of the 64 vectors: 0, 9, ..., 63
@@ -135,7 +147,12 @@ def test_full_size_blur1024_batch64(lib, adjoint):
     Ud = torch.from_numpy(U).cuda()
     out = torch.zeros_like(Ud)
     (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, out)
+    # the persistent form of the launch gives the same bits
+    op.set_tuning(lib.PC_TUNE_PERSISTENT, 1)
+    again = torch.full_like(Ud, float("nan"))
+    (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, again)
     torch.cuda.synchronize()
+    assert torch.equal(again, out)
     got = out.cpu().numpy()
     assert np.all(np.isfinite(got))
     ora = OracleOperator.from_workload(w)

@@ -356,11 +356,12 @@ def test_emulated_kernels_under_address_sanitizer():
 def test_autotune_candidates():
     """The autotuner's candidate schedules: the library default first, no
     duplicates, 3-D candidates vary chunk and scratch, 2-D colour launches
-    against staging, chunk and overlap."""
+    against staging, persistent launches, chunk and overlap."""
     import types
     from paper_1805_06018_amd import _lib, tune
     defaults = {_lib.PC_TUNE_DIRECT: 0, _lib.PC_TUNE_STREAMS: 4}
-    for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP, _lib.PC_TUNE_DIRECT, _lib.PC_TUNE_STREAMS}),
+    for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP, _lib.PC_TUNE_DIRECT, _lib.PC_TUNE_STREAMS,
+                         _lib.PC_TUNE_PERSISTENT}),
                     (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
         c = tune.candidates(types.SimpleNamespace(d=d), 16)
         assert all(v == defaults.get(k, 0) for k, v in c[0].items())
