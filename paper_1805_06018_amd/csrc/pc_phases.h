@@ -48,18 +48,17 @@ __host__ __device__ __forceinline__ int imul24(int a, int b) {
 // (x + 1/2) / d stays at least 1/(2d) away from an integer).
 __host__ __device__ inline int fdiv(int x, float inv) { return (int)(((float)x + 0.5f) * inv); }
 
-// w[k1] = tw[j0 k1] for 1 <= k1 < A (the twiddles of one pass-1 task;
-// w[0] = 1 is never read).  All of a task's twiddles are read before any of
-// its results is written back to LDS: the compiler cannot tell the twiddle
+// w[k1] = w_n^(j0 k1) for 1 <= k1 < A: the twiddles of pass-1 task j0,
+// stored as one run per task (entry j0 (A - 1) + k1 - 1 of the table), so
+// one multiply finds the run and the reads take immediate offsets; w[0] = 1
+// is never read.  All of a task's twiddles are read before any of its
+// results is written back to LDS: the compiler cannot tell the twiddle
 // table from the box, so a read placed after a store would wait for it.
 template <int A, class T>
 __host__ __device__ __forceinline__ void twiddle_run(const cx<T>* tw, int j0, cx<T>* w) {
-    const cx<T>* q = tw;
+    const cx<T>* q = tw + imul24(j0, A - 1) - 1;
 #pragma unroll
-    for (int k1 = 1; k1 < A; ++k1) {
-        q += j0;
-        w[k1] = *q;
-    }
+    for (int k1 = 1; k1 < A; ++k1) w[k1] = q[k1];
 }
 
 template <class T>
@@ -77,9 +76,9 @@ struct Ctx {
     const T* w;                       // weight table of the item's input box
     const cx<T>* spec;
     int spec_ld;                      // spectrum row stride (m + 1 for 2-D items)
-    const cx<T>* tw0;                 // w_{n0}^e
-    const cx<T>* twm;                 // w_m^e
-    const cx<T>* tw2m;                // w_{2m}^e
+    const cx<T>* tw0;                 // column pass-1 twiddles (runs per task, see twiddle_run)
+    const cx<T>* twm;                 // row pass-1 twiddles (the same layout)
+    const cx<T>* tw2m;                // w_2m^(k1 + am k0) at k1 bm + k0 (post-/pre-processing)
     int64_t pitch;                    // Omega row pitch (elements)
 };
 
@@ -124,28 +123,32 @@ __host__ __device__ inline Ctx<T> make_ctx(const Item& it, bool adj, const T* in
     return c;
 }
 
-// The item's twiddle tables (w_{n0}, w_m, w_{2m}: n0 + 3m complex) are
-// copied into LDS right after the FFT box, cooperatively and before the first
-// barrier; the phases then read their twiddles from LDS.
-__host__ __device__ inline int64_t tw_lds_elems(const Item& it) { return (int64_t)it.n0 + 3 * (int64_t)it.m; }
+// The item's twiddle tables (column pass 1: b0 (a0 - 1), row pass 1:
+// bm (am - 1), pairs: (am / 2 + 1) bm complex) are copied into LDS right
+// after the FFT box, cooperatively and before the first barrier; the phases
+// then read their twiddles from LDS.
+__host__ __device__ inline int64_t tw_lds_elems(const Item& it) {
+    return (int64_t)it.b0 * (it.a0 - 1) + (int64_t)it.bm * (it.am - 1) + (int64_t)(it.am / 2 + 1) * it.bm;
+}
 
 // With copy false the tables are already there (only the pointers are set).
 template <class T>
 __host__ __device__ inline void twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth, bool copy = true) {
-    const int n0 = c.it.n0, m = c.it.m, n = copy ? n0 + 3 * m : 0;
+    const int l0 = c.it.b0 * (c.it.a0 - 1), lm = c.it.bm * (c.it.am - 1);
+    const int n = copy ? (int)tw_lds_elems(c.it) : 0;
     for (int t = tid; t < n; t += nth) {
         cx<T> v;
-        if (t < n0)
+        if (t < l0)
             v = c.tw0[t];
-        else if (t < n0 + m)
-            v = c.twm[t - n0];
+        else if (t < l0 + lm)
+            v = c.twm[t - l0];
         else
-            v = c.tw2m[t - n0 - m];
+            v = c.tw2m[t - l0 - lm];
         dst[t] = v;
     }
     c.tw0 = dst;
-    c.twm = dst + n0;
-    c.tw2m = dst + n0 + m;
+    c.twm = dst + l0;
+    c.tw2m = dst + l0 + lm;
 }
 
 #define PC_RADIX_SWITCH(R, FN, ...)               \
@@ -200,26 +203,34 @@ __host__ __device__ inline void phA0(const Ctx<T>& c, cx<T>* buf, int tid, int n
     const int e = col - c.s_off1;        // column inside the gathered box
     const bool live = (unsigned)e < (unsigned)c.s_n1;
     const bool wgt = live && !c.adj;
-    T* rows = reinterpret_cast<T*>(buf) + c.s_off0 * (2 * c.it.ld) + col;
-    const int rstride = 2 * c.it.ld;
-    const T* src = c.src + (int64_t)(c.it.g0 + c.s_off0) * c.pitch + c.it.g1 + col;
-    const T* w = c.w + e;
+    const int rstride = 2 * c.it.ld, rstep = rps * rstride;
+    T* rows = reinterpret_cast<T*>(buf) + (c.s_off0 + r0) * rstride + col;
+    // Global addresses: a workgroup-uniform base plus a 32-bit byte offset
+    // per lane, which the loads take as scalar base + vector offset (the
+    // rows of a box are fewer than 256 and pc_create limits every extent of
+    // Omega to 2^20, so the offsets stay below 2^31); a batch's rows are a
+    // uniform stride apart.
+    const char* sbase = reinterpret_cast<const char*>(c.src + (int64_t)(c.it.g0 + c.s_off0) * c.pitch + c.it.g1);
+    const char* wbase = reinterpret_cast<const char*>(c.w);
+    uint32_t soff = (uint32_t)(r0 * c.pitch + col) * (uint32_t)sizeof(T);
+    uint32_t woff = (uint32_t)(r0 * c.it.w_ld + e) * (uint32_t)sizeof(T);
+    const uint32_t sstep = (uint32_t)(rps * c.pitch) * (uint32_t)sizeof(T);
+    const uint32_t wstep = (uint32_t)(rps * c.it.w_ld) * (uint32_t)sizeof(T);
     // predicated batches: every row of a batch is loaded before any is used
     for (int q = r0; q < c.s_n0; q += U * rps) {
         T v[U], f[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = q + u * rps;
-            v[u] = (live && r < c.s_n0) ? src[(int64_t)r * c.pitch] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = q + u * rps;
-            f[u] = (wgt && r < c.s_n0) ? w[(int64_t)r * c.it.w_ld] : T(1);
-        }
+        for (int u = 0; u < U; ++u)
+            v[u] = (live && q + u * rps < c.s_n0) ? *reinterpret_cast<const T*>(sbase + (soff + u * sstep)) : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (q + u * rps < c.s_n0) rows[(q + u * rps) * rstride] = v[u] * f[u];
+            f[u] = (wgt && q + u * rps < c.s_n0) ? *reinterpret_cast<const T*>(wbase + (woff + u * wstep)) : T(1);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (q + u * rps < c.s_n0) rows[u * rstep] = v[u] * f[u];
+        soff += U * sstep;
+        woff += U * wstep;
+        rows += U * rstep;
     }
 }
 
@@ -293,8 +304,9 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
         }
         // w[k0] = w_2m^(k1 + am k0): the twiddles of every branch below
+        const cx<T>* tq = c.tw2m + imul24(k1, Bm);
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = c.tw2m[k1 + am * k0];
+        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = tq[k0];
         Dft<Bm, -1>::run(za);
         if (k1b != k1) {
             Dft<Bm, -1>::run(zb);
@@ -475,8 +487,9 @@ __host__ __device__ inline void phF_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
             for (int k0 = 0; k0 < Bm; ++k0) zb[k0] = pb[k0];
         }
         // w[k0] = w_2m^(k1 + am k0): the twiddles of every branch below
+        const cx<T>* tq = c.tw2m + imul24(k1, Bm);
 #pragma unroll
-        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = c.tw2m[k1 + am * k0];
+        for (int k0 = 0; k0 < Bm; ++k0) w[k0] = tq[k0];
         if (k1b != k1) {
 #pragma unroll
             for (int k0 = 0; k0 < Bm; ++k0) {
@@ -583,16 +596,26 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     const int rps = nth / n1;            // rows per sweep (n1 <= 256 <= nth)
     const int r0 = tid / n1, e = tid - r0 * n1;
     if (r0 >= rps) return;
-    const T* rows = reinterpret_cast<const T*>(buf) + c.d_off0 * (2 * c.it.ld) + c.d_off1 + e;
-    const int rstride = 2 * c.it.ld;
-    const T* w = c.w + e;
-    T* dst = c.dst + e;
-    const int64_t rs = c.dst_rs;
+    // the thread's first row; consecutive rows of a batch are a uniform
+    // stride apart, so every address is one add from these pointers
+    const int rstride = 2 * c.it.ld, rstep = rps * rstride;
+    const T* rows = reinterpret_cast<const T*>(buf) + (c.d_off0 + r0) * rstride + c.d_off1 + e;
+    // global addresses: uniform bases plus 32-bit byte offsets per lane, as
+    // in the gather (the staging box or the output rows of the box)
+    char* dbase = reinterpret_cast<char*>(c.dst);
+    const char* wbase = reinterpret_cast<const char*>(c.w);
+    uint32_t doff = (uint32_t)(r0 * c.dst_rs + e) * (uint32_t)sizeof(T);
+    uint32_t woff = (uint32_t)(r0 * c.it.w_ld + e) * (uint32_t)sizeof(T);
+    const uint32_t dstep = (uint32_t)(rps * c.dst_rs) * (uint32_t)sizeof(T);
+    const uint32_t wstep = (uint32_t)(rps * c.it.w_ld) * (uint32_t)sizeof(T);
     if (OUT == kOutAdd || (OUT == kOutEither && c.add)) {
         // one atomic add per element; nothing returns, so no batching
         for (int r = r0; r < c.d_n0; r += rps) {
-            const T p = rows[r * rstride] * (c.adj ? w[(int64_t)r * c.it.w_ld] : T(1));
-            add_to(&dst[(int64_t)r * rs], p);
+            const T p = rows[0] * (c.adj ? *reinterpret_cast<const T*>(wbase + woff) : T(1));
+            add_to(reinterpret_cast<T*>(dbase + doff), p);
+            rows += rstep;
+            woff += wstep;
+            doff += dstep;
         }
         return;
     }
@@ -600,18 +623,17 @@ __host__ __device__ inline void phH(const Ctx<T>& c, cx<T>* buf, int tid, int nt
     for (int q = r0; q < c.d_n0; q += U * rps) {
         T v[U], f[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = q + u * rps;
-            v[u] = r < c.d_n0 ? rows[r * rstride] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = q + u * rps;
-            f[u] = (c.adj && r < c.d_n0) ? w[(int64_t)r * c.it.w_ld] : T(1);
-        }
+        for (int u = 0; u < U; ++u) v[u] = q + u * rps < c.d_n0 ? rows[u * rstep] : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (q + u * rps < c.d_n0) __builtin_nontemporal_store(v[u] * f[u], &dst[(int64_t)(q + u * rps) * rs]);
+            f[u] = (c.adj && q + u * rps < c.d_n0) ? *reinterpret_cast<const T*>(wbase + (woff + u * wstep)) : T(1);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (q + u * rps < c.d_n0)
+                __builtin_nontemporal_store(v[u] * f[u], reinterpret_cast<T*>(dbase + (doff + u * dstep)));
+        rows += U * rstep;
+        woff += U * wstep;
+        doff += U * dstep;
     }
 }
 

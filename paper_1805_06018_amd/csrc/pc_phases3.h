@@ -215,10 +215,11 @@ __host__ __device__ inline void axis_store(const Ctx<T>& c, const cx<T>* buf, cx
     }
 }
 
-// Axis-0 twiddles (w_nz, nz complex) copied into LDS after the block's box.
+// Axis-0 pass-1 twiddles (bz (az - 1) complex, runs per task) copied into
+// LDS after the block's box.
 template <class T>
 __host__ __device__ inline void axis_twiddles_to_lds(Ctx<T>& c, cx<T>* dst, int tid, int nth) {
-    const int n = c.it.n0;
+    const int n = c.it.b0 * (c.it.a0 - 1);
     for (int t = tid; t < n; t += nth) dst[t] = c.tw0[t];
     c.tw0 = dst;
     c.twm = dst;

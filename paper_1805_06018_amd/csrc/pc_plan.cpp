@@ -49,6 +49,42 @@ int next_fft_size(int need) {
 
 int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
 
+int TwiddleTables::pass(int a, int b) {
+    const auto key = std::make_pair(a, b);
+    auto f = pass_off.find(key);
+    if (f != pass_off.end()) return f->second;
+    const int off = (int)(tw->size() / 2);
+    pass_off[key] = off;
+    const int n = a * b;
+    for (int j0 = 0; j0 < b; ++j0)
+        for (int k1 = 1; k1 < a; ++k1) {
+            const double ang = 2.0 * kPi * (double)((int64_t)j0 * k1 % n) / (double)n;
+            tw->push_back(std::cos(ang));
+            tw->push_back(-std::sin(ang));
+        }
+    return off;
+}
+
+int TwiddleTables::pair(int am, int bm) {
+    const auto key = std::make_pair(am, bm);
+    auto f = pair_off.find(key);
+    if (f != pair_off.end()) return f->second;
+    const int off = (int)(tw->size() / 2);
+    pair_off[key] = off;
+    const int n2 = 2 * am * bm;
+    for (int k1 = 0; k1 <= am / 2; ++k1)
+        for (int k0 = 0; k0 < bm; ++k0) {
+            const double ang = 2.0 * kPi * (double)(k1 + am * k0) / (double)n2;
+            tw->push_back(std::cos(ang));
+            tw->push_back(-std::sin(ang));
+        }
+    return off;
+}
+
+int64_t twiddle_elems(int a0, int b0, int am, int bm) {
+    return (int64_t)b0 * (a0 - 1) + (int64_t)bm * (am - 1) + (int64_t)(am / 2 + 1) * bm;
+}
+
 // Estimated time of one convolution unit (one piece, one vector) on a CU,
 // in cycles.  Each phase runs its tasks (t = thread, thread + NT, ...) on
 // NT threads; waves go round-robin to the 4 SIMDs, a SIMD issues one wave64
@@ -56,11 +92,11 @@ int perm_slot(int k, int a, int b) { return b * (k % a) + k / a; }
 // costs 4 x (waves on the busiest SIMD) x (instructions per task).  The
 // per-task counts are the vector instructions of each phase's task loop in
 // the compiled gfx950 kernel, by radix (0 where the radix does not occur):
-//   kRow: row passes 1 (phases A and G) and column inverse pass 1 (E),
-//   kCol1: column pass 1 (C), kCol2: column pass 2, spectral product and
+//   kRow: row pass 1 (phases A and G), kCol1: column pass 1 (C), kColInv:
+//   inverse column pass 1 (E), kCol2: column pass 2, spectral product and
 //   inverse column pass 2 (D), kPair: row pass 2 with the real-row post- or
 //   pre-processing of two frequency groups (B and F).
-// Gather (A0) and copy-out (H) take 120 and 59 instructions per batch of 8
+// Gather (A0) and copy-out (H) take 94 and 43 instructions per batch of 8
 // and 4 rows, and the reduction costs about 0.56 CU-cycles per staged
 // element (measured on the 1024^2 blur: 7.9e8 elements in 0.72 ms on 256
 // CUs).
@@ -72,20 +108,21 @@ double simd_rounds(int64_t ntask, int NT) {
 }
 
 double unit_cycles(int NT, int n0, int a0, int b0, int M, int am, int bm, int64_t in0, int64_t out0, int64_t out1) {
-    static const double kRow[17] = {0, 11, 25, 48, 59, 89, 110, 137, 134, 190, 207, 0, 237, 0, 319, 354, 309};
-    static const double kCol1[17] = {0, 11, 34, 55, 67, 97, 119, 147, 145, 201, 219, 0, 251, 0, 335, 371, 327};
+    static const double kRow[17] = {0, 11, 28, 43, 50, 75, 92, 115, 108, 159, 172, 0, 194, 0, 268, 299, 250};
+    static const double kCol1[17] = {0, 11, 35, 55, 65, 95, 115, 142, 139, 195, 212, 0, 242, 0, 324, 359, 314};
+    static const double kColInv[17] = {0, 11, 29, 48, 56, 86, 104, 130, 126, 182, 196, 0, 224, 0, 304, 338, 292};
     static const double kCol2[17] = {0, 11, 45, 76, 93, 143, 179, 226, 214, 316, 344, 0, 392, 0, 546, 611, 517};
-    static const double kPair[11] = {0, 56, 95, 144, 179, 248, 302, 368, 375, 496, 542};
+    static const double kPair[11] = {0, 55, 94, 140, 176, 242, 295, 360, 368, 486, 531};
     if (a0 > 16 || b0 > 16 || am > 16 || bm > 10) return 1e30;
     const int64_t NC = M + 1, H = am / 2 + 1;
     double c = simd_rounds(in0 * bm, NT) * kRow[am] + simd_rounds(in0 * H, NT) * kPair[bm] +
                simd_rounds(NC * b0, NT) * kCol1[a0] + simd_rounds(NC * a0, NT) * kCol2[b0] +
-               simd_rounds(NC * b0, NT) * kRow[a0] + simd_rounds(out0 * H, NT) * kPair[bm] +
+               simd_rounds(NC * b0, NT) * kColInv[a0] + simd_rounds(out0 * H, NT) * kPair[bm] +
                simd_rounds(out0 * bm, NT) * kRow[am];
     (void)n0;
     const int64_t rps_in = std::max<int64_t>(1, NT / (2 * M)), rps_out = std::max<int64_t>(1, NT / std::max<int64_t>(out1, 1));
-    c += (NT / 256) * (double)((in0 + 8 * rps_in - 1) / (8 * rps_in)) * 120.0;
-    c += (NT / 256) * (double)((out0 + 4 * rps_out - 1) / (4 * rps_out)) * 59.0;
+    c += (NT / 256) * (double)((in0 + 8 * rps_in - 1) / (8 * rps_in)) * 94.0;
+    c += (NT / 256) * (double)((out0 + 4 * rps_out - 1) / (4 * rps_out)) * 43.0;
     return 4.0 * c + 0.56 * (double)(out0 * out1);
 }
 
@@ -751,18 +788,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
     const bool half = (a.flags & PC_PLAN_HALF_LDS) != 0;
     const int64_t lds_cap = half ? kLdsBytes / 2 : kLdsBytes;
     p.conv_threads = (half || a.dtype == PC_F64) ? 512 : 1024;
-    std::map<int, int> tw_off;   // length -> complex offset
-    auto want_tw = [&](int len) {
-        if (tw_off.count(len)) return tw_off[len];
-        int off = (int)(p.tw.size() / 2);
-        tw_off[len] = off;
-        for (int e = 0; e < len; ++e) {
-            double ang = 2.0 * kPi * (double)e / (double)len;
-            p.tw.push_back(std::cos(ang));
-            p.tw.push_back(-std::sin(ang));
-        }
-        return off;
-    };
+    TwiddleTables twt{&p.tw, {}, {}};
     p.items.clear();
     p.spec.clear();
     struct PatchOut {
@@ -909,7 +935,8 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                     for (int n0p = nlo; n0p <= nhi; ++n0p) {
                         int a0p = 1, b0p = 1;
                         if (d != 1 && !fft_factor(n0p, &a0p, &b0p)) continue;
-                        if (((int64_t)n0p * ld_p + n0p + 3 * Mp) * (int64_t)csz > lds_cap) continue;   // box + twiddles
+                        if (((int64_t)n0p * ld_p + twiddle_elems(a0p, b0p, ap, bp)) * (int64_t)csz > lds_cap)
+                            continue;   // box + twiddles
                         fit = true;
                         double cost;
                         if (smallest) {
@@ -1022,7 +1049,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
         const int64_t spec_off = spec_total;
         po.spec_off = spec_off;
         spec_total += (int64_t)po.n0 * (po.M + 1);
-        const int t0 = want_tw(po.n0), tm = want_tw(po.M), t2m = want_tw(2 * po.M);
+        const int t0 = twt.pass(po.a0, po.b0), tm = twt.pass(po.am, po.bm), t2m = twt.pair(po.am, po.bm);
         int ldr = po.M + 1;
         if (ldr % 2 == 0) ++ldr;
         for (Item it : po.items) {
@@ -1035,7 +1062,7 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             p.slot_fwd += (int64_t)it.out_n0 * it.out_n1;
             p.slot_adj += (int64_t)it.in_n0 * it.in_n1;
             p.sum_fft_points += (int64_t)po.n0 * 2 * po.M;
-            p.max_lds = std::max(p.max_lds, (int)(((int64_t)po.n0 * ldr + po.n0 + 3 * po.M) * csz));
+            p.max_lds = std::max(p.max_lds, (int)(((int64_t)po.n0 * ldr + twiddle_elems(po.a0, po.b0, po.am, po.bm)) * csz));
             p.items.push_back(it);
         }
     }

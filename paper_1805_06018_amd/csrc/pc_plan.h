@@ -4,6 +4,8 @@
 // runtime calls) so the same planner serves the library and its CPU
 // emulation build.
 #pragma once
+#include <map>
+#include <utility>
 #include <stdint.h>
 #include <complex>
 #include <string>
@@ -80,6 +82,25 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err);
 // FFT lengths usable by the kernels: n = a * b with a, b radices.
 bool fft_factor(int n, int* a, int* b);
 int next_fft_size(int need);
+
+// Twiddle tables in the layout the kernels read (interleaved complex FP64,
+// appended to tw; the returned value is the table's complex offset).
+// TwiddleTables keeps one table per (kind, a, b):
+//   pass(a, b): the inter-pass twiddles of a length n = a b transform, one
+//     run per pass-1 task: entry j0 (a - 1) + k1 - 1 = w_n^(j0 k1) for
+//     j0 < b, 1 <= k1 < a (b (a - 1) entries);
+//   pair(am, bm): the real-row post-/pre-processing twiddles of m = am bm,
+//     one run per frequency group: entry k1 bm + k0 = w_2m^(k1 + am k0) for
+//     k1 <= am / 2, k0 < bm.
+// with w_n = exp(-2 pi i / n).
+struct TwiddleTables {
+    std::vector<double>* tw;
+    std::map<std::pair<int, int>, int> pass_off, pair_off;
+    int pass(int a, int b);
+    int pair(int am, int bm);
+};
+// Complex elements of an item's three tables (column pass, row pass, pairs).
+int64_t twiddle_elems(int a0, int b0, int am, int bm);
 
 // ---- planner internals shared by the 2-D and 3-D planners
 using cd = std::complex<double>;

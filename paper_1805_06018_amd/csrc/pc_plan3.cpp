@@ -430,19 +430,7 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         g.flops = 5.0 * nn * std::log2((double)nn) + 3.0 * nn + (double)I + (double)O;
     }
     // ----------------------------------- offsets (patch order) and tables
-    std::map<int, int> tw_off;
-    auto want_tw = [&](int len) {
-        auto f = tw_off.find(len);
-        if (f != tw_off.end()) return f->second;
-        int off = (int)(p.tw.size() / 2);
-        tw_off[len] = off;
-        for (int e = 0; e < len; ++e) {
-            double ang = 2.0 * kPi * (double)e / (double)len;
-            p.tw.push_back(std::cos(ang));
-            p.tw.push_back(-std::sin(ang));
-        }
-        return off;
-    };
+    TwiddleTables twt{&p.tw, {}, {}};
     int64_t spec_total = 0;
     for (int64_t k = 0; k < r; ++k) {
         Geo3& g = geo[(size_t)k];
@@ -453,10 +441,10 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
         if (!p.sel[(size_t)k]) continue;
         Item3& it = g.it;
         Item& q = it.p;
-        q.tw0 = want_tw(q.n0);
-        q.twm = want_tw(q.m);
-        q.tw2m = want_tw(2 * q.m);
-        it.twz = want_tw(it.nz);
+        q.tw0 = twt.pass(q.a0, q.b0);
+        q.twm = twt.pass(q.am, q.bm);
+        q.tw2m = twt.pair(q.am, q.bm);
+        it.twz = twt.pass(it.az, it.bz);
         const int64_t plane = (int64_t)q.n0 * (q.m + 1);
         q.spec_off = spec_total;
         spec_total += (int64_t)it.nz * plane;
