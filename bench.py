@@ -218,7 +218,7 @@ def main():
     traffic = None
     chosen = schedule.get("chosen", {}) if schedule["autotuned"] else {}
     direct, persistent = chosen.get("direct", 0), chosen.get("persistent", 0)
-    if not three_d and not f64 and not direct and not persistent:
+    if not three_d and not f64 and not direct and not persistent and not chosen.get("item_major", 0):
         per_vec = st["slot_elems_fwd"] * esz
         cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's 2 GiB staging cap
         chunk = schedule.get("chosen", {}).get("chunk", 0) if schedule["autotuned"] else 0

@@ -352,9 +352,14 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
  *                   unit; 0 (default) launches one workgroup per unit.
  *                   Ignored where the item data leaves no room in LDS for
  *                   the queue slot, and by the other entry points.
+ *  PC_TUNE_XCD_ORDER  staged 1-D/2-D applies, one workgroup per unit: 0
+ *                   (default) gives each of the 8 XCDs whole items with all
+ *                   their vectors (a patch's spectrum stays in one XCD's
+ *                   L2); 1 deals the workgroups item-major, so the vectors
+ *                   of one item run on all XCDs at once.
  * Results are bitwise identical for every setting. */
 enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4, PC_TUNE_DIRECT = 5,
-       PC_TUNE_STREAMS = 6, PC_TUNE_PERSISTENT = 7 };
+       PC_TUNE_STREAMS = 6, PC_TUNE_PERSISTENT = 7, PC_TUNE_XCD_ORDER = 8 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 /* pc_device_bytes -- device bytes the operator holds now: its resident data

@@ -58,6 +58,7 @@ struct pc_op {
     bool tune_direct = false;     // d <= 2: colour launches add into the outputs (no staging)
     int tune_streams = 4;         // colour launches: vector chunks run on this many streams at once
     bool tune_persistent = false; // staged 1-D/2-D applies: persistent convolution launches
+    bool tune_item_major = false; // staged 1-D/2-D applies: item-major block order over the XCDs
     hipStream_t lanes[kMaxLanes] = {};       // the library's streams of the colour launches
     hipEvent_t lane_done[kMaxLanes] = {};    // end of each lane's work in the current call
     hipEvent_t fork = nullptr;               // start of the current call on the caller's stream
@@ -521,7 +522,8 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
             if (op->tune_persistent && pc::persistent_fits(op->dev))
                 e = pc::launch_conv_persistent(op->dev, adj, nb, in, ldu, slots, per, s);
             else
-                e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s);
+                e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s,
+                                    op->tune_item_major);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
             prof_end(op, s, ev, 0, nb);
         }
@@ -1081,6 +1083,9 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
             return PC_OK;
         case PC_TUNE_PERSISTENT:
             op->tune_persistent = value != 0;
+            return PC_OK;
+        case PC_TUNE_XCD_ORDER:
+            op->tune_item_major = value != 0;
             return PC_OK;
         case PC_TUNE_BUDGET:
             if (value < 0) return fail(PC_ERR_ARG, "budget out of range");

@@ -52,9 +52,11 @@ struct Conv3Launch {
 // B vectors starting at 'in'.  With out null the written boxes go to
 // staging; otherwise they are added into the B outputs at out (stride ldo),
 // which is only race-free and deterministic for items of one colour.
+// item_major: staged launches deal the blocks item-major over the XCDs
+// instead of whole items per XCD (the same results).
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                       hipStream_t s);
+                       hipStream_t s, bool item_major = false);
 
 // Staged launch of all items in persistent form (fixed grid, per-XCD unit
 // queues at P.queue, cleared on s first): the same staging boxes as

@@ -60,6 +60,7 @@ struct ConvArgs {
     T* out;                 // non-null: add the written boxes into out (items of one colour)
     int64_t ldo;
     int64_t pitch;
+    int item_major;         // staged launches: 1 = item-major block order (see conv_kernel)
 };
 
 // One (item, vector) unit of the convolution, phases A0 to H.  With
@@ -97,14 +98,16 @@ __device__ __forceinline__ void conv_unit(const ConvArgs<T>& A, cx<T>* buf, int 
 // is fetched into one XCD's L2 and reused there by every vector.  A colour
 // launch holds a few dozen items of uneven size, and whole items per XCD
 // would leave the XCD with the largest ones working alone at the end, so
-// there the blocks of one item run through all XCDs (item-major order).
+// there the blocks of one item run through all XCDs (item-major order);
+// staged launches take that order too when A.item_major is set (a tuning
+// choice).
 template <class T, int NT, bool ADD>
 __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
     const int bid = blockIdx.x;
     int item, rhs;
-    if (ADD) {
+    if (ADD || A.item_major) {
         item = bid / A.B;
         rhs = bid - item * A.B;
     } else {
@@ -456,7 +459,7 @@ hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, 
 template <class T>
 static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item_lo, int item_hi, int B,
                          const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                         hipStream_t s) {
+                         hipStream_t s, bool item_major) {
     ConvArgs<T> A;
     A.items = items;
     A.item_lo = item_lo;
@@ -473,8 +476,9 @@ static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item
     A.out = static_cast<T*>(out);
     A.ldo = ldo;
     A.pitch = P.cols;
+    A.item_major = item_major ? 1 : 0;
     if (A.n_items <= 0 || B <= 0) return hipSuccess;
-    const int64_t nblk = out ? (int64_t)A.n_items * B : 8 * ((int64_t)((A.n_items + 7) / 8) * B);
+    const int64_t nblk = (out || item_major) ? (int64_t)A.n_items * B : 8 * ((int64_t)((A.n_items + 7) / 8) * B);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
     if (P.conv_threads == 512) {
         if (out)
@@ -522,6 +526,7 @@ static hipError_t conv_persistent_t(const DevPlan& P, bool adj, int B, const voi
     A.out = nullptr;
     A.ldo = 0;
     A.pitch = P.cols;
+    A.item_major = 0;
     const int q_off = persistent_q_off(P), lds = q_off + 16;
     // workgroups per CU that LDS and the 2048 threads of a CU allow
     const int per_cu = std::max(1, std::min(kLdsBytes / lds, 2048 / P.conv_threads));
@@ -546,10 +551,12 @@ hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const v
 
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                       hipStream_t s) {
+                       hipStream_t s, bool item_major) {
     if (P.dtype == 1)
-        return conv_t<double>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s);
-    return conv_t<float>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s);
+        return conv_t<double>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s,
+                              item_major);
+    return conv_t<float>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s,
+                         item_major);
 }
 
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride, void* out,

@@ -113,17 +113,19 @@ def test_batch_column_equals_single_apply_and_plain(lib):
         assert torch.equal(Ob[:, :w.N], out[:3]) and torch.all(Ob[:, w.N:] == 7.0)
     op.set_tuning(lib.PC_TUNE_DIRECT, 0)
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
-    # persistent convolution launches (units from per-XCD queues): the same bits
-    op.set_tuning(lib.PC_TUNE_PERSISTENT, 1)
-    for chunk in (0, 3):
-        op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
-        got = torch.full_like(U, float("nan"))
-        op.apply_batch(U, got)
-        gota = torch.full_like(U, float("nan"))
-        op.apply_adjoint_batch(U, gota)
-        torch.cuda.synchronize()
-        assert torch.equal(got, out) and torch.equal(gota, adj_ref), chunk
-    op.set_tuning(lib.PC_TUNE_PERSISTENT, 0)
+    # persistent convolution launches (units from per-XCD queues) and the
+    # item-major block order: the same bits
+    for key in (lib.PC_TUNE_PERSISTENT, lib.PC_TUNE_XCD_ORDER):
+        op.set_tuning(key, 1)
+        for chunk in (0, 3):
+            op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
+            got = torch.full_like(U, float("nan"))
+            op.apply_batch(U, got)
+            gota = torch.full_like(U, float("nan"))
+            op.apply_adjoint_batch(U, gota)
+            torch.cuda.synchronize()
+            assert torch.equal(got, out) and torch.equal(gota, adj_ref), (key, chunk)
+        op.set_tuning(key, 0)
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
 
 

@@ -361,7 +361,7 @@ def test_autotune_candidates():
     from paper_1805_06018_amd import _lib, tune
     defaults = {_lib.PC_TUNE_DIRECT: 0, _lib.PC_TUNE_STREAMS: 4}
     for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP, _lib.PC_TUNE_DIRECT, _lib.PC_TUNE_STREAMS,
-                         _lib.PC_TUNE_PERSISTENT}),
+                         _lib.PC_TUNE_PERSISTENT, _lib.PC_TUNE_XCD_ORDER}),
                     (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
         c = tune.candidates(types.SimpleNamespace(d=d), 16)
         assert all(v == defaults.get(k, 0) for k, v in c[0].items())
