@@ -259,22 +259,24 @@ __host__ __device__ inline void phA(const Ctx<T>& c, cx<T>* buf, int tid, int nt
 }
 
 // Real-row post-processing of one frequency pair: from Z[k], Z[m-k] of
-// Z = DFT_m(x_even + i x_odd) to X[k] and X[m-k] of X = DFT_2m(x).
+// Z = DFT_m(x_even + i x_odd) to 2 X[k] and 2 X[m-k] of X = DFT_2m(x).
+// The factor 1/2 of the even/odd split is left out here and in pre_pair
+// (so every row spectrum is 2 X and every pre-processed row 2 Z); the
+// spectra carry the product 1/4 instead.  Scaling by powers of two is
+// exact, so the results are bit for bit those of the halved formulas.
 template <class T>
 __host__ __device__ inline void post_pair(cx<T> Zk, cx<T> Zm, cx<T> w, cx<T>& Xk, cx<T>& Xm) {
-    const T h = T(0.5);
-    const cx<T> E = {(Zk.x + Zm.x) * h, (Zk.y - Zm.y) * h};
-    const cx<T> O = {(Zk.y + Zm.y) * h, (Zm.x - Zk.x) * h};
+    const cx<T> E = {Zk.x + Zm.x, Zk.y - Zm.y};
+    const cx<T> O = {Zk.y + Zm.y, Zm.x - Zk.x};
     const cx<T> wO = cmul(w, O);
     Xk = E + wO;
     Xm = conj(E - wO);
 }
-// Inverse: from X[k], X[m-k] back to Z[k], Z[m-k].
+// Inverse: from X[k], X[m-k] back to 2 Z[k], 2 Z[m-k].
 template <class T>
 __host__ __device__ inline void pre_pair(cx<T> Xk, cx<T> Xm, cx<T> w, cx<T>& Zk, cx<T>& Zm) {
-    const T h = T(0.5);
-    const cx<T> E = {(Xk.x + Xm.x) * h, (Xk.y - Xm.y) * h};
-    const cx<T> D = {(Xk.x - Xm.x) * h, (Xk.y + Xm.y) * h};
+    const cx<T> E = {Xk.x + Xm.x, Xk.y - Xm.y};
+    const cx<T> D = {Xk.x - Xm.x, Xk.y + Xm.y};
     const cx<T> O = cmulc(D, w);
     Zk = {E.x - O.y, E.y + O.x};
     Zm = {E.x + O.y, O.x - E.y};
@@ -329,8 +331,8 @@ __host__ __device__ inline void phB_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
                 za[k0] = Xk;
                 if (2 * k0 != Bm) za[Bm - k0] = Xm;
             }
-            za[0] = {z0.x + z0.y, T(0)};
-            p[M] = {z0.x - z0.y, T(0)};
+            za[0] = {(z0.x + z0.y) * T(2), T(0)};   // 2 X[0] and 2 X[m], as post_pair
+            p[M] = {(z0.x - z0.y) * T(2), T(0)};
         } else {
             // am even, k1 = am/2: k0 pairs with bm - 1 - k0
 #pragma unroll
@@ -390,11 +392,14 @@ __host__ __device__ inline void phD_r(const Ctx<T>& c, cx<T>* buf, int tid, int 
         cx<T>* p = buf + (imul24(k1, B0 * ld) + col);
         cx<T> x[B0];
         if (MODE == 0) {
-            const int sld = c.spec_ld;
-            const unsigned so = (unsigned)(imul24(k1, B0 * sld) + col);
+            // spectrum: a uniform base plus a 32-bit byte offset per lane
+            // (a scalar-base load); rows k0 a uniform stride apart
+            const uint32_t sstride = (uint32_t)c.spec_ld * (uint32_t)sizeof(cx<T>);
+            const uint32_t so = (uint32_t)(imul24(k1, B0 * c.spec_ld) + col) * (uint32_t)sizeof(cx<T>);
+            const char* sb = reinterpret_cast<const char*>(c.spec);
             cx<T> s[B0];
 #pragma unroll
-            for (int k0 = 0; k0 < B0; ++k0) s[k0] = c.spec[so + (unsigned)(k0 * sld)];
+            for (int k0 = 0; k0 < B0; ++k0) s[k0] = *reinterpret_cast<const cx<T>*>(sb + (so + k0 * sstride));
 #pragma unroll
             for (int k0 = 0; k0 < B0; ++k0) x[k0] = p[k0 * ld];
             Dft<B0, -1>::run(x);

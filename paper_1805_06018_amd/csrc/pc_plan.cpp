@@ -111,8 +111,8 @@ double unit_cycles(int NT, int n0, int a0, int b0, int M, int am, int bm, int64_
     static const double kRow[17] = {0, 11, 28, 43, 50, 75, 92, 115, 108, 159, 172, 0, 194, 0, 268, 299, 250};
     static const double kCol1[17] = {0, 11, 35, 55, 65, 95, 115, 142, 139, 195, 212, 0, 242, 0, 324, 359, 314};
     static const double kColInv[17] = {0, 11, 29, 48, 56, 86, 104, 130, 126, 182, 196, 0, 224, 0, 304, 338, 292};
-    static const double kCol2[17] = {0, 11, 45, 76, 93, 143, 179, 226, 214, 316, 344, 0, 392, 0, 546, 611, 517};
-    static const double kPair[11] = {0, 55, 94, 140, 176, 242, 295, 360, 368, 486, 531};
+    static const double kCol2[17] = {0, 11, 44, 73, 88, 137, 171, 217, 204, 305, 331, 0, 375, 0, 523, 585, 488};
+    static const double kPair[11] = {0, 50, 85, 127, 159, 221, 270, 331, 335, 449, 490};
     if (a0 > 16 || b0 > 16 || am > 16 || bm > 10) return 1e30;
     const int64_t NC = M + 1, H = am / 2 + 1;
     double c = simd_rounds(in0 * bm, NT) * kRow[am] + simd_rounds(in0 * H, NT) * kPair[bm] +
@@ -1116,7 +1116,10 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
             F1.run(&G[(size_t)i0 * n1], 1, rowout.data());
             for (int kk = 0; kk <= M; ++kk) H[(size_t)i0 * (M + 1) + kk] = rowout[kk];
         }
-        const double sc = 1.0 / ((double)n0 * (double)M);
+        // 1/(n0 M) normalises the inverse transforms; the extra 1/4 stands
+        // for the factors 1/2 that the kernels' real-row post- and
+        // pre-processing leave out
+        const double sc = 0.25 / ((double)n0 * (double)M);
         double* out = &p.spec[(size_t)(2 * po.spec_off)];
         for (int kk = 0; kk <= M; ++kk) {
             for (int i0 = 0; i0 < n0; ++i0) colin[i0] = H[(size_t)i0 * (M + 1) + kk];

@@ -547,7 +547,9 @@ pc_status build_plan_3d(const CreateArgs& a, Plan& p, std::string& err) {
                 F1.run(buf_in.data(), 1, buf_out.data());
                 for (int k1 = 0; k1 < n1; ++k1) H[(size_t)((i0 * n1 + k1) * NC + kk)] = buf_out[k1];
             }
-        const double sc = 1.0 / ((double)nz * (double)n1 * (double)M);
+        // normalisation of the inverse transforms, and 1/4 for the factors
+        // 1/2 that the real-row post- and pre-processing leave out
+        const double sc = 0.25 / ((double)nz * (double)n1 * (double)M);
         double* out = &p.spec[(size_t)(2 * it.p.spec_off)];
         for (int k1 = 0; k1 < n1; ++k1)
             for (int kk = 0; kk < NC; ++kk) {
