@@ -27,7 +27,9 @@ PEAK_FP64_VALU = 78.6e12       # MI355X FP64 vector FLOP/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E B/s
 
 # HBM bytes per convolution launch from the committed counter runs (FETCH_SIZE
-# x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy), one line per launch
+# x 2.0 + WRITE_SIZE x 1.0, calibrated on a plain copy), one line per plan,
+# launch form (split: the large items' launch and the small items' two-per-CU
+# launch of one vector chunk; single: one launch for all items) and launch
 # size; valid only while the kernel and planner sources hash to the recorded
 # value.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_kernel_blur1024_b64.md")
@@ -35,7 +37,7 @@ TRAFFIC_SOURCES = ["paper_1805_06018_amd/csrc/" + f
                    for f in ("pc_kernels.hip", "pc_phases.h", "pc_fft.h", "pc_internal.h", "pc_plan.cpp")]
 
 
-def measured_traffic(vectors_per_launch, plan_flags=0):
+def measured_traffic(vectors_per_launch, plan_flags=0, launch="split"):
     import hashlib
     import re
     try:
@@ -46,10 +48,11 @@ def measured_traffic(vectors_per_launch, plan_flags=0):
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    for m in re.finditer(r"traffic plan_flags=(\d+) vectors_per_launch=(\d+) bytes_per_launch=([0-9.eE+]+) "
+    for m in re.finditer(r"traffic plan_flags=(\d+) launch=(\w+) vectors_per_launch=(\d+) bytes_per_launch=([0-9.eE+]+) "
                          r"sources_sha256=([0-9a-f]{64})", text):
-        if (int(m.group(1)), int(m.group(2))) == (plan_flags, vectors_per_launch) and m.group(4) == h.hexdigest():
-            return float(m.group(3))
+        if ((int(m.group(1)), m.group(2), int(m.group(3))) == (plan_flags, launch, vectors_per_launch)
+                and m.group(5) == h.hexdigest()):
+            return float(m.group(4))
     return None
 
 
@@ -225,7 +228,8 @@ def main():
         chunk = min(cap, chunk if chunk > 0 else B)
         sizes = [chunk] * (B // chunk) + ([B % chunk] if B % chunk else [])
         if len(sizes) == prof["conv_launches"] / args.steps:
-            per = [measured_traffic(v, plan_flags) for v in sizes]
+            launch = "split" if chosen.get("split", 1) else "single"
+            per = [measured_traffic(v, plan_flags, launch) for v in sizes]
             if all(x is not None for x in per):
                 traffic = sum(per) / len(per)
 

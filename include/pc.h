@@ -357,9 +357,14 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
  *                   their vectors (a patch's spectrum stays in one XCD's
  *                   L2); 1 deals the workgroups item-major, so the vectors
  *                   of one item run on all XCDs at once.
+ *  PC_TUNE_SPLIT    staged FP32 applies, one workgroup per unit, whole items
+ *                   per XCD: 1 (default) runs the items whose FFT box and
+ *                   twiddles take at most 79 KiB of LDS as a second launch
+ *                   of 512-thread workgroups, two per CU, after the others;
+ *                   0 runs all items as 1024-thread workgroups, one per CU.
  * Results are bitwise identical for every setting. */
 enum { PC_TUNE_CHUNK = 1, PC_TUNE_OVERLAP = 2, PC_TUNE_SCRATCH = 3, PC_TUNE_BUDGET = 4, PC_TUNE_DIRECT = 5,
-       PC_TUNE_STREAMS = 6, PC_TUNE_PERSISTENT = 7, PC_TUNE_XCD_ORDER = 8 };
+       PC_TUNE_STREAMS = 6, PC_TUNE_PERSISTENT = 7, PC_TUNE_XCD_ORDER = 8, PC_TUNE_SPLIT = 9 };
 pc_status   pc_set_tuning(pc_op* op, int key, int64_t value);
 pc_status   pc_read_profile(pc_op* op, pc_profile* out);
 /* pc_device_bytes -- device bytes the operator holds now: its resident data

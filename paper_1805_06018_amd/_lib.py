@@ -76,7 +76,7 @@ _lib.pc_set_profiling.restype = ctypes.c_int
 _lib.pc_set_tuning.argtypes = [_P, ctypes.c_int, _I64]
 _lib.pc_set_tuning.restype = ctypes.c_int
 (PC_TUNE_CHUNK, PC_TUNE_OVERLAP, PC_TUNE_SCRATCH, PC_TUNE_BUDGET, PC_TUNE_DIRECT, PC_TUNE_STREAMS,
- PC_TUNE_PERSISTENT, PC_TUNE_XCD_ORDER) = 1, 2, 3, 4, 5, 6, 7, 8
+ PC_TUNE_PERSISTENT, PC_TUNE_XCD_ORDER, PC_TUNE_SPLIT) = 1, 2, 3, 4, 5, 6, 7, 8, 9
 _lib.pc_read_profile.argtypes = [_P, ctypes.POINTER(PcProfile)]
 _lib.pc_read_profile.restype = ctypes.c_int
 _lib.pc_device_bytes.argtypes = [_P]

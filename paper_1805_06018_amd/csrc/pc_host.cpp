@@ -59,6 +59,7 @@ struct pc_op {
     int tune_streams = 4;         // colour launches: vector chunks run on this many streams at once
     bool tune_persistent = false; // staged 1-D/2-D applies: persistent convolution launches
     bool tune_item_major = false; // staged 1-D/2-D applies: item-major block order over the XCDs
+    bool tune_split = true;       // staged FP32 applies: small items two workgroups per CU
     hipStream_t lanes[kMaxLanes] = {};       // the library's streams of the colour launches
     hipEvent_t lane_done[kMaxLanes] = {};    // end of each lane's work in the current call
     hipEvent_t fork = nullptr;               // start of the current call on the caller's stream
@@ -457,6 +458,11 @@ pc_status run_direct(pc_op* op, bool adj, int64_t B, const void* U, int64_t ldu,
     return mark_used(op, s);
 }
 
+// The staged FP32 launch runs in two parts (see DevPlan::items_split).
+bool uses_split(const pc_op* op) {
+    return op->dev.n_small > 0 && op->dev.dtype == 0 && op->dev.conv_threads == 1024;
+}
+
 bool uses_direct(const pc_op* op) { return op->tune_direct && op->plan.d <= 2 && !op->plan.cbeg_fwd.empty(); }
 
 pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, int64_t ldu, void* OUT, int64_t ldo,
@@ -521,6 +527,8 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
             prof_begin(op, s, &ev);
             if (op->tune_persistent && pc::persistent_fits(op->dev))
                 e = pc::launch_conv_persistent(op->dev, adj, nb, in, ldu, slots, per, s);
+            else if (op->tune_split && !op->tune_item_major && uses_split(op))
+                e = pc::launch_conv_split(op->dev, adj, nb, in, ldu, slots, per, s);
             else
                 e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s,
                                     op->tune_item_major);
@@ -635,7 +643,37 @@ pc_status create_impl(int d, const int64_t* shape, int64_t n_leaves, const int64
             return st;
         }
     }
+    // the items again, those above kSmallItemLds first (they run as 1024-
+    // thread workgroups), then the others (two 512-thread workgroups per CU)
+    void* d_split = d_items;
+    int n_big = 0, n_small = 0, lds_big = 0, lds_small = 0;
+    if (!P.items.empty()) {
+        const int64_t csz = (dtype == PC_F64) ? 16 : 8;
+        std::vector<pc::Item> big, small;
+        for (const pc::Item& it : P.items) {
+            const int lds = (int)(((int64_t)it.n0 * it.ld + pc::twiddle_elems(it.a0, it.b0, it.am, it.bm)) * csz);
+            if (lds <= pc::kSmallItemLds) {
+                small.push_back(it);
+                lds_small = std::max(lds_small, lds);
+            } else {
+                big.push_back(it);
+                lds_big = std::max(lds_big, lds);
+            }
+        }
+        n_big = (int)big.size();
+        n_small = (int)small.size();
+        big.insert(big.end(), small.begin(), small.end());
+        if ((st = upload(op, big, &d_split, s)) != PC_OK) {
+            delete op;
+            return st;
+        }
+    }
     pc::DevPlan& D = op->dev;
+    D.items_split = static_cast<const pc::Item*>(d_split);
+    D.n_big = n_big;
+    D.n_small = n_small;
+    D.lds_big = lds_big;
+    D.lds_small = lds_small;
     D.items = static_cast<const pc::Item*>(d_items);
     D.n_items = (int)P.items.size();
     D.items_ord[0] = static_cast<const pc::Item*>(d_ord[0]);
@@ -1086,6 +1124,9 @@ pc_status pc_set_tuning(pc_op* op, int key, int64_t value) {
             return PC_OK;
         case PC_TUNE_XCD_ORDER:
             op->tune_item_major = value != 0;
+            return PC_OK;
+        case PC_TUNE_SPLIT:
+            op->tune_split = value != 0;
             return PC_OK;
         case PC_TUNE_BUDGET:
             if (value < 0) return fail(PC_ERR_ARG, "budget out of range");

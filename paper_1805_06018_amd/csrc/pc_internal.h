@@ -10,6 +10,8 @@ namespace pc {
 // the library is a * b with a, b in {1,2,3,4,5,6,7,8,9,10,12,14,15,16}.
 constexpr int kMaxRadix = 16;
 constexpr int kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+// Largest item LDS (box and twiddles) that runs two workgroups per CU.
+constexpr int kSmallItemLds = kLdsBytes / 2 - 1024;
 constexpr int kReduceCols = 256;       // reduce tile width (threads)
 constexpr int kReduceRows = 8;         // reduce tile height (accumulators per thread)
 constexpr int kAxisThreads = 256;      // threads of the 3-D axis-0 kernel

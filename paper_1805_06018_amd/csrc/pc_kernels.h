@@ -28,6 +28,12 @@ struct DevPlan {
     int conv_threads;               // 1-D/2-D convolution workgroup size (1024 or 512)
     int max_lds_axis;               // 3-D axis-0 kernel
     int dtype;                      // 0 = f32, 1 = f64
+    // staged FP32 launches in two parts: the items whose LDS fits twice in a
+    // CU (kSmallItemLds) run as 512-thread workgroups, two per CU, after the
+    // others; items_split holds the others, then those (n_big + n_small)
+    const Item* items_split;
+    int n_big, n_small;
+    int lds_big, lds_small;         // LDS bytes of the two launches
     int* queue;                     // persistent launches: 8 XCD counters, 16 ints apart
     int n_cu;                       // compute units of the device
 };
@@ -65,6 +71,11 @@ hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int it
 bool persistent_fits(const DevPlan& P);
 hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
                                   int64_t slot_stride, hipStream_t s);
+
+// Staged FP32 launch of all items in two parts (see DevPlan::items_split):
+// the same staging boxes as launch_conv with out null.
+hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
+                             int64_t slot_stride, hipStream_t s);
 
 // out[b * ld + i] = 0 for b < B, i < N.
 hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, hipStream_t s);

@@ -119,6 +119,20 @@ __global__ __launch_bounds__(NT) void conv_kernel(ConvArgs<T> A) {
     conv_unit<T, NT, ADD>(A, buf, item, rhs, true, threadIdx.x);
 }
 
+// Staged FP32 launch of the small items: 512-thread workgroups held to 128
+// VGPRs, so that two fit in a CU (LDS, waves and registers), otherwise as
+// conv_kernel<T, 512, false>.
+template <class T>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void conv_kernel_small(ConvArgs<T> A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, l = bid >> 3;
+    const int item = xcd + 8 * (l / A.B);
+    if (item >= A.n_items) return;
+    conv_unit<T, 512, false>(A, buf, item, l % A.B, true, threadIdx.x);
+}
+
 // Persistent form of the staged launch: a fixed grid of workgroups (one per
 // CU), each taking units from the queue of its XCD (block id mod 8).  Unit l
 // of XCD x is item x + 8 (l / B) with vector l mod B: the same units on the
@@ -549,6 +563,42 @@ hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const v
     return conv_persistent_t<float>(P, adjoint, B, in, ld_in, slots, slot_stride, s);
 }
 
+hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
+                             int64_t slot_stride, hipStream_t s) {
+    if (P.dtype != 0 || P.conv_threads != 1024) return hipErrorInvalidValue;
+    if (B <= 0) return hipSuccess;
+    ConvArgs<float> A;
+    A.items = P.items_split;
+    A.item_lo = 0;
+    A.n_items = P.n_big;
+    A.B = B;
+    A.adj = adjoint ? 1 : 0;
+    A.spec = static_cast<const cx<float>*>(P.spec);
+    A.wts = static_cast<const float*>(P.wts);
+    A.tw = static_cast<const cx<float>*>(P.tw);
+    A.in = static_cast<const float*>(in);
+    A.ld_in = ld_in;
+    A.slots = static_cast<float*>(slots);
+    A.slot_stride = slot_stride;
+    A.out = nullptr;
+    A.ldo = 0;
+    A.pitch = P.cols;
+    A.item_major = 0;
+    if (P.n_big > 0) {
+        const int64_t nblk = 8 * ((int64_t)((P.n_big + 7) / 8) * B);
+        if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((conv_kernel<float, 1024, false>), dim3((unsigned)nblk), dim3(1024), P.lds_big, s, A);
+    }
+    if (P.n_small > 0) {
+        A.item_lo = P.n_big;
+        A.n_items = P.n_small;
+        const int64_t nblk = 8 * ((int64_t)((P.n_small + 7) / 8) * B);
+        if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((conv_kernel_small<float>), dim3((unsigned)nblk), dim3(512), P.lds_small, s, A);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
                        hipStream_t s, bool item_major) {
@@ -608,6 +658,7 @@ hipError_t set_kernel_attributes() {
         reinterpret_cast<const void*>(&conv_kernel<float, 1024, true>),
         reinterpret_cast<const void*>(&conv_kernel<float, 512, true>),
         reinterpret_cast<const void*>(&conv_kernel<double, 512, true>),
+        reinterpret_cast<const void*>(&conv_kernel_small<float>),
         reinterpret_cast<const void*>(&conv_persistent_kernel<float, 1024>),
         reinterpret_cast<const void*>(&conv_persistent_kernel<float, 512>),
         reinterpret_cast<const void*>(&conv_persistent_kernel<double, 512>),

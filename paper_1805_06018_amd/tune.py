@@ -4,8 +4,9 @@ The library's schedule knobs (pc_set_tuning) change how a batched apply is
 cut into launches, never what it computes: colour launches adding into the
 outputs or staged boxes and a reduction (PC_TUNE_DIRECT, 1-D/2-D
 operators), staged convolutions as one workgroup per unit (whole items
-per XCD or item-major, PC_TUNE_XCD_ORDER) or as a fixed grid taking units
-from queues (PC_TUNE_PERSISTENT), vectors per
+per XCD or item-major, PC_TUNE_XCD_ORDER; small items two workgroups per
+CU, PC_TUNE_SPLIT) or as a fixed grid taking units from queues
+(PC_TUNE_PERSISTENT), vectors per
 convolution launch (PC_TUNE_CHUNK), reduction
 overlapped on a second stream (PC_TUNE_OVERLAP, staged 1-D/2-D) and the
 plane-spectrum scratch per item group (PC_TUNE_SCRATCH, 3-D operators).
@@ -35,6 +36,7 @@ def candidates(op, B, allow_overlap=True):
         default[_lib.PC_TUNE_STREAMS] = 4
         default[_lib.PC_TUNE_PERSISTENT] = 0
         default[_lib.PC_TUNE_XCD_ORDER] = 0
+        default[_lib.PC_TUNE_SPLIT] = 1
     out = [dict(default)]
     # powers of two and the sizes in between (for B = 64: 8, 10, 12, 16, 20,
     # 22, 24, 28, 32, 64); a batch that a chunk does not divide ends with a
@@ -50,14 +52,16 @@ def candidates(op, B, allow_overlap=True):
                     out.append(c)
     else:
         for overlap in ((0, 1) if allow_overlap else (0,)):   # staged boxes and a reduction
-            # one workgroup per unit (whole items per XCD, or item-major), or unit queues
-            for persistent, xcd in ((0, 0), (0, 1), (1, 0)):
+            # one workgroup per unit (whole items per XCD with the small
+            # items two per CU or not, or item-major), or unit queues
+            for persistent, xcd, split in ((0, 0, 1), (0, 0, 0), (0, 1, 0), (1, 0, 0)):
                 for chunk in [0] + chunks:
                     c = dict(default)
                     c[_lib.PC_TUNE_CHUNK] = chunk
                     c[_lib.PC_TUNE_OVERLAP] = overlap
                     c[_lib.PC_TUNE_PERSISTENT] = persistent
                     c[_lib.PC_TUNE_XCD_ORDER] = xcd
+                    c[_lib.PC_TUNE_SPLIT] = split
                     if c != default:
                         out.append(c)
         for streams in (4, 2, 1):               # colour launches
@@ -172,5 +176,6 @@ def names(setting):
     s = {int(k): v for k, v in setting.items()}
     return {"direct": s.get(_lib.PC_TUNE_DIRECT, 0), "streams": s.get(_lib.PC_TUNE_STREAMS, 1),
             "persistent": s.get(_lib.PC_TUNE_PERSISTENT, 0), "item_major": s.get(_lib.PC_TUNE_XCD_ORDER, 0),
+            "split": s.get(_lib.PC_TUNE_SPLIT, 1),
             "chunk": s.get(_lib.PC_TUNE_CHUNK, 0),
             "overlap": s.get(_lib.PC_TUNE_OVERLAP, 0), "scratch_MiB": s.get(_lib.PC_TUNE_SCRATCH, 0) // _MiB}

@@ -113,10 +113,11 @@ def test_batch_column_equals_single_apply_and_plain(lib):
         assert torch.equal(Ob[:, :w.N], out[:3]) and torch.all(Ob[:, w.N:] == 7.0)
     op.set_tuning(lib.PC_TUNE_DIRECT, 0)
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
-    # persistent convolution launches (units from per-XCD queues) and the
-    # item-major block order: the same bits
-    for key in (lib.PC_TUNE_PERSISTENT, lib.PC_TUNE_XCD_ORDER):
-        op.set_tuning(key, 1)
+    # persistent convolution launches (units from per-XCD queues), the
+    # item-major block order and one launch for all items (no two-per-CU
+    # part for the small items): the same bits
+    for key, val in ((lib.PC_TUNE_PERSISTENT, 1), (lib.PC_TUNE_XCD_ORDER, 1), (lib.PC_TUNE_SPLIT, 0)):
+        op.set_tuning(key, val)
         for chunk in (0, 3):
             op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
             got = torch.full_like(U, float("nan"))
@@ -125,7 +126,7 @@ def test_batch_column_equals_single_apply_and_plain(lib):
             op.apply_adjoint_batch(U, gota)
             torch.cuda.synchronize()
             assert torch.equal(got, out) and torch.equal(gota, adj_ref), (key, chunk)
-        op.set_tuning(key, 0)
+        op.set_tuning(key, 1 - val)
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
 
 
@@ -149,12 +150,15 @@ def test_full_size_blur1024_batch64(lib, adjoint):
     Ud = torch.from_numpy(U).cuda()
     out = torch.zeros_like(Ud)
     (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, out)
-    # the persistent form of the launch gives the same bits
-    op.set_tuning(lib.PC_TUNE_PERSISTENT, 1)
-    again = torch.full_like(Ud, float("nan"))
-    (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, again)
-    torch.cuda.synchronize()
-    assert torch.equal(again, out)
+    # the persistent form of the launch and the single launch for all items
+    # give the same bits
+    for key, val in ((lib.PC_TUNE_PERSISTENT, 1), (lib.PC_TUNE_SPLIT, 0)):
+        op.set_tuning(key, val)
+        again = torch.full_like(Ud, float("nan"))
+        (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, again)
+        torch.cuda.synchronize()
+        assert torch.equal(again, out), key
+        op.set_tuning(key, 1 - val)
     got = out.cpu().numpy()
     assert np.all(np.isfinite(got))
     ora = OracleOperator.from_workload(w)

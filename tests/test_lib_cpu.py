@@ -359,9 +359,9 @@ def test_autotune_candidates():
     against staging, persistent launches, chunk and overlap."""
     import types
     from paper_1805_06018_amd import _lib, tune
-    defaults = {_lib.PC_TUNE_DIRECT: 0, _lib.PC_TUNE_STREAMS: 4}
+    defaults = {_lib.PC_TUNE_DIRECT: 0, _lib.PC_TUNE_STREAMS: 4, _lib.PC_TUNE_SPLIT: 1}
     for d, keys in ((2, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_OVERLAP, _lib.PC_TUNE_DIRECT, _lib.PC_TUNE_STREAMS,
-                         _lib.PC_TUNE_PERSISTENT, _lib.PC_TUNE_XCD_ORDER}),
+                         _lib.PC_TUNE_PERSISTENT, _lib.PC_TUNE_XCD_ORDER, _lib.PC_TUNE_SPLIT}),
                     (3, {_lib.PC_TUNE_CHUNK, _lib.PC_TUNE_SCRATCH})):
         c = tune.candidates(types.SimpleNamespace(d=d), 16)
         assert all(v == defaults.get(k, 0) for k, v in c[0].items())
