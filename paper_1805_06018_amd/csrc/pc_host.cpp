@@ -459,9 +459,7 @@ pc_status run_direct(pc_op* op, bool adj, int64_t B, const void* U, int64_t ldu,
 }
 
 // The staged FP32 launch runs in two parts (see DevPlan::items_split).
-bool uses_split(const pc_op* op) {
-    return op->dev.n_small > 0 && op->dev.dtype == 0 && op->dev.conv_threads == 1024;
-}
+bool uses_split(const pc_op* op) { return op->dev.n_small > 0 && op->dev.dtype == 0; }
 
 bool uses_direct(const pc_op* op) { return op->tune_direct && op->plan.d <= 2 && !op->plan.cbeg_fwd.empty(); }
 

@@ -565,7 +565,7 @@ hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const v
 
 hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
                              int64_t slot_stride, hipStream_t s) {
-    if (P.dtype != 0 || P.conv_threads != 1024) return hipErrorInvalidValue;
+    if (P.dtype != 0) return hipErrorInvalidValue;
     if (B <= 0) return hipSuccess;
     ConvArgs<float> A;
     A.items = P.items_split;

@@ -946,6 +946,10 @@ pc_status build_plan(const CreateArgs& a, Plan& p, std::string& err) {
                             const int64_t out0 = std::min<int64_t>(n0p, h0 + K[0] - 1);
                             cost = (double)P0 * P1 *
                                    unit_cycles(NT, n0p, a0p, b0p, Mp, ap, bp, h0, out0, std::min<int64_t>(2 * Mp, h1 + K[1] - 1));
+                            // FP32 items within half a CU's LDS run two workgroups per CU
+                            // (measured: about 0.73 of their one-per-CU time)
+                            const int64_t lds_item = ((int64_t)n0p * ld_p + twiddle_elems(a0p, b0p, ap, bp)) * (int64_t)csz;
+                            if (a.dtype == PC_F32 && lds_item <= kSmallItemLds) cost *= 0.73;
                         }
                         if (cost < best_cost) {
                             best_cost = cost;
