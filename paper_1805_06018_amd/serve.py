@@ -89,7 +89,7 @@ class _Batch:
 
 
 class Server:
-    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=4, large_work=256 << 20):
+    def __init__(self, residents, hbm_budget=16 << 30, max_batch=64, n_streams=4, large_work=128 << 20):
         """max_batch: vectors merged into one launch; large_work: requests
         whose work (_work) exceeds it run alone, and merged batches stay
         below it."""
@@ -229,7 +229,10 @@ class Server:
             # overlapped, and do not overtake a large request at the head
             if any(b.large for b in inflight):
                 continue
-            head = next((q for q in pending if q.op not in busy_ops), None)
+            # a large request at the head of the queue is served next, whatever
+            # operator it needs: nothing behind it is admitted while it waits
+            head = pending[0] if self._large(pending[0]) else next(
+                (q for q in pending if q.op not in busy_ops), None)
             if head is None:
                 continue
             if self._large(head):
@@ -372,7 +375,7 @@ def main(argv=None):
     ap.add_argument("--ops", choices=["2d", "all"], default="all")
     ap.add_argument("--plain-requests", type=int, default=40)
     ap.add_argument("--loads", type=str, default="0.5,0.8,1.0")
-    ap.add_argument("--large-mwork", type=float, default=256.0,
+    ap.add_argument("--large-mwork", type=float, default=128.0,
                     help="requests whose work (vectors x grid points, 3-D points x 10) exceeds this many "
                          "million run alone in the batched loop")
     args = ap.parse_args(argv)
