@@ -25,7 +25,8 @@
  *    thread-local message readable with pc_last_error().
  *  - An operator is read-only after pc_create.  Calls on one operator must be
  *    serialised by the caller (they share the operator's work buffers:
- *    staging, 3-D scratch, estimator buffers); different operators are
+ *    staging, 3-D scratch, estimator buffers, the unit counters of the
+ *    persistent launch); different operators are
  *    independent.  A call whose work buffers must grow releases the old ones
  *    in stream order after the operator's previous call has ended (an event;
  *    neither the host nor other streams wait) and allocates on its stream.
