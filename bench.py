@@ -125,6 +125,7 @@ def main():
         schedule = {"autotuned": True, "plan_flags": res["plan_flags"], "plans": res["plans"],
                     "chosen": tune.names(res["best"]), "best_ms": res["best_ms"],
                     "default_ms": res["default_ms"], "candidates": len(res["table"]),
+                    "confirmed": [dict(tune.names(c["setting"]), ms=c["ms"]) for c in res.get("confirm", [])],
                     "tune_s": time.time() - t_tune}
         print(f"# autotune: {schedule}", file=sys.stderr, flush=True)
 
@@ -223,9 +224,9 @@ def main():
     direct, persistent = chosen.get("direct", 0), chosen.get("persistent", 0)
     if not three_d and not f64 and not direct and not persistent and not chosen.get("item_major", 0):
         per_vec = st["slot_elems_fwd"] * esz
-        cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's default 2 GiB staging cap
+        cap = max(1, (2 << 30) // max(per_vec, 1))          # the library's 2 GiB staging cap
         chunk = schedule.get("chosen", {}).get("chunk", 0) if schedule["autotuned"] else 0
-        chunk = min(B, chunk) if chunk > 0 else min(cap, B)  # an explicit chunk is taken as given
+        chunk = min(cap, chunk if chunk > 0 else B)
         sizes = [chunk] * (B // chunk) + ([B % chunk] if B % chunk else [])
         if len(sizes) == prof["conv_launches"] / args.steps:
             launch = "split" if chosen.get("split", 1) else "single"

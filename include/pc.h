@@ -318,8 +318,8 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
 
 /* Schedule knobs (defaults chosen by the library; an autotuner may override).
  *  PC_TUNE_CHUNK    vectors per convolution launch (0 = library default:
- *                   as many as fit a 2 GiB staging buffer; an explicit
- *                   value is taken even beyond that size)
+ *                   as many as fit a 2 GiB staging buffer; 3-D operators
+ *                   take an explicit value even beyond that size)
  *  PC_TUNE_OVERLAP  1: reduce chunk i on a library stream while chunk i+1
  *                   convolves; 0: everything on the caller's stream
  *                   (2-D operators only)

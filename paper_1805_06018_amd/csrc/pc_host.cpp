@@ -482,13 +482,11 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
     const size_t per_bytes = (size_t)std::max<int64_t>(per, 1) * op->esz;
     int64_t chunk = 1;
     if (!plain) {
-        // an explicit chunk overrides the default staging cap (as in 3-D)
         const size_t cap_bytes = op->tune_overlap ? kSlotCapBytes / 2 : kSlotCapBytes;
         const int64_t cap = (int64_t)std::max<size_t>(1, cap_bytes / per_bytes);
-        if (op->tune_chunk > 0)
-            chunk = std::min<int64_t>(op->tune_chunk, B);
-        else
-            chunk = std::min<int64_t>(cap, std::max<int64_t>(1, op->tune_overlap ? (B + kMinChunks - 1) / kMinChunks : B));
+        const int64_t want = op->tune_chunk > 0 ? op->tune_chunk
+                             : (op->tune_overlap ? (B + kMinChunks - 1) / kMinChunks : B);
+        chunk = std::min<int64_t>(cap, std::max<int64_t>(1, want));
     }
     const int64_t nchunks = (B + chunk - 1) / chunk;
     const bool overlap = !plain && op->tune_overlap && nchunks > 1;

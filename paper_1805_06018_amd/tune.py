@@ -10,9 +10,10 @@ CU, PC_TUNE_SPLIT) or as a fixed grid taking units from queues
 convolution launch (PC_TUNE_CHUNK), reduction
 overlapped on a second stream (PC_TUNE_OVERLAP, staged 1-D/2-D) and the
 plane-spectrum scratch per item group (PC_TUNE_SCRATCH, 3-D operators).
-autotune() times each candidate setting on the caller's own vectors, checks
-that every schedule gives the bitwise same result, applies the fastest and
-returns the whole table.  Results can
+autotune() times each candidate setting on the caller's own vectors, times
+the fastest few again in alternating rounds, checks that every schedule
+gives the bitwise same result, applies the one with the least median and
+returns both tables.  Results can
 be cached in a JSON file keyed by the operator's shape, size and batch.
 """
 import json
@@ -84,11 +85,28 @@ def _apply_settings(op, setting):
         op.set_tuning(int(k), int(v))
 
 
-def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=True):
+def _time(fn, U, OUT, reps):
+    """Durations (ms) of reps back-to-back calls, each bracketed by events."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        fn(U, OUT)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=True, confirm=4, confirm_reps=8,
+             confirm_rounds=2):
     """Times every candidate schedule for applying op (adjoint: its adjoint)
-    to the batch U into OUT, leaves the fastest one set on op and returns
-    {"best": {key: value}, "best_ms": t, "default_ms": t0, "table": [...]}.
-    Raises if two schedules disagree bitwise."""
+    to the batch U into OUT (the least of reps calls each), then times the
+    confirm fastest again in confirm_rounds alternating rounds of
+    confirm_reps calls, leaves the one with the least median set on op and
+    returns {"best": {key: value}, "best_ms": its median, "default_ms": t0,
+    "table": [first pass], "confirm": [second pass]}.  A single pass of a
+    few calls lets run-to-run noise choose among schedules within a percent
+    of each other; the second pass is what decides.  Raises if two
+    schedules disagree bitwise."""
     B = 1 if U.dim() == 1 else U.shape[0]
     key = _key(op, B, adjoint) + ("" if allow_overlap else "_noovl")
     if cache_path and os.path.exists(cache_path):
@@ -101,7 +119,8 @@ def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=T
     fn = op.apply_adjoint_batch if adjoint else op.apply_batch
     ref = None
     table = []
-    for setting in candidates(op, B, allow_overlap):
+    cands = candidates(op, B, allow_overlap)
+    for setting in cands:
         _apply_settings(op, setting)
         fn(U, OUT)   # sizes the work buffers for this schedule
         torch.cuda.synchronize()
@@ -109,17 +128,22 @@ def autotune(op, U, OUT, adjoint=False, reps=3, cache_path=None, allow_overlap=T
             ref = OUT.clone()
         elif not torch.equal(OUT, ref):
             raise RuntimeError(f"schedule {setting} changed the result")
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-        ev[0].record()
-        for i in range(reps):
-            fn(U, OUT)
-            ev[i + 1].record()
-        torch.cuda.synchronize()
-        ms = min(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        ms = min(_time(fn, U, OUT, reps))
         table.append({"setting": {str(k): v for k, v in setting.items()}, "ms": ms})
-    best = min(table, key=lambda r: r["ms"])
-    res = {"best": best["setting"], "best_ms": best["ms"], "default_ms": table[0]["ms"], "table": table}
-    _apply_settings(op, {int(k): v for k, v in best["setting"].items()})
+    top = sorted(range(len(table)), key=lambda i: table[i]["ms"])[:max(1, confirm)]
+    runs = {i: [] for i in top}
+    for _ in range(max(1, confirm_rounds)):
+        for i in top:
+            _apply_settings(op, cands[i])
+            fn(U, OUT)
+            runs[i] += _time(fn, U, OUT, max(1, confirm_reps))
+            if not torch.equal(OUT, ref):
+                raise RuntimeError(f"schedule {cands[i]} changed the result")
+    med = {i: sorted(runs[i])[len(runs[i]) // 2] for i in top}
+    bi = min(top, key=lambda i: med[i])
+    res = {"best": table[bi]["setting"], "best_ms": med[bi], "default_ms": table[0]["ms"], "table": table,
+           "confirm": [{"setting": table[i]["setting"], "ms": med[i]} for i in top]}
+    _apply_settings(op, cands[bi])
     if cache_path:
         cache = {}
         if os.path.exists(cache_path):

@@ -150,16 +150,15 @@ def test_full_size_blur1024_batch64(lib, adjoint):
     Ud = torch.from_numpy(U).cuda()
     out = torch.zeros_like(Ud)
     (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, out)
-    # the persistent form of the launch, the single launch for all items and
-    # one launch for all 64 vectors (an explicit chunk beyond the default
-    # staging cap, which cuts the batch in two) give the same bits
-    for key, val, off in ((lib.PC_TUNE_PERSISTENT, 1, 0), (lib.PC_TUNE_SPLIT, 0, 1), (lib.PC_TUNE_CHUNK, 64, 0)):
+    # the persistent form of the launch and the single launch for all items
+    # give the same bits
+    for key, val in ((lib.PC_TUNE_PERSISTENT, 1), (lib.PC_TUNE_SPLIT, 0)):
         op.set_tuning(key, val)
         again = torch.full_like(Ud, float("nan"))
         (op.apply_adjoint_batch if adjoint else op.apply_batch)(Ud, again)
         torch.cuda.synchronize()
         assert torch.equal(again, out), key
-        op.set_tuning(key, off)
+        op.set_tuning(key, 1 - val)
     got = out.cpu().numpy()
     assert np.all(np.isfinite(got))
     ora = OracleOperator.from_workload(w)
