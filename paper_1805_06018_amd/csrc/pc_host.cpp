@@ -237,6 +237,31 @@ void prof_end(pc_op* op, hipStream_t s, hipEvent_t start, int kind, int vectors)
     op->timed.push_back({start, e, kind, vectors});
 }
 
+// Events for a launch that carries its own timing (pc::LaunchEvents: no
+// marker packets between the kernels); both null when not profiling or
+// under capture.  prof_take registers them once the launch is enqueued,
+// prof_drop returns them to the pool when it failed.
+pc::LaunchEvents prof_events(pc_op* op, hipStream_t s) {
+    pc::LaunchEvents ev;
+    if (!op->profiling || capturing(s)) return ev;
+    ev.start = get_event(op);
+    ev.stop = ev.start ? get_event(op) : nullptr;
+    if (ev.start && !ev.stop) {
+        op->event_pool.push_back(ev.start);
+        ev.start = nullptr;
+    }
+    return ev;
+}
+
+void prof_take(pc_op* op, const pc::LaunchEvents& ev, int kind, int vectors) {
+    if (ev.start && ev.stop) op->timed.push_back({ev.start, ev.stop, kind, vectors});
+}
+
+void prof_drop(pc_op* op, const pc::LaunchEvents& ev) {
+    if (ev.start) op->event_pool.push_back(ev.start);
+    if (ev.stop) op->event_pool.push_back(ev.stop);
+}
+
 // Test hook: the operator's convolution launches numbered dbg_first ..
 // dbg_first + dbg_count - 1 (counted from the last pc_debug_fail_launches)
 // fail before anything of theirs is enqueued.
@@ -520,18 +545,25 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
                 if (e != hipSuccess) return hip_fail(e, "conv launch");
                 prof_end(op, s, ev, 0, 1);
             }
-        } else {
+        } else if (op->tune_persistent && pc::persistent_fits(op->dev)) {
             if (injected_failure(op)) return injected();
-            prof_begin(op, s, &ev);
-            if (op->tune_persistent && pc::persistent_fits(op->dev))
-                e = pc::launch_conv_persistent(op->dev, adj, nb, in, ldu, slots, per, s);
-            else if (op->tune_split && !op->tune_item_major && uses_split(op))
-                e = pc::launch_conv_split(op->dev, adj, nb, in, ldu, slots, per, s);
-            else
-                e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s,
-                                    op->tune_item_major);
+            prof_begin(op, s, &ev);   // a fill kernel, then the persistent kernel
+            e = pc::launch_conv_persistent(op->dev, adj, nb, in, ldu, slots, per, s);
             if (e != hipSuccess) return hip_fail(e, "conv launch");
             prof_end(op, s, ev, 0, nb);
+        } else {
+            if (injected_failure(op)) return injected();
+            const pc::LaunchEvents lev = prof_events(op, s);
+            if (op->tune_split && !op->tune_item_major && uses_split(op))
+                e = pc::launch_conv_split(op->dev, adj, nb, in, ldu, slots, per, s, lev);
+            else
+                e = pc::launch_conv(op->dev, op->dev.items, adj, 0, n_items, nb, in, ldu, slots, per, nullptr, 0, s,
+                                    op->tune_item_major, lev);
+            if (e != hipSuccess) {
+                prof_drop(op, lev);
+                return hip_fail(e, "conv launch");
+            }
+            prof_take(op, lev, 0, nb);
         }
         hipStream_t rs = s;
         if (overlap) {
@@ -540,10 +572,13 @@ pc_status run_batch(pc_op* op, bool adj, bool plain, int64_t B, const void* U, i
             if (e != hipSuccess) return hip_fail(e, "event chaining");
             rs = op->aux;
         }
-        prof_begin(op, rs, &ev);
-        e = pc::launch_reduce(op->dev, adj, nb, slots, per, out, ldo, rs, acc, alpha);
-        if (e != hipSuccess) return hip_fail(e, "reduce launch");
-        prof_end(op, rs, ev, 1, nb);
+        const pc::LaunchEvents rev = prof_events(op, rs);
+        e = pc::launch_reduce(op->dev, adj, nb, slots, per, out, ldo, rs, acc, alpha, rev);
+        if (e != hipSuccess) {
+            prof_drop(op, rev);
+            return hip_fail(e, "reduce launch");
+        }
+        prof_take(op, rev, 1, nb);
         if (overlap) {
             e = hipEventRecord(op->ev_red[pb], op->aux);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -53,6 +53,14 @@ struct Conv3Launch {
     int max_gather, max_write, max_tiles;
 };
 
+// Timing events of a launch, carried by its own dispatch packets (the start
+// event by the first kernel, the stop event by the last), so that timing adds
+// no marker packets to the stream; both null for an untimed launch.  A launch
+// with no work records both as plain events on its stream.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Convolution items (one workgroup per item and vector): items[item_lo,
 // item_hi) of the given array (the plain mode launches one item at a time),
 // B vectors starting at 'in'.  With out null the written boxes go to
@@ -62,7 +70,7 @@ struct Conv3Launch {
 // instead of whole items per XCD (the same results).
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                       hipStream_t s, bool item_major = false);
+                       hipStream_t s, bool item_major = false, LaunchEvents ev = {});
 
 // Staged launch of all items in persistent form (fixed grid, per-XCD unit
 // queues at P.queue, cleared on s first): the same staging boxes as
@@ -75,7 +83,7 @@ hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const v
 // Staged FP32 launch of all items in two parts (see DevPlan::items_split):
 // the same staging boxes as launch_conv with out null.
 hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
-                             int64_t slot_stride, hipStream_t s);
+                             int64_t slot_stride, hipStream_t s, LaunchEvents ev = {});
 
 // out[b * ld + i] = 0 for b < B, i < N.
 hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, hipStream_t s);
@@ -86,7 +94,8 @@ hipError_t launch_conv3(const DevPlan& P, const Conv3Launch& L, hipStream_t s);
 // Deterministic reduction of the staging boxes into the outputs (out = sum,
 // or out += alpha * sum with accumulate).
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride,
-                         void* out, int64_t ldo, hipStream_t s, bool accumulate = false, double alpha = 1.0);
+                         void* out, int64_t ldo, hipStream_t s, bool accumulate = false, double alpha = 1.0,
+                         LaunchEvents ev = {});
 
 // Estimator: per-leaf (leaf_box [L][6]) FP64 sums of squares of (Yt - Y) over q vectors into
 // leaf_sq, and the totals sum (Yt - Y)^2 and sum Y^2 into totals[2] (through n_part

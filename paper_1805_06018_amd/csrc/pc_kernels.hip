@@ -2,11 +2,33 @@
 #include <algorithm>
 #include <mutex>
 
+#include <hip/hip_ext.h>
+
 #include "pc_kernels.h"
 #include "pc_entries.h"
 #include "pc_phases3.h"
 
 namespace pc {
+
+// A kernel launch that carries timing events in its dispatch when START or
+// STOP is non-null (never under stream capture: the host does not time
+// captured calls), else a plain launch.
+#define PC_LAUNCH(K, G, BL, LDS, S, START, STOP, ...)                                                  \
+    do {                                                                                               \
+        if ((START) || (STOP))                                                                         \
+            hipExtLaunchKernelGGL(K, G, BL, (std::uint32_t)(LDS), S, START, STOP, 0u, __VA_ARGS__);    \
+        else                                                                                           \
+            hipLaunchKernelGGL(K, G, BL, LDS, S, __VA_ARGS__);                                         \
+    } while (0)
+
+// The events of a timed launch that enqueued no kernel, recorded on s so
+// that the caller can still read them.
+static hipError_t record_unused(const LaunchEvents& ev, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (ev.start) e = hipEventRecord(ev.start, s);
+    if (e == hipSuccess && ev.stop) e = hipEventRecord(ev.stop, s);
+    return e;
+}
 
 // ------------------------------------------------- allocation-free work area
 // Staging and 3-D scratch of pc_apply_batch_noalloc: a file-scope device
@@ -473,7 +495,7 @@ hipError_t launch_fill_zero(int dtype, void* out, int64_t ld, int64_t N, int B, 
 template <class T>
 static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item_lo, int item_hi, int B,
                          const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                         hipStream_t s, bool item_major) {
+                         hipStream_t s, bool item_major, LaunchEvents ev) {
     ConvArgs<T> A;
     A.items = items;
     A.item_lo = item_lo;
@@ -491,20 +513,21 @@ static hipError_t conv_t(const DevPlan& P, const Item* items, bool adj, int item
     A.ldo = ldo;
     A.pitch = P.cols;
     A.item_major = item_major ? 1 : 0;
-    if (A.n_items <= 0 || B <= 0) return hipSuccess;
+    if (A.n_items <= 0 || B <= 0) return record_unused(ev, s);
     const int64_t nblk = (out || item_major) ? (int64_t)A.n_items * B : 8 * ((int64_t)((A.n_items + 7) / 8) * B);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblk);
     if (P.conv_threads == 512) {
         if (out)
-            hipLaunchKernelGGL((conv_kernel<T, 512, true>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
+            PC_LAUNCH((conv_kernel<T, 512, true>), grid, dim3(512), P.max_lds, s, ev.start, ev.stop, A);
         else
-            hipLaunchKernelGGL((conv_kernel<T, 512, false>), dim3((unsigned)nblk), dim3(512), P.max_lds, s, A);
+            PC_LAUNCH((conv_kernel<T, 512, false>), grid, dim3(512), P.max_lds, s, ev.start, ev.stop, A);
     } else {
         if constexpr (sizeof(T) == 4) {
             if (out)
-                hipLaunchKernelGGL((conv_kernel<T, 1024, true>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+                PC_LAUNCH((conv_kernel<T, 1024, true>), grid, dim3(1024), P.max_lds, s, ev.start, ev.stop, A);
             else
-                hipLaunchKernelGGL((conv_kernel<T, 1024, false>), dim3((unsigned)nblk), dim3(1024), P.max_lds, s, A);
+                PC_LAUNCH((conv_kernel<T, 1024, false>), grid, dim3(1024), P.max_lds, s, ev.start, ev.stop, A);
         } else {
             return hipErrorInvalidValue;   // FP64 items always use 512 threads
         }
@@ -564,9 +587,9 @@ hipError_t launch_conv_persistent(const DevPlan& P, bool adjoint, int B, const v
 }
 
 hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* in, int64_t ld_in, void* slots,
-                             int64_t slot_stride, hipStream_t s) {
+                             int64_t slot_stride, hipStream_t s, LaunchEvents ev) {
     if (P.dtype != 0) return hipErrorInvalidValue;
-    if (B <= 0) return hipSuccess;
+    if (B <= 0 || (P.n_big <= 0 && P.n_small <= 0)) return record_unused(ev, s);
     ConvArgs<float> A;
     A.items = P.items_split;
     A.item_lo = 0;
@@ -584,46 +607,50 @@ hipError_t launch_conv_split(const DevPlan& P, bool adjoint, int B, const void* 
     A.ldo = 0;
     A.pitch = P.cols;
     A.item_major = 0;
+    const int64_t nblk_big = 8 * ((int64_t)((P.n_big + 7) / 8) * B);
+    const int64_t nblk_small = 8 * ((int64_t)((P.n_small + 7) / 8) * B);
+    if (nblk_big > 0x7fffffff || nblk_small > 0x7fffffff) return hipErrorInvalidValue;
+    // timing: the start event rides on the first kernel, the stop event on the last
     if (P.n_big > 0) {
-        const int64_t nblk = 8 * ((int64_t)((P.n_big + 7) / 8) * B);
-        if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((conv_kernel<float, 1024, false>), dim3((unsigned)nblk), dim3(1024), P.lds_big, s, A);
+        const hipEvent_t stop = P.n_small > 0 ? nullptr : ev.stop;
+        PC_LAUNCH((conv_kernel<float, 1024, false>), dim3((unsigned)nblk_big), dim3(1024), P.lds_big, s, ev.start,
+                  stop, A);
     }
     if (P.n_small > 0) {
         A.item_lo = P.n_big;
         A.n_items = P.n_small;
-        const int64_t nblk = 8 * ((int64_t)((P.n_small + 7) / 8) * B);
-        if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((conv_kernel_small<float>), dim3((unsigned)nblk), dim3(512), P.lds_small, s, A);
+        const hipEvent_t start = P.n_big > 0 ? nullptr : ev.start;
+        PC_LAUNCH((conv_kernel_small<float>), dim3((unsigned)nblk_small), dim3(512), P.lds_small, s, start, ev.stop,
+                  A);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_conv(const DevPlan& P, const Item* items, bool adjoint, int item_lo, int item_hi, int B,
                        const void* in, int64_t ld_in, void* slots, int64_t slot_stride, void* out, int64_t ldo,
-                       hipStream_t s, bool item_major) {
+                       hipStream_t s, bool item_major, LaunchEvents ev) {
     if (P.dtype == 1)
         return conv_t<double>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s,
-                              item_major);
+                              item_major, ev);
     return conv_t<float>(P, items, adjoint, item_lo, item_hi, B, in, ld_in, slots, slot_stride, out, ldo, s,
-                         item_major);
+                         item_major, ev);
 }
 
 hipError_t launch_reduce(const DevPlan& P, bool adjoint, int B, const void* slots, int64_t slot_stride, void* out,
-                         int64_t ldo, hipStream_t s, bool accumulate, double alpha) {
+                         int64_t ldo, hipStream_t s, bool accumulate, double alpha, LaunchEvents ev) {
     const int nt = adjoint ? P.n_tiles_adj : P.n_tiles_fwd;
-    if (nt <= 0 || B <= 0) return hipSuccess;
+    if (nt <= 0 || B <= 0) return record_unused(ev, s);
     const Tile* tiles = adjoint ? P.tiles_adj : P.tiles_fwd;
     const Box* cboxes = adjoint ? P.cboxes_adj : P.cboxes_fwd;
     dim3 grid((unsigned)nt, (unsigned)B);
     if (P.dtype == 1)
-        hipLaunchKernelGGL(reduce_kernel<double>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
-                           static_cast<const double*>(slots), slot_stride, static_cast<double*>(out), ldo,
-                           (int64_t)P.cols, accumulate ? 1 : 0, alpha);
+        PC_LAUNCH(reduce_kernel<double>, grid, dim3(kReduceCols), 0, s, ev.start, ev.stop, tiles, cboxes,
+                  static_cast<const double*>(slots), slot_stride, static_cast<double*>(out), ldo, (int64_t)P.cols,
+                  accumulate ? 1 : 0, alpha);
     else
-        hipLaunchKernelGGL(reduce_kernel<float>, grid, dim3(kReduceCols), 0, s, tiles, cboxes,
-                           static_cast<const float*>(slots), slot_stride, static_cast<float*>(out), ldo,
-                           (int64_t)P.cols, accumulate ? 1 : 0, (float)alpha);
+        PC_LAUNCH(reduce_kernel<float>, grid, dim3(kReduceCols), 0, s, ev.start, ev.stop, tiles, cboxes,
+                  static_cast<const float*>(slots), slot_stride, static_cast<float*>(out), ldo, (int64_t)P.cols,
+                  accumulate ? 1 : 0, (float)alpha);
     return hipGetLastError();
 }
 

@@ -130,6 +130,55 @@ def test_batch_column_equals_single_apply_and_plain(lib):
     op.set_tuning(lib.PC_TUNE_CHUNK, 0)
 
 
+def test_profiling_times_every_launch(lib):
+    """pc_set_profiling / pc_read_profile: every convolution and reduction
+    launch of a timed call is counted with a positive duration, whichever
+    launch form runs (two-part staged launch and single launch time through
+    events carried by their dispatches, the persistent form through events
+    around its launches, the plain path per item), and timing changes no
+    bit of the result."""
+    w = make_config(1, scale=0.25)
+    _note(f"profiling: r={w.r}")
+    op = lib.PcOperator.from_workload(w, dtype=lib.PC_F32)
+    n_items = op.stats()["n_items"]
+    U = torch.from_numpy(w.vectors(7, dtype=np.float32)).cuda()
+    ref = torch.zeros_like(U)
+    op.apply_batch(U, ref)
+    torch.cuda.synchronize()
+    op.read_profile()
+    for key, val, off in ((lib.PC_TUNE_SPLIT, 1, 1), (lib.PC_TUNE_SPLIT, 0, 1), (lib.PC_TUNE_PERSISTENT, 1, 0)):
+        op.set_tuning(key, val)
+        for chunk, launches in ((0, 1), (3, 3)):
+            op.set_tuning(lib.PC_TUNE_CHUNK, chunk)
+            op.set_profiling(True)
+            for adj in (False, True):
+                got = torch.full_like(U, float("nan"))
+                (op.apply_adjoint_batch if adj else op.apply_batch)(U, got)
+            op.set_profiling(False)
+            pr = op.read_profile()
+            torch.cuda.synchronize()
+            assert pr["conv_launches"] == 2 * launches and pr["reduce_launches"] == 2 * launches, (key, val, pr)
+            assert pr["conv_vectors"] == 2 * 7 and pr["conv_ms"] > 0 and pr["reduce_ms"] > 0, (key, val, pr)
+            out = torch.zeros_like(U)
+            op.apply_batch(U, out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (key, val, chunk)
+        op.set_tuning(key, off)
+    op.set_tuning(lib.PC_TUNE_CHUNK, 0)
+    # the plain path: one timed launch per item and vector
+    op.set_profiling(True)
+    plain = torch.zeros_like(U)
+    op.apply_batch_plain(U, plain)
+    op.set_profiling(False)
+    pr = op.read_profile()
+    assert pr["conv_launches"] == 7 * n_items and pr["reduce_launches"] == 7, pr
+    assert torch.equal(plain, ref)
+    # nothing left over once read
+    pr = op.read_profile()
+    assert pr["conv_launches"] == 0 and pr["reduce_launches"] == 0
+    op.close()
+
+
 FULL_VECTORS = tuple(range(0, 64, 9))   # 8 of the 64 vectors: 0, 9, ..., 63
 
 
