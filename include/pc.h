@@ -318,14 +318,16 @@ pc_status   pc_debug_fail_launches(pc_op* op, int64_t first, int64_t count);
 
 /* Schedule knobs (defaults chosen by the library; an autotuner may override).
  *  PC_TUNE_CHUNK    vectors per convolution launch (0 = library default:
- *                   as many as fit a 2 GiB staging buffer; 3-D operators
- *                   take an explicit value even beyond that size)
+ *                   as many as fit a 2 GiB staging buffer, 8 GiB for 3-D
+ *                   operators; 3-D operators take an explicit value even
+ *                   beyond that size)
  *  PC_TUNE_OVERLAP  1: reduce chunk i on a library stream while chunk i+1
  *                   convolves; 0: everything on the caller's stream
  *                   (2-D operators only)
  *  PC_TUNE_SCRATCH  3-D operators: bytes of plane-spectrum scratch per item
- *                   group (0 = library default, 512 MiB); one item group runs
- *                   its three kernels before the next group starts
+ *                   group (0 = library default: 1 GiB in FP32, 256 MiB in
+ *                   FP64); one item group runs its three kernels before the
+ *                   next group starts
  *  PC_TUNE_DIRECT   1-D/2-D operators, pc_apply_batch and the adjoint: 1
  *                   runs the items colour by colour - the items of one
  *                   colour write pairwise disjoint boxes - and adds each box

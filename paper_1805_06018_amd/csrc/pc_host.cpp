@@ -33,9 +33,14 @@ pc_status hip_fail(hipError_t e, const char* what) {
 // the reduction of one vector chunk overlaps the next chunk's convolution).
 constexpr size_t kSlotCapBytes = size_t(2) << 30;
 constexpr int64_t kMinChunks = 4;
-// 3-D operators: default scratch bytes of one item group (all vectors of a
-// chunk), the plane spectra between the three kernels of the group.
-constexpr size_t kScratchCapBytes = size_t(512) << 20;
+// 3-D operators: default staging cap of one vector chunk (a 128^3 vector
+// stages about 0.7 GB in FP32), and default scratch bytes of one item group
+// (all vectors of a chunk), the plane spectra between the three kernels of
+// the group, by dtype (the faster sizes on the 128^3 blur: 1 GiB in FP32,
+// 256 MiB in FP64).
+constexpr size_t kSlotCapBytes3 = size_t(8) << 30;
+constexpr size_t kScratchCapBytesF32 = size_t(1) << 30;
+constexpr size_t kScratchCapBytesF64 = size_t(256) << 20;
 // Colour launches: most streams that vector chunks run on at once.
 constexpr int kMaxLanes = 4;
 
@@ -315,10 +320,11 @@ pc_status run_3d(pc_op* op, const std::vector<pc::Item3>& items, const pc::DevPl
         chunk = std::min<int64_t>(ext->chunk, B);
     } else if (!plain) {
         // an explicit chunk overrides the default staging cap
-        const int64_t cap = (int64_t)std::max<size_t>(1, kSlotCapBytes / per_bytes);
+        const int64_t cap = (int64_t)std::max<size_t>(1, kSlotCapBytes3 / per_bytes);
         chunk = op->tune_chunk > 0 ? std::min<int64_t>(op->tune_chunk, B) : std::min<int64_t>(cap, B);
     }
-    const size_t scap = ext ? ext->scratch_cap : op->tune_scratch > 0 ? (size_t)op->tune_scratch : kScratchCapBytes;
+    const size_t scap_default = P.dtype == PC_F64 ? kScratchCapBytesF64 : kScratchCapBytesF32;
+    const size_t scap = ext ? ext->scratch_cap : op->tune_scratch > 0 ? (size_t)op->tune_scratch : scap_default;
     const int n = (int)items.size();
     const int cols = pc::axis_cols(P.dtype);
     auto scratch_of = [&](int i) { return items[(size_t)i].scratch_off; };
