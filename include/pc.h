@@ -291,10 +291,14 @@ typedef struct {
 pc_status   pc_get_stats(const pc_op* op, pc_stats* st);
 
 /* Kernel timing for measurement.  pc_set_profiling(op, 1) makes every later
- * apply record a HIP event pair on its stream around each convolution and
- * each reduction launch; pc_read_profile waits for those events, returns the
- * accumulated device times and launch counts since the last read, and resets
- * them.  Profiling is off after pc_create. */
+ * apply (not under stream capture) time each convolution and each reduction
+ * launch with a HIP event pair: in staged 1-D/2-D applies the events travel
+ * on the launch's own dispatches (start with its first kernel, stop with its
+ * last), elsewhere they are recorded on the stream around the launch.
+ * pc_read_profile waits for those events, returns the accumulated device
+ * times and launch counts since the last read, and resets them.  Timing
+ * costs the stream a few microseconds per launch.  Profiling is off after
+ * pc_create. */
 typedef struct {
     double  conv_ms;          /* summed duration of the convolution launches  */
     double  reduce_ms;        /* summed duration of the reduction launches    */
